@@ -1,0 +1,261 @@
+/*
+ * sphidx.h -- C ABI of libsphidx: spherical-indexing neighbourhood queries
+ * (N. Brodu, "Spherical Indexing for Neighborhood Queries", arXiv
+ * cs/0608108) on one AMD Instinct MI355X (gfx950).
+ *
+ * Conventions for every entry point:
+ *   - "dev" pointers are device memory (for instance torch.Tensor.data_ptr()
+ *     of a CUDA/HIP tensor), "host" pointers are host memory.
+ *   - `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ *   - A call validates its host-visible arguments synchronously, enqueues its
+ *     kernels on `stream` and returns without synchronising, unless its
+ *     comment says otherwise.  Argument errors are returned as a status and
+ *     nothing is enqueued.
+ *   - Conditions found in device arrays (coordinates out of range, output
+ *     capacity exceeded) set bits of the lattice's device status word, read
+ *     with sphidx_lattice_status().  The affected rows are left empty; no
+ *     out-of-bounds write happens.
+ *   - The caller owns every device buffer it passes (coordinates, queries,
+ *     outputs, workspaces).  The library owns only the opaque handles and the
+ *     sphere-table storage.  No C++ type or exception crosses the ABI.
+ *
+ * Geometry (Section II.B): a lattice of 2^log2_cells[a] cubic cells per axis,
+ * each cell 2^frac_bits fixed-point units wide, each axis cyclic or clipped.
+ * Coordinates are uint32 fixed point.  On a cyclic axis any value is accepted
+ * and reduced modulo the world width W_a = 2^(log2_cells[a] + frac_bits); on
+ * a clipped axis values must be below 2^30; values >= W_a lie outside the
+ * region of interest and are kept in the one "outside" cell (Section II.B,
+ * non-cyclic case), whose index is the number of region cells.
+ *
+ * Query semantics (Section II.A): the neighbours of centre q for radius r are
+ * the objects p with |p - q| <= r (inclusive), distances measured with the
+ * minimum image on cyclic axes; each object appears at most once.  The K
+ * nearest are the first min(K, |R|) of those within the search cap r.  Every
+ * output row lists ids ordered by (squared distance, id) ascending; squared
+ * distances are exact int64 in fixed-point units^2.
+ */
+#ifndef SPHIDX_H
+#define SPHIDX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPHIDX_OK = 0,
+    SPHIDX_ERR_INVALID_ARG = 1,   /* bad pointer, size or descriptor */
+    SPHIDX_ERR_RANGE = 2,         /* coordinate out of the accepted range (device-detected) */
+    SPHIDX_ERR_RADIUS = 3,        /* radius beyond what the call accepts */
+    SPHIDX_ERR_CAPACITY = 4,      /* output or workspace too small */
+    SPHIDX_ERR_OUT_OF_MEMORY = 5, /* library-owned allocation failed */
+    SPHIDX_ERR_DEVICE = 6,        /* a HIP call failed */
+    SPHIDX_ERR_IO = 7             /* table file missing, truncated or corrupt */
+} sphidx_status;
+
+/* Device status word bits (sphidx_lattice_status). */
+#define SPHIDX_FLAG_RANGE 1u    /* a clipped-axis coordinate >= 2^30 was seen; that point/query was skipped */
+#define SPHIDX_FLAG_CAPACITY 2u /* row_ptr[Q] exceeded csr.capacity; the write pass wrote nothing */
+#define SPHIDX_FLAG_FALLBACK 4u /* informational: some queries used the cube scan (radius beyond the
+                                   tables' cap or the cyclic limit, or centre outside the region) */
+
+/* ---------------------------------------------------------------------- */
+/* Lattice (Section II.B): power-of-two cells per axis, per-axis cyclicity. */
+
+typedef struct {
+    uint32_t log2_cells[3]; /* 0..10 per axis; sum <= 30 */
+    uint32_t frac_bits;     /* F: cell edge = 2^F units; F + log2_cells[a] <= 30 */
+    uint32_t cyclic_mask;   /* bit a set: axis a wraps (minimum image) */
+} sphidx_lattice_desc;
+
+typedef struct sphidx_lattice sphidx_lattice; /* opaque, host-side handle */
+typedef struct sphidx_tables sphidx_tables;   /* opaque, host-side handle */
+
+/* Device workspace needed by a lattice of up to max_points objects. */
+size_t sphidx_lattice_workspace_bytes(const sphidx_lattice_desc* desc, uint32_t max_points);
+
+/* Bind a lattice handle to a caller-owned device workspace (>= the size
+ * above, 256-byte aligned).  Returns INVALID_ARG for a descriptor outside the
+ * limits, CAPACITY for a short workspace.  Synchronous; launches nothing. */
+sphidx_status sphidx_lattice_create(const sphidx_lattice_desc* desc, uint32_t max_points,
+                                    void* workspace_dev, size_t workspace_bytes,
+                                    sphidx_lattice** out);
+void sphidx_lattice_destroy(sphidx_lattice* lat);
+
+/* Rebuild the cell lists from n objects (dev x, y, z: uint32[n]) as a
+ * counting sort: cell-id histogram, exclusive scan, scatter into per-cell
+ * SoA arrays (each object is in exactly one cell, Section I).  Object ids are
+ * their input indices.  Objects with a clipped-axis coordinate >= 2^30 set
+ * SPHIDX_FLAG_RANGE and are left out.  n <= max_points.  The lattice must not
+ * be read by queries still in flight on other streams. */
+sphidx_status sphidx_build_lattice(sphidx_lattice* lat, const uint32_t* x_dev, const uint32_t* y_dev,
+                                   const uint32_t* z_dev, uint32_t n, void* stream);
+
+/* Device views of the lattice, for inspection: cell_start has ncells + 3
+ * entries (region cells, then the outside cell, then the cell of skipped
+ * objects), cell k holding sorted positions [cell_start[k], cell_start[k+1]);
+ * xs/ys/zs are normalised coordinates and ids the object ids, by sorted
+ * position.  Valid after the build's kernels complete. */
+typedef struct {
+    const uint32_t* cell_start;
+    const uint32_t* xs;
+    const uint32_t* ys;
+    const uint32_t* zs;
+    const uint32_t* ids;
+    uint32_t n;
+    uint32_t ncells;
+} sphidx_lattice_view;
+sphidx_status sphidx_lattice_get_view(const sphidx_lattice* lat, sphidx_lattice_view* out);
+
+/* Synchronise `stream`, return the device status word in *flags_out (may be
+ * NULL) and clear it.  Returns RANGE or CAPACITY when those bits were set. */
+sphidx_status sphidx_lattice_status(sphidx_lattice* lat, void* stream, uint32_t* flags_out);
+
+/* ---------------------------------------------------------------------- */
+/* Sphere tables (Section II.A; sub-cell specialisation, Section III.A).    */
+/*                                                                          */
+/* For each sub-cell class (subcell_bits s per axis: the query's position    */
+/* inside its cell, truncated to s bits per axis) the table lists every cell */
+/* offset o whose key -- the minimum squared distance from any position of  */
+/* the class box to the nearest position of cell o -- is <= rmax_fx^2,      */
+/* sorted by increasing key.  A query of radius r <= rmax walks the prefix  */
+/* with key <= r^2, centre to edge (Section II.A).                          */
+
+/* Build on the host and upload (allocates device memory; synchronous).
+ * s <= 3 and s <= frac_bits; rmax_fx <= 2^31 - 2^(frac_bits+2); the
+ * offset bound ceil(rmax/2^F) + 1 must be <= 511. */
+sphidx_status sphidx_build_sphere_tables(const sphidx_lattice_desc* desc, uint32_t subcell_bits,
+                                         uint32_t rmax_fx, sphidx_tables** out);
+void sphidx_tables_destroy(sphidx_tables* tab);
+
+typedef struct {
+    uint32_t subcell_bits;
+    uint32_t frac_bits;
+    uint32_t rmax_fx;
+    uint32_t nclasses;      /* 2^(3s) */
+    uint64_t total_entries; /* over all classes */
+    uint64_t device_bytes;
+} sphidx_tables_info;
+sphidx_status sphidx_tables_get_info(const sphidx_tables* tab, sphidx_tables_info* out);
+
+/* Copy class `cls`'s entries to host: offsets_host int32[3*n] as (ox, oy, oz)
+ * triples, keys_host int64[n] (either may be NULL).  *n_inout holds the
+ * capacity on entry and the class's entry count on return; CAPACITY if short. */
+sphidx_status sphidx_tables_export(const sphidx_tables* tab, uint32_t cls, int32_t* offsets_host,
+                                   int64_t* keys_host, uint64_t* n_inout);
+
+/* Save/load (Section II.A: the table may come from an external file).  The
+ * file holds a header (magic, version, s, F, rmax), the entries and a 64-bit
+ * checksum; load returns IO for a missing, truncated or corrupt file. */
+sphidx_status sphidx_tables_save(const sphidx_tables* tab, const char* path);
+sphidx_status sphidx_tables_load(const char* path, sphidx_tables** out);
+
+/* ---------------------------------------------------------------------- */
+/* Queries.                                                                */
+
+#define SPHIDX_MODE_RADIUS 0u /* every query: all objects within radius_fx */
+#define SPHIDX_MODE_KNN 1u    /* every query: K nearest within the cap radius_fx */
+#define SPHIDX_MODE_MIXED 2u  /* query i: K-NN when k_i > 0, else radius */
+
+#define SPHIDX_EXCLUDE_SELF 1u /* all-agents mode: leave out the query's own id */
+
+typedef struct {
+    uint32_t count;          /* Q */
+    const uint32_t* x_dev;   /* query centres (uint32[Q] each); all NULL = all agents: */
+    const uint32_t* y_dev;   /*   query i is object i of the lattice (Q must equal its n) */
+    const uint32_t* z_dev;
+    const uint32_t* radius_fx_dev; /* per-query radius (K-NN: search cap); NULL = use radius_fx */
+    uint32_t radius_fx;
+    const uint32_t* k_dev; /* per-query K; NULL = use k */
+    uint32_t k;
+    uint32_t mode;  /* SPHIDX_MODE_* */
+    uint32_t flags; /* SPHIDX_EXCLUDE_SELF */
+} sphidx_queries;
+
+typedef struct {
+    int64_t* row_ptr_dev; /* Q + 1 entries */
+    uint32_t* ids_dev;    /* capacity entries */
+    int64_t* dist2_dev;   /* capacity entries, or NULL when not wanted */
+    int64_t capacity;     /* entries available in ids (and dist2) */
+    void* workspace_dev;  /* sphidx_query_workspace_bytes(Q) bytes, 256-byte aligned */
+    size_t workspace_bytes;
+} sphidx_csr;
+
+#define SPHIDX_METHOD_SPHERE 0u /* sphere-table walk (falls back to the cube where the tables do not apply) */
+#define SPHIDX_METHOD_CUBE 1u   /* bin-lattice bounding-cube scan: the paper's baseline */
+
+#define SPHIDX_SCHED_PLAIN 0u      /* one launch, each wave owns a fixed slice of queries */
+#define SPHIDX_SCHED_PERSISTENT 1u /* resident waves pull query tiles from per-XCD work queues */
+
+typedef struct {
+    uint32_t method;          /* SPHIDX_METHOD_* */
+    uint32_t schedule;        /* SPHIDX_SCHED_* */
+    uint32_t waves_per_block; /* 1, 2, 4, 8 or 16; 0 = default */
+    uint32_t tile;            /* queries per wave slice / per queue grab; 0 = default */
+    uint32_t blocks_per_cu;   /* persistent residency; 0 = default */
+    uint32_t sort_cap;        /* per-wave row buffer (64..1024, power of two); 0 = default */
+    uint32_t table_in_lds;    /* 1: stage the whole table in LDS when it fits */
+    uint32_t reserved;
+    uint32_t* stats_dev; /* optional uint32[4*Q]: per query walked entries, kept cells,
+                            candidate objects tested, cube cells (count pass) */
+} sphidx_launch;
+
+/* Bytes of device scratch a query call on Q queries needs. */
+size_t sphidx_query_workspace_bytes(uint32_t Q);
+
+/* Pass 1: per-query row sizes, then an exclusive scan into row_ptr (so
+ * row_ptr[Q] = total pairs).  For K-NN rows the size is min(K, objects
+ * within the cap).  `tab` may be NULL with method CUBE.  `launch` may be
+ * NULL for the defaults (sphere, persistent).  Outputs other than row_ptr
+ * are untouched. */
+sphidx_status sphidx_count(const sphidx_lattice* lat, const sphidx_tables* tab, const sphidx_queries* q,
+                           sphidx_csr* csr, const sphidx_launch* launch, void* stream);
+
+/* Pass 2: fill ids (and dist2) of every row using row_ptr from sphidx_count
+ * on the same inputs.  If row_ptr[Q] > capacity it sets SPHIDX_FLAG_CAPACITY
+ * and writes nothing (checked on the device, so it can run under capture). */
+sphidx_status sphidx_write(const sphidx_lattice* lat, const sphidx_tables* tab, const sphidx_queries* q,
+                           sphidx_csr* csr, const sphidx_launch* launch, void* stream);
+
+/* Both passes. */
+sphidx_status sphidx_query(const sphidx_lattice* lat, const sphidx_tables* tab, const sphidx_queries* q,
+                           sphidx_csr* csr, const sphidx_launch* launch, void* stream);
+
+/* Named forms of sphidx_query with the default launch: radius (mode forced
+ * to RADIUS), K nearest (mode forced to KNN), and the bin-lattice baseline
+ * (method forced to CUBE, tables unused). */
+sphidx_status sphidx_radius_query(const sphidx_lattice* lat, const sphidx_tables* tab,
+                                  const sphidx_queries* q, sphidx_csr* csr, void* stream);
+sphidx_status sphidx_knn_query(const sphidx_lattice* lat, const sphidx_tables* tab,
+                               const sphidx_queries* q, sphidx_csr* csr, void* stream);
+sphidx_status sphidx_cube_scan_radius(const sphidx_lattice* lat, const sphidx_queries* q, sphidx_csr* csr,
+                                      void* stream);
+sphidx_status sphidx_cube_scan_knn(const sphidx_lattice* lat, const sphidx_queries* q, sphidx_csr* csr,
+                                   void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Moving agents (dynamic objects, Section I).                             */
+
+/* Displace each coordinate of object i by delta in [-2^F/4, 2^F/4], drawn
+ * from hash(seed, 1000 + 3*step + axis, i) with hash(s, t, i) =
+ * mix64(s ^ mix64((t << 40) ^ i)), mix64 = the SplitMix64 finaliser; wrap on
+ * cyclic axes, clamp to [0, W-1] on clipped ones.  In place on x, y, z. */
+sphidx_status sphidx_move_agents(const sphidx_lattice_desc* desc, uint64_t seed, uint32_t step,
+                                 uint32_t* x_dev, uint32_t* y_dev, uint32_t* z_dev, uint32_t n, void* stream);
+
+/* out_dev[0] = sum of row sizes, out_dev[1] = sum_i mix64((i << 32) | size_i)
+ * (mod 2^64), from row_ptr (Q + 1 entries).  out_dev is uint64[2]. */
+sphidx_status sphidx_count_checksum(const int64_t* row_ptr_dev, uint32_t Q, uint64_t* out_dev, void* stream);
+
+/* ---------------------------------------------------------------------- */
+
+const char* sphidx_status_string(sphidx_status s);
+/* Library version, e.g. "sphidx 1.0 gfx950". */
+const char* sphidx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPHIDX_H */

@@ -1,0 +1,445 @@
+// C ABI of libsphidx: argument validation, workspace layout and dispatch.
+#include <cstring>
+#include <new>
+
+#include "sphidx_internal.h"
+
+sphidx_status tables_build_host(uint32_t F, uint32_t s, uint32_t rmax_fx, sphidx_tables* t);
+void tables_free(sphidx_tables* t);
+sphidx_status tables_save_file(const sphidx_tables* t, const char* path);
+sphidx_status tables_upload(sphidx_tables* t);
+sphidx_status tables_load_file(const char* path, sphidx_tables* t);
+size_t scan_u32_tmp_words(size_t n);
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr size_t kMaxBlockLds = 64 * 1024;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+bool desc_ok(const sphidx_lattice_desc* d) {
+    if (!d) return false;
+    uint32_t sum = 0;
+    for (int a = 0; a < 3; ++a) {
+        if (d->log2_cells[a] > 10) return false;
+        if (d->frac_bits + d->log2_cells[a] > 30) return false;
+        sum += d->log2_cells[a];
+    }
+    return sum <= SPHIDX_MAX_LOG2_SUM && d->cyclic_mask <= 7u;
+}
+
+uint32_t ncells_of(const sphidx_lattice_desc* d) {
+    return 1u << (d->log2_cells[0] + d->log2_cells[1] + d->log2_cells[2]);
+}
+
+struct Layout {
+    size_t cell_start, xs, ys, zs, ids, rank, scan_tmp, status, total;
+};
+
+Layout lattice_layout(const sphidx_lattice_desc* d, uint32_t max_points) {
+    Layout L;
+    size_t nc = (size_t)ncells_of(d);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align_up(bytes ? bytes : 4);
+        return o;
+    };
+    L.cell_start = take((nc + 4) * 4);
+    L.xs = take((size_t)max_points * 4);
+    L.ys = take((size_t)max_points * 4);
+    L.zs = take((size_t)max_points * 4);
+    L.ids = take((size_t)max_points * 4);
+    L.rank = take((size_t)max_points * 4);
+    L.scan_tmp = take(scan_u32_tmp_words(nc + 2) * 4);
+    L.status = take(64 * 4);
+    L.total = off;
+    return L;
+}
+
+LatArgs lat_args(const sphidx_lattice* lat) {
+    LatArgs L;
+    for (int a = 0; a < 3; ++a) L.lg[a] = lat->desc.log2_cells[a];
+    L.F = lat->desc.frac_bits;
+    L.cyc = lat->desc.cyclic_mask;
+    L.ncells = lat->ncells;
+    L.n = lat->n;
+    L.cs = lat->cell_start;
+    L.xs = lat->xs;
+    L.ys = lat->ys;
+    L.zs = lat->zs;
+    L.ids = lat->ids;
+    L.status = lat->status;
+    return L;
+}
+
+TabArgs tab_args(const sphidx_tables* t) {
+    TabArgs T;
+    std::memset(&T, 0, sizeof(T));
+    if (!t) return T;
+    T.off = t->d_off;
+    T.key = t->d_key;
+    T.cstart = t->d_class_start;
+    T.rindex = t->d_rindex;
+    T.s = t->s;
+    T.rshift = t->rshift;
+    T.nr = t->nr;
+    T.rmax = t->rmax_fx;
+    T.total = (uint32_t)t->total;
+    T.has = 1;
+    return T;
+}
+
+struct Launch {
+    uint32_t method, persistent, waves, tile, bpc, cap, tab_lds;
+    uint32_t* stats;
+};
+
+sphidx_status resolve_launch(const sphidx_launch* in, const sphidx_tables* tab, Launch& o) {
+    o.method = in ? in->method : SPHIDX_METHOD_SPHERE;
+    o.persistent = in ? (in->schedule == SPHIDX_SCHED_PERSISTENT) : 1u;
+    o.waves = (in && in->waves_per_block) ? in->waves_per_block : 4u;
+    o.tile = (in && in->tile) ? in->tile : (o.persistent ? 4u : 1u);
+    o.bpc = (in && in->blocks_per_cu) ? in->blocks_per_cu : 8u;
+    o.cap = (in && in->sort_cap) ? in->sort_cap : 256u;
+    o.tab_lds = in ? in->table_in_lds : 0u;
+    o.stats = in ? in->stats_dev : nullptr;
+    if (in && in->schedule > SPHIDX_SCHED_PERSISTENT) return SPHIDX_ERR_INVALID_ARG;
+    if (o.method > SPHIDX_METHOD_CUBE) return SPHIDX_ERR_INVALID_ARG;
+    if (!(o.waves == 1 || o.waves == 2 || o.waves == 4)) return SPHIDX_ERR_INVALID_ARG;
+    if (o.cap < 64 || o.cap > 1024 || (o.cap & (o.cap - 1))) return SPHIDX_ERR_INVALID_ARG;
+    if (o.tile > 4096 || o.bpc > 64) return SPHIDX_ERR_INVALID_ARG;
+    if (o.method == SPHIDX_METHOD_SPHERE && !tab) return SPHIDX_ERR_INVALID_ARG;
+    size_t wave_bytes = (size_t)o.cap * 24 + 64 * 12;
+    size_t tab_bytes = (o.tab_lds && tab) ? ((size_t)tab->total * 4 + 15) / 16 * 16 : 0;
+    if ((size_t)o.waves * wave_bytes > kMaxBlockLds) return SPHIDX_ERR_INVALID_ARG;
+    if (o.tab_lds && (!tab || tab_bytes + (size_t)o.waves * wave_bytes > kMaxBlockLds)) return SPHIDX_ERR_CAPACITY;
+    if (o.method == SPHIDX_METHOD_CUBE) o.tab_lds = 0;
+    return SPHIDX_OK;
+}
+
+size_t query_ws_bytes(uint32_t Q) { return align_up(SPHIDX_NQUEUE * 8) + align_up(scan_i64_tmp_bytes(Q)); }
+
+sphidx_status check_queries(const sphidx_lattice* lat, const sphidx_queries* q, const sphidx_csr* csr) {
+    if (!lat || !q || !csr || !csr->row_ptr_dev) return SPHIDX_ERR_INVALID_ARG;
+    bool all = q->x_dev == nullptr;
+    if (all != (q->y_dev == nullptr) || all != (q->z_dev == nullptr)) return SPHIDX_ERR_INVALID_ARG;
+    if (all && q->count != lat->n) return SPHIDX_ERR_INVALID_ARG;
+    if (q->mode > SPHIDX_MODE_MIXED) return SPHIDX_ERR_INVALID_ARG;
+    if (q->flags & ~SPHIDX_EXCLUDE_SELF) return SPHIDX_ERR_INVALID_ARG;
+    if (csr->capacity < 0) return SPHIDX_ERR_INVALID_ARG;
+    if (!csr->workspace_dev || csr->workspace_bytes < query_ws_bytes(q->count)) return SPHIDX_ERR_CAPACITY;
+    if (((uintptr_t)csr->workspace_dev) % kAlign) return SPHIDX_ERR_INVALID_ARG;
+    return SPHIDX_OK;
+}
+
+QArgs q_args(const sphidx_queries* q, sphidx_csr* csr, const Launch& ln) {
+    QArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.Q = q->count;
+    A.qx = q->x_dev;
+    A.qy = q->y_dev;
+    A.qz = q->z_dev;
+    A.rad = q->radius_fx_dev;
+    A.rad_u = q->radius_fx;
+    A.kk = q->k_dev;
+    A.k_u = q->k;
+    A.mode = q->mode;
+    A.flags = q->flags;
+    A.row_ptr = csr->row_ptr_dev;
+    A.out_ids = csr->ids_dev;
+    A.out_d2 = csr->dist2_dev;
+    A.capacity = csr->capacity;
+    A.queues = (uint32_t*)csr->workspace_dev;
+    A.stats = ln.stats;
+    A.method = ln.method;
+    A.persistent = ln.persistent;
+    A.tile = ln.tile;
+    A.sort_cap = ln.cap;
+    return A;
+}
+
+void* scan_tmp_of(sphidx_csr* csr) { return (char*)csr->workspace_dev + align_up(SPHIDX_NQUEUE * 8); }
+
+sphidx_status dev_err(hipError_t e) { return e == hipSuccess ? SPHIDX_OK : SPHIDX_ERR_DEVICE; }
+
+// Upload freshly built or loaded tables when a device is present.  Without
+// one (a CPU-only host) the tables stay host-only: they can be inspected,
+// saved and loaded, and are uploaded on first use by a query.
+sphidx_status attach_device(sphidx_tables* t) {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return SPHIDX_OK;
+    return tables_upload(t);
+}
+
+sphidx_status run_pass(int pass, const sphidx_lattice* lat, const sphidx_tables* tab, const sphidx_queries* q,
+                       sphidx_csr* csr, const sphidx_launch* launch, hipStream_t st) {
+    sphidx_status s = check_queries(lat, q, csr);
+    if (s != SPHIDX_OK) return s;
+    Launch ln;
+    s = resolve_launch(launch, tab, ln);
+    if (s != SPHIDX_OK) return s;
+    if (pass == 1 && csr->capacity > 0 && !csr->ids_dev) return SPHIDX_ERR_INVALID_ARG;
+    if (tab && tab->F != lat->desc.frac_bits) return SPHIDX_ERR_INVALID_ARG;
+    if (tab && ln.method == SPHIDX_METHOD_SPHERE && !tab->d_off) {
+        s = tables_upload(const_cast<sphidx_tables*>(tab));
+        if (s != SPHIDX_OK) return s;
+    }
+    LatArgs L = lat_args(lat);
+    TabArgs T = tab_args(ln.method == SPHIDX_METHOD_SPHERE ? tab : nullptr);
+    T.lds = ln.tab_lds;
+    QArgs A = q_args(q, csr, ln);
+    if (pass == 0) {
+        if (q->count > 0) {
+            s = dev_err(launch_query_pass(0, L, T, A, ln.waves, ln.bpc, st));
+            if (s != SPHIDX_OK) return s;
+        }
+        return dev_err(launch_scan_i64(csr->row_ptr_dev, q->count, scan_tmp_of(csr), st));
+    }
+    return dev_err(launch_query_pass(1, L, T, A, ln.waves, ln.bpc, st));
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sphidx_lattice_workspace_bytes(const sphidx_lattice_desc* desc, uint32_t max_points) {
+    if (!desc_ok(desc)) return 0;
+    return lattice_layout(desc, max_points).total;
+}
+
+sphidx_status sphidx_lattice_create(const sphidx_lattice_desc* desc, uint32_t max_points, void* workspace_dev,
+                                    size_t workspace_bytes, sphidx_lattice** out) {
+    if (!out) return SPHIDX_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!desc_ok(desc) || !workspace_dev || ((uintptr_t)workspace_dev % kAlign)) return SPHIDX_ERR_INVALID_ARG;
+    if (max_points > 0xFFFFFF00u) return SPHIDX_ERR_INVALID_ARG;
+    Layout ly = lattice_layout(desc, max_points);
+    if (workspace_bytes < ly.total) return SPHIDX_ERR_CAPACITY;
+    sphidx_lattice* lat = new (std::nothrow) sphidx_lattice();
+    if (!lat) return SPHIDX_ERR_OUT_OF_MEMORY;
+    char* b = (char*)workspace_dev;
+    lat->desc = *desc;
+    lat->max_points = max_points;
+    lat->n = 0;
+    lat->ncells = ncells_of(desc);
+    lat->cell_start = (uint32_t*)(b + ly.cell_start);
+    lat->xs = (uint32_t*)(b + ly.xs);
+    lat->ys = (uint32_t*)(b + ly.ys);
+    lat->zs = (uint32_t*)(b + ly.zs);
+    lat->ids = (uint32_t*)(b + ly.ids);
+    lat->rank = (uint32_t*)(b + ly.rank);
+    lat->scan_tmp = (uint32_t*)(b + ly.scan_tmp);
+    lat->status = (uint32_t*)(b + ly.status);
+    lat->bytes = ly.total;
+    (void)hipGetDevice(&lat->device);
+    // an empty lattice until the first build: every cell empty, status clear
+    // (skipped on a host without a device, where only validation can run)
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0 &&
+        (launch_fill_u32(lat->cell_start, 0u, (size_t)lat->ncells + 4, nullptr) != hipSuccess ||
+         launch_fill_u32(lat->status, 0u, 64, nullptr) != hipSuccess)) {
+        delete lat;
+        return SPHIDX_ERR_DEVICE;
+    }
+    *out = lat;
+    return SPHIDX_OK;
+}
+
+void sphidx_lattice_destroy(sphidx_lattice* lat) { delete lat; }
+
+sphidx_status sphidx_build_lattice(sphidx_lattice* lat, const uint32_t* x_dev, const uint32_t* y_dev,
+                                   const uint32_t* z_dev, uint32_t n, void* stream) {
+    if (!lat || n > lat->max_points) return lat ? SPHIDX_ERR_CAPACITY : SPHIDX_ERR_INVALID_ARG;
+    if (n > 0 && (!x_dev || !y_dev || !z_dev)) return SPHIDX_ERR_INVALID_ARG;
+    lat->n = n;
+    return dev_err(launch_build(lat, x_dev, y_dev, z_dev, n, (hipStream_t)stream));
+}
+
+sphidx_status sphidx_lattice_get_view(const sphidx_lattice* lat, sphidx_lattice_view* out) {
+    if (!lat || !out) return SPHIDX_ERR_INVALID_ARG;
+    out->cell_start = lat->cell_start;
+    out->xs = lat->xs;
+    out->ys = lat->ys;
+    out->zs = lat->zs;
+    out->ids = lat->ids;
+    out->n = lat->n;
+    out->ncells = lat->ncells;
+    return SPHIDX_OK;
+}
+
+sphidx_status sphidx_lattice_status(sphidx_lattice* lat, void* stream, uint32_t* flags_out) {
+    if (!lat) return SPHIDX_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t v = 0;
+    if (hipMemcpyAsync(&v, lat->status, 4, hipMemcpyDeviceToHost, st) != hipSuccess) return SPHIDX_ERR_DEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) return SPHIDX_ERR_DEVICE;
+    if (launch_fill_u32(lat->status, 0u, 1, st) != hipSuccess) return SPHIDX_ERR_DEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) return SPHIDX_ERR_DEVICE;
+    if (flags_out) *flags_out = v;
+    if (v & SPHIDX_FLAG_RANGE) return SPHIDX_ERR_RANGE;
+    if (v & SPHIDX_FLAG_CAPACITY) return SPHIDX_ERR_CAPACITY;
+    return SPHIDX_OK;
+}
+
+sphidx_status sphidx_build_sphere_tables(const sphidx_lattice_desc* desc, uint32_t subcell_bits,
+                                         uint32_t rmax_fx, sphidx_tables** out) {
+    if (!out) return SPHIDX_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!desc_ok(desc)) return SPHIDX_ERR_INVALID_ARG;
+    const uint32_t F = desc->frac_bits;
+    if (subcell_bits > 3 || subcell_bits > F) return SPHIDX_ERR_INVALID_ARG;
+    if (F + 2 >= 31 || (uint64_t)rmax_fx > (1ull << 31) - (1ull << (F + 2))) return SPHIDX_ERR_RADIUS;
+    uint64_t m = (((uint64_t)rmax_fx + (1ull << F) - 1) >> F) + 1;
+    if (m > 511) return SPHIDX_ERR_RADIUS;
+    sphidx_tables* t = new (std::nothrow) sphidx_tables();
+    if (!t) return SPHIDX_ERR_OUT_OF_MEMORY;
+    sphidx_status s = tables_build_host(F, subcell_bits, rmax_fx, t);
+    if (s == SPHIDX_OK) s = attach_device(t);
+    if (s != SPHIDX_OK) {
+        tables_free(t);
+        delete t;
+        return s;
+    }
+    *out = t;
+    return SPHIDX_OK;
+}
+
+void sphidx_tables_destroy(sphidx_tables* tab) {
+    if (!tab) return;
+    tables_free(tab);
+    delete tab;
+}
+
+sphidx_status sphidx_tables_get_info(const sphidx_tables* tab, sphidx_tables_info* out) {
+    if (!tab || !out) return SPHIDX_ERR_INVALID_ARG;
+    out->subcell_bits = tab->s;
+    out->frac_bits = tab->F;
+    out->rmax_fx = tab->rmax_fx;
+    out->nclasses = tab->nclasses;
+    out->total_entries = tab->total;
+    out->device_bytes = tab->device_bytes;
+    return SPHIDX_OK;
+}
+
+sphidx_status sphidx_tables_export(const sphidx_tables* tab, uint32_t cls, int32_t* offsets_host,
+                                   int64_t* keys_host, uint64_t* n_inout) {
+    if (!tab || !n_inout || cls >= tab->nclasses) return SPHIDX_ERR_INVALID_ARG;
+    uint32_t b = tab->h_class_start[cls], e = tab->h_class_start[cls + 1];
+    uint64_t n = e - b, cap = *n_inout;
+    *n_inout = n;
+    if ((offsets_host || keys_host) && cap < n) return SPHIDX_ERR_CAPACITY;
+    for (uint64_t i = 0; i < n && (offsets_host || keys_host); ++i) {
+        uint32_t w = tab->h_off[b + i];
+        if (offsets_host) {
+            offsets_host[3 * i + 0] = ((int32_t)(w << 22)) >> 22;
+            offsets_host[3 * i + 1] = ((int32_t)(w << 12)) >> 22;
+            offsets_host[3 * i + 2] = ((int32_t)(w << 2)) >> 22;
+        }
+        if (keys_host) keys_host[i] = tab->h_key[b + i];
+    }
+    return SPHIDX_OK;
+}
+
+sphidx_status sphidx_tables_save(const sphidx_tables* tab, const char* path) {
+    if (!tab || !path) return SPHIDX_ERR_INVALID_ARG;
+    return tables_save_file(tab, path);
+}
+
+sphidx_status sphidx_tables_load(const char* path, sphidx_tables** out) {
+    if (!path || !out) return SPHIDX_ERR_INVALID_ARG;
+    *out = nullptr;
+    sphidx_tables* t = new (std::nothrow) sphidx_tables();
+    if (!t) return SPHIDX_ERR_OUT_OF_MEMORY;
+    sphidx_status s = tables_load_file(path, t);
+    if (s == SPHIDX_OK) s = attach_device(t);
+    if (s != SPHIDX_OK) {
+        tables_free(t);
+        delete t;
+        return s;
+    }
+    *out = t;
+    return SPHIDX_OK;
+}
+
+size_t sphidx_query_workspace_bytes(uint32_t Q) { return query_ws_bytes(Q); }
+
+sphidx_status sphidx_count(const sphidx_lattice* lat, const sphidx_tables* tab, const sphidx_queries* q,
+                           sphidx_csr* csr, const sphidx_launch* launch, void* stream) {
+    return run_pass(0, lat, tab, q, csr, launch, (hipStream_t)stream);
+}
+
+sphidx_status sphidx_write(const sphidx_lattice* lat, const sphidx_tables* tab, const sphidx_queries* q,
+                           sphidx_csr* csr, const sphidx_launch* launch, void* stream) {
+    return run_pass(1, lat, tab, q, csr, launch, (hipStream_t)stream);
+}
+
+sphidx_status sphidx_query(const sphidx_lattice* lat, const sphidx_tables* tab, const sphidx_queries* q,
+                           sphidx_csr* csr, const sphidx_launch* launch, void* stream) {
+    sphidx_status s = run_pass(0, lat, tab, q, csr, launch, (hipStream_t)stream);
+    if (s != SPHIDX_OK) return s;
+    return run_pass(1, lat, tab, q, csr, launch, (hipStream_t)stream);
+}
+
+static sphidx_status with_mode(const sphidx_lattice* lat, const sphidx_tables* tab, const sphidx_queries* q,
+                               sphidx_csr* csr, uint32_t mode, uint32_t method, void* stream) {
+    if (!q) return SPHIDX_ERR_INVALID_ARG;
+    sphidx_queries qq = *q;
+    qq.mode = mode;
+    sphidx_launch ln;
+    std::memset(&ln, 0, sizeof(ln));
+    ln.method = method;
+    ln.schedule = SPHIDX_SCHED_PERSISTENT;
+    return sphidx_query(lat, tab, &qq, csr, &ln, stream);
+}
+
+sphidx_status sphidx_radius_query(const sphidx_lattice* lat, const sphidx_tables* tab, const sphidx_queries* q,
+                                  sphidx_csr* csr, void* stream) {
+    return with_mode(lat, tab, q, csr, SPHIDX_MODE_RADIUS, SPHIDX_METHOD_SPHERE, stream);
+}
+
+sphidx_status sphidx_knn_query(const sphidx_lattice* lat, const sphidx_tables* tab, const sphidx_queries* q,
+                               sphidx_csr* csr, void* stream) {
+    return with_mode(lat, tab, q, csr, SPHIDX_MODE_KNN, SPHIDX_METHOD_SPHERE, stream);
+}
+
+sphidx_status sphidx_cube_scan_radius(const sphidx_lattice* lat, const sphidx_queries* q, sphidx_csr* csr,
+                                      void* stream) {
+    return with_mode(lat, nullptr, q, csr, SPHIDX_MODE_RADIUS, SPHIDX_METHOD_CUBE, stream);
+}
+
+sphidx_status sphidx_cube_scan_knn(const sphidx_lattice* lat, const sphidx_queries* q, sphidx_csr* csr,
+                                   void* stream) {
+    return with_mode(lat, nullptr, q, csr, SPHIDX_MODE_KNN, SPHIDX_METHOD_CUBE, stream);
+}
+
+sphidx_status sphidx_move_agents(const sphidx_lattice_desc* desc, uint64_t seed, uint32_t step, uint32_t* x_dev,
+                                 uint32_t* y_dev, uint32_t* z_dev, uint32_t n, void* stream) {
+    if (!desc_ok(desc)) return SPHIDX_ERR_INVALID_ARG;
+    if (n > 0 && (!x_dev || !y_dev || !z_dev)) return SPHIDX_ERR_INVALID_ARG;
+    return dev_err(launch_move_agents(*desc, seed, step, x_dev, y_dev, z_dev, n, (hipStream_t)stream));
+}
+
+sphidx_status sphidx_count_checksum(const int64_t* row_ptr_dev, uint32_t Q, uint64_t* out_dev, void* stream) {
+    if (!row_ptr_dev || !out_dev) return SPHIDX_ERR_INVALID_ARG;
+    return dev_err(launch_count_checksum(row_ptr_dev, Q, out_dev, (hipStream_t)stream));
+}
+
+const char* sphidx_status_string(sphidx_status s) {
+    switch (s) {
+        case SPHIDX_OK: return "ok";
+        case SPHIDX_ERR_INVALID_ARG: return "invalid argument";
+        case SPHIDX_ERR_RANGE: return "coordinate out of range";
+        case SPHIDX_ERR_RADIUS: return "radius out of range";
+        case SPHIDX_ERR_CAPACITY: return "capacity exceeded";
+        case SPHIDX_ERR_OUT_OF_MEMORY: return "out of memory";
+        case SPHIDX_ERR_DEVICE: return "device error";
+        case SPHIDX_ERR_IO: return "table file error";
+    }
+    return "unknown status";
+}
+
+const char* sphidx_version(void) { return "sphidx 1.0 gfx950"; }
+
+}  // extern "C"

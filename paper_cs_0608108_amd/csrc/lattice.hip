@@ -1,0 +1,240 @@
+// Lattice rebuild as a counting sort (each object in exactly one cell,
+// Section I; packed ZYX cell index and the unique outside cell, Section II.B):
+//   fill    count[0 .. ncells+2) = 0
+//   hist    per object: normalise, cell id, slot = atomicAdd(count[cell], 1)
+//   scan    exclusive prefix over ncells + 2 counts -> cell_start (+ total)
+//   scatter per object: position = cell_start[cell] + slot; SoA store
+// plus the reduce-then-scan used for cell_start and for query row pointers.
+#include "sphidx_internal.h"
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;  // per thread
+constexpr int kScanBlock = kScanThreads * kScanItems;
+
+__global__ void fill_u32_kernel(uint32_t* __restrict__ p, uint32_t v, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+struct BuildArgs {
+    uint32_t lg[3];
+    uint32_t F;
+    uint32_t cyc;
+    uint32_t ncells;
+    uint32_t n;
+    const uint32_t* x;
+    const uint32_t* y;
+    const uint32_t* z;
+    uint32_t* count;  // == cell_start storage
+    uint32_t* rank;
+    uint32_t* xs;
+    uint32_t* ys;
+    uint32_t* zs;
+    uint32_t* ids;
+    uint32_t* status;
+};
+
+// Normalise one object and return its cell: region cells are packed ZYX
+// (z << (lx+ly) | y << lx | x), ncells is the outside cell and ncells + 1
+// holds objects with an unusable clipped coordinate (>= 2^30).
+__device__ __forceinline__ uint32_t object_cell(const BuildArgs& a, uint32_t& vx, uint32_t& vy,
+                                                uint32_t& vz, bool& bad) {
+    uint32_t v[3] = {vx, vy, vz};
+    uint32_t c[3];
+    bool out = false;
+    bad = false;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        uint32_t wbits = a.lg[k] + a.F;
+        if ((a.cyc >> k) & 1u) {
+            v[k] &= (1u << wbits) - 1u;
+        } else {
+            bad |= v[k] >= (1u << 30);
+            out |= (v[k] >> wbits) != 0u;
+        }
+        c[k] = v[k] >> a.F;
+    }
+    vx = v[0];
+    vy = v[1];
+    vz = v[2];
+    if (bad) return a.ncells + 1u;
+    if (out) return a.ncells;
+    return (c[2] << (a.lg[0] + a.lg[1])) | (c[1] << a.lg[0]) | c[0];
+}
+
+__global__ __launch_bounds__(256) void hist_kernel(BuildArgs a) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    uint32_t vx = a.x[i], vy = a.y[i], vz = a.z[i];
+    bool bad;
+    uint32_t cell = object_cell(a, vx, vy, vz, bad);
+    if (bad) atomicOr(a.status, SPHIDX_FLAG_RANGE);
+    a.rank[i] = atomicAdd(&a.count[cell], 1u);
+}
+
+__global__ __launch_bounds__(256) void scatter_kernel(BuildArgs a) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    uint32_t vx = a.x[i], vy = a.y[i], vz = a.z[i];
+    bool bad;
+    uint32_t cell = object_cell(a, vx, vy, vz, bad);
+    uint32_t pos = a.count[cell] + a.rank[i];
+    a.xs[pos] = vx;
+    a.ys[pos] = vy;
+    a.zs[pos] = vz;
+    a.ids[pos] = i;
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan, reduce-then-scan over blocks of kScanBlock elements.
+// No inter-block waiting: three launches, each block independent.
+
+template <typename T>
+__device__ T block_exclusive_scan(T v, T* sh, T& total) {
+    // wave-level inclusive scan
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    T x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        T t = __shfl_up(x, d);
+        if (lane >= d) x += t;
+    }
+    if (lane == 63) sh[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T acc = 0;
+        for (int w = 0; w < kScanThreads / 64; ++w) {
+            T s = sh[w];
+            sh[w] = acc;
+            acc += s;
+        }
+        sh[kScanThreads / 64] = acc;
+    }
+    __syncthreads();
+    total = sh[kScanThreads / 64];
+    T r = x - v + sh[wave];
+    __syncthreads();
+    return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const T* __restrict__ in, size_t n,
+                                                                   T* __restrict__ partial) {
+    __shared__ T sh[kScanThreads / 64 + 1];
+    size_t base = (size_t)blockIdx.x * kScanBlock + (size_t)threadIdx.x * kScanItems;
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < n) s += in[base + k];
+    T tot;
+    block_exclusive_scan<T>(s, sh, tot);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void scan_partials_kernel(T* __restrict__ partial, uint32_t nb) {
+    __shared__ T sh[kScanThreads / 64 + 1];
+    // each thread owns a contiguous run of ceil(nb / threads) partials;
+    // partial[nb] receives the grand total
+    uint32_t per = (nb + kScanThreads - 1) / kScanThreads;
+    uint32_t b0 = threadIdx.x * per;
+    T s = 0;
+    for (uint32_t k = 0; k < per; ++k)
+        if (b0 + k < nb) s += partial[b0 + k];
+    T tot;
+    T off = block_exclusive_scan<T>(s, sh, tot);
+    for (uint32_t k = 0; k < per; ++k)
+        if (b0 + k < nb) {
+            T t = partial[b0 + k];
+            partial[b0 + k] = off;
+            off += t;
+        }
+    if (threadIdx.x == 0) partial[nb] = tot;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void scan_down_kernel(T* __restrict__ data, size_t n,
+                                                                 const T* __restrict__ partial, uint32_t nb) {
+    __shared__ T sh[kScanThreads / 64 + 1];
+    size_t base = (size_t)blockIdx.x * kScanBlock + (size_t)threadIdx.x * kScanItems;
+    T v[kScanItems];
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (base + k < n) ? data[base + k] : (T)0;
+        s += v[k];
+    }
+    T tot;
+    T off = block_exclusive_scan<T>(s, sh, tot) + partial[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) data[base + k] = off;
+        off += v[k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) data[n] = partial[nb];
+}
+
+// In-place exclusive scan of data[0..n); data[n] receives the total.
+// `partial` needs ceil(n / kScanBlock) + 1 elements.
+template <typename T>
+hipError_t scan_exclusive(T* data, size_t n, T* partial, hipStream_t st) {
+    uint32_t nb = (uint32_t)((n + kScanBlock - 1) / kScanBlock);
+    if (nb == 0) nb = 1;
+    scan_reduce_kernel<T><<<nb, kScanThreads, 0, st>>>(data, n, partial);
+    scan_partials_kernel<T><<<1, kScanThreads, 0, st>>>(partial, nb);
+    scan_down_kernel<T><<<nb, kScanThreads, 0, st>>>(data, n, partial, nb);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    fill_u32_kernel<<<(uint32_t)blocks, 256, 0, st>>>(p, value, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_build(const sphidx_lattice* lat, const uint32_t* x, const uint32_t* y, const uint32_t* z,
+                        uint32_t n, hipStream_t st) {
+    BuildArgs a;
+    for (int k = 0; k < 3; ++k) a.lg[k] = lat->desc.log2_cells[k];
+    a.F = lat->desc.frac_bits;
+    a.cyc = lat->desc.cyclic_mask;
+    a.ncells = lat->ncells;
+    a.n = n;
+    a.x = x;
+    a.y = y;
+    a.z = z;
+    a.count = lat->cell_start;
+    a.rank = lat->rank;
+    a.xs = lat->xs;
+    a.ys = lat->ys;
+    a.zs = lat->zs;
+    a.ids = lat->ids;
+    a.status = lat->status;
+    size_t ncount = (size_t)lat->ncells + 2;
+    hipError_t e = launch_fill_u32(lat->cell_start, 0u, ncount + 1, st);
+    if (e != hipSuccess) return e;
+    uint32_t blocks = (n + 255) / 256;
+    if (n > 0) hist_kernel<<<blocks, 256, 0, st>>>(a);
+    e = scan_exclusive<uint32_t>(lat->cell_start, ncount, lat->scan_tmp, st);
+    if (e != hipSuccess) return e;
+    if (n > 0) scatter_kernel<<<blocks, 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+size_t scan_i64_tmp_bytes(uint32_t n) {
+    size_t nb = ((size_t)n + kScanBlock - 1) / kScanBlock + 2;
+    return nb * sizeof(int64_t);
+}
+
+hipError_t launch_scan_i64(int64_t* data, uint32_t n, void* tmp, hipStream_t st) {
+    return scan_exclusive<int64_t>(data, n, (int64_t*)tmp, st);
+}
+
+size_t scan_u32_tmp_words(size_t n) { return (n + kScanBlock - 1) / kScanBlock + 2; }

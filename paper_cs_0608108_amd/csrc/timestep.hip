@@ -1,0 +1,92 @@
+// Moving agents (dynamic objects whose positions change every step,
+// Section I) and the order-independent checksum of per-row neighbour counts.
+#include "sphidx_internal.h"
+
+namespace {
+
+// SplitMix64 output finaliser (Steele, Lea and Flood, OOPSLA 2014).
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t counter_hash(uint64_t seed, uint64_t tag, uint64_t i) {
+    return mix64(seed ^ mix64((tag << 40) ^ i));
+}
+
+struct MoveArgs {
+    uint32_t wbits[3];
+    uint32_t cyc;
+    uint32_t dmax;
+    uint64_t seed;
+    uint32_t step;
+    uint32_t n;
+    uint32_t* v[3];
+};
+
+__global__ __launch_bounds__(256) void move_kernel(MoveArgs a) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const uint64_t span = 2ull * a.dmax + 1ull;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        uint64_t h = counter_hash(a.seed, 1000ull + 3ull * a.step + (uint64_t)k, i);
+        int64_t delta = (int64_t)(((h >> 32) * span) >> 32) - (int64_t)a.dmax;
+        int64_t w = (int64_t)1 << a.wbits[k];
+        int64_t nv = (int64_t)a.v[k][i] + delta;
+        if ((a.cyc >> k) & 1u)
+            nv &= w - 1;
+        else
+            nv = nv < 0 ? 0 : (nv > w - 1 ? w - 1 : nv);
+        a.v[k][i] = (uint32_t)nv;
+    }
+}
+
+__global__ __launch_bounds__(256) void checksum_kernel(const int64_t* __restrict__ row_ptr, uint32_t Q,
+                                                       unsigned long long* out) {
+    uint64_t s = 0, h = 0;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < Q; i += gridDim.x * blockDim.x) {
+        uint64_t c = (uint64_t)(row_ptr[i + 1] - row_ptr[i]);
+        s += c;
+        h += mix64(((uint64_t)i << 32) | (c & 0xffffffffull));
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        s += __shfl_xor(s, d);
+        h += __shfl_xor(h, d);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&out[0], (unsigned long long)s);
+        atomicAdd(&out[1], (unsigned long long)h);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_move_agents(const sphidx_lattice_desc& d, uint64_t seed, uint32_t step, uint32_t* x,
+                              uint32_t* y, uint32_t* z, uint32_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    MoveArgs a;
+    for (int k = 0; k < 3; ++k) a.wbits[k] = d.log2_cells[k] + d.frac_bits;
+    a.cyc = d.cyclic_mask;
+    a.dmax = (1u << d.frac_bits) / 4u;
+    a.seed = seed;
+    a.step = step;
+    a.n = n;
+    a.v[0] = x;
+    a.v[1] = y;
+    a.v[2] = z;
+    move_kernel<<<(n + 255) / 256, 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_checksum(const int64_t* row_ptr, uint32_t Q, uint64_t* out, hipStream_t st) {
+    hipError_t e = launch_fill_u32((uint32_t*)out, 0u, 4, st);
+    if (e != hipSuccess) return e;
+    uint32_t blocks = (Q + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks == 0) blocks = 1;
+    checksum_kernel<<<blocks, 256, 0, st>>>(row_ptr, Q, (unsigned long long*)out);
+    return hipGetLastError();
+}

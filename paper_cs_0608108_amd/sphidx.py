@@ -1,0 +1,382 @@
+"""Thin ctypes binding of libsphidx (C ABI in include/sphidx.h).
+
+Argument marshalling only: every step of the query path runs in the HIP
+kernels of ``libsphidx.so``.  PyTorch provides device memory and streams.
+The library must have been built (``python -m paper_cs_0608108_amd.build``);
+importing this module without it raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsphidx.so")
+
+OK, ERR_INVALID_ARG, ERR_RANGE, ERR_RADIUS, ERR_CAPACITY, ERR_OOM, ERR_DEVICE, ERR_IO = range(8)
+FLAG_RANGE, FLAG_CAPACITY, FLAG_FALLBACK = 1, 2, 4
+MODE_RADIUS, MODE_KNN, MODE_MIXED = 0, 1, 2
+EXCLUDE_SELF = 1
+METHOD_SPHERE, METHOD_CUBE = 0, 1
+SCHED_PLAIN, SCHED_PERSISTENT = 0, 1
+
+U32, I32, U64, I64, SZ, P = (ctypes.c_uint32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64,
+                             ctypes.c_size_t, ctypes.c_void_p)
+
+
+class LatticeDesc(ctypes.Structure):
+    _fields_ = [("log2_cells", U32 * 3), ("frac_bits", U32), ("cyclic_mask", U32)]
+
+
+class LatticeView(ctypes.Structure):
+    _fields_ = [("cell_start", P), ("xs", P), ("ys", P), ("zs", P), ("ids", P), ("n", U32), ("ncells", U32)]
+
+
+class TablesInfo(ctypes.Structure):
+    _fields_ = [("subcell_bits", U32), ("frac_bits", U32), ("rmax_fx", U32), ("nclasses", U32),
+                ("total_entries", U64), ("device_bytes", U64)]
+
+
+class Queries(ctypes.Structure):
+    _fields_ = [("count", U32), ("x_dev", P), ("y_dev", P), ("z_dev", P), ("radius_fx_dev", P),
+                ("radius_fx", U32), ("k_dev", P), ("k", U32), ("mode", U32), ("flags", U32)]
+
+
+class CSRDesc(ctypes.Structure):
+    _fields_ = [("row_ptr_dev", P), ("ids_dev", P), ("dist2_dev", P), ("capacity", I64),
+                ("workspace_dev", P), ("workspace_bytes", SZ)]
+
+
+class LaunchDesc(ctypes.Structure):
+    _fields_ = [("method", U32), ("schedule", U32), ("waves_per_block", U32), ("tile", U32),
+                ("blocks_per_cu", U32), ("sort_cap", U32), ("table_in_lds", U32), ("reserved", U32),
+                ("stats_dev", P)]
+
+
+# Every symbol include/sphidx.h declares, with its ctypes signature.
+SIGNATURES = {
+    "sphidx_lattice_workspace_bytes": (SZ, [ctypes.POINTER(LatticeDesc), U32]),
+    "sphidx_lattice_create": (ctypes.c_int, [ctypes.POINTER(LatticeDesc), U32, P, SZ, ctypes.POINTER(P)]),
+    "sphidx_lattice_destroy": (None, [P]),
+    "sphidx_build_lattice": (ctypes.c_int, [P, P, P, P, U32, P]),
+    "sphidx_lattice_get_view": (ctypes.c_int, [P, ctypes.POINTER(LatticeView)]),
+    "sphidx_lattice_status": (ctypes.c_int, [P, P, ctypes.POINTER(U32)]),
+    "sphidx_build_sphere_tables": (ctypes.c_int, [ctypes.POINTER(LatticeDesc), U32, U32, ctypes.POINTER(P)]),
+    "sphidx_tables_destroy": (None, [P]),
+    "sphidx_tables_get_info": (ctypes.c_int, [P, ctypes.POINTER(TablesInfo)]),
+    "sphidx_tables_export": (ctypes.c_int, [P, U32, P, P, ctypes.POINTER(U64)]),
+    "sphidx_tables_save": (ctypes.c_int, [P, ctypes.c_char_p]),
+    "sphidx_tables_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(P)]),
+    "sphidx_query_workspace_bytes": (SZ, [U32]),
+    "sphidx_count": (ctypes.c_int, [P, P, ctypes.POINTER(Queries), ctypes.POINTER(CSRDesc),
+                                    ctypes.POINTER(LaunchDesc), P]),
+    "sphidx_write": (ctypes.c_int, [P, P, ctypes.POINTER(Queries), ctypes.POINTER(CSRDesc),
+                                    ctypes.POINTER(LaunchDesc), P]),
+    "sphidx_query": (ctypes.c_int, [P, P, ctypes.POINTER(Queries), ctypes.POINTER(CSRDesc),
+                                    ctypes.POINTER(LaunchDesc), P]),
+    "sphidx_radius_query": (ctypes.c_int, [P, P, ctypes.POINTER(Queries), ctypes.POINTER(CSRDesc), P]),
+    "sphidx_knn_query": (ctypes.c_int, [P, P, ctypes.POINTER(Queries), ctypes.POINTER(CSRDesc), P]),
+    "sphidx_cube_scan_radius": (ctypes.c_int, [P, ctypes.POINTER(Queries), ctypes.POINTER(CSRDesc), P]),
+    "sphidx_cube_scan_knn": (ctypes.c_int, [P, ctypes.POINTER(Queries), ctypes.POINTER(CSRDesc), P]),
+    "sphidx_move_agents": (ctypes.c_int, [ctypes.POINTER(LatticeDesc), U64, U32, P, P, P, U32, P]),
+    "sphidx_count_checksum": (ctypes.c_int, [P, U32, P, P]),
+    "sphidx_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "sphidx_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load():
+    """Load libsphidx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_cs_0608108_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class SphidxError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        msg = load().sphidx_status_string(code).decode()
+        super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
+
+
+def check(code, what=""):
+    if code != OK:
+        raise SphidxError(code, what)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def desc_of(log2_cells, frac_bits, cyclic_mask) -> LatticeDesc:
+    d = LatticeDesc()
+    for a in range(3):
+        d.log2_cells[a] = int(log2_cells[a])
+    d.frac_bits = int(frac_bits)
+    d.cyclic_mask = int(cyclic_mask)
+    return d
+
+
+def to_dev_u32(a, device="cuda"):
+    """Host uint32 array -> device tensor holding the same 32-bit patterns (int32 storage)."""
+    a = np.ascontiguousarray(a, dtype=np.uint32)
+    return torch.from_numpy(a.view(np.int32)).to(device)
+
+
+def to_host_u32(t) -> np.ndarray:
+    return t.detach().cpu().numpy().view(np.uint32)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Lattice:
+    """A lattice handle bound to a device workspace owned by this object."""
+
+    def __init__(self, log2_cells, frac_bits, cyclic_mask, max_points, device="cuda"):
+        lib = load()
+        self.desc = desc_of(log2_cells, frac_bits, cyclic_mask)
+        self.max_points = int(max_points)
+        nbytes = lib.sphidx_lattice_workspace_bytes(ctypes.byref(self.desc), self.max_points)
+        if nbytes == 0:
+            raise SphidxError(ERR_INVALID_ARG, "lattice descriptor")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self._ws_ptr = base + off
+        h = P()
+        check(lib.sphidx_lattice_create(ctypes.byref(self.desc), self.max_points, ctypes.c_void_p(self._ws_ptr),
+                                        nbytes, ctypes.byref(h)), "lattice_create")
+        self.handle = h
+        self.n = 0
+        self.log2_cells = tuple(int(v) for v in log2_cells)
+        self.frac_bits = int(frac_bits)
+        self.cyclic_mask = int(cyclic_mask)
+
+    def __del__(self):
+        try:
+            if self.handle:
+                load().sphidx_lattice_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+    @property
+    def ncells(self):
+        return 1 << sum(self.log2_cells)
+
+    def build(self, x, y, z, stream=None):
+        n = int(x.numel())
+        check(load().sphidx_build_lattice(self.handle, _ptr(x), _ptr(y), _ptr(z), n, _stream(stream)), "build")
+        self.n = n
+
+    def view(self):
+        v = LatticeView()
+        check(load().sphidx_lattice_get_view(self.handle, ctypes.byref(v)))
+        return v
+
+    def status(self, stream=None):
+        """(status code, flags); synchronises the stream and clears the word."""
+        f = U32(0)
+        code = load().sphidx_lattice_status(self.handle, _stream(stream), ctypes.byref(f))
+        return code, int(f.value)
+
+    def host_arrays(self):
+        """Copy cell_start and the sorted SoA arrays back to the host (for tests).
+        The view's pointers lie inside this object's workspace tensor."""
+        v = self.view()
+        base = self.workspace.data_ptr()
+
+        def grab(ptr, count):
+            off = ptr - base
+            t = self.workspace[off:off + 4 * count].view(torch.int32)
+            return t.cpu().numpy().view(np.uint32)
+
+        torch.cuda.synchronize()
+        return dict(cell_start=grab(v.cell_start, v.ncells + 3), xs=grab(v.xs, v.n), ys=grab(v.ys, v.n),
+                    zs=grab(v.zs, v.n), ids=grab(v.ids, v.n))
+
+
+class Tables:
+    def __init__(self, lattice_or_desc, subcell_bits=2, rmax_fx=None, handle=None):
+        lib = load()
+        if handle is not None:
+            self.handle = handle
+        else:
+            desc = lattice_or_desc.desc if isinstance(lattice_or_desc, Lattice) else lattice_or_desc
+            h = P()
+            check(lib.sphidx_build_sphere_tables(ctypes.byref(desc), int(subcell_bits), int(rmax_fx),
+                                                 ctypes.byref(h)), "build_sphere_tables")
+            self.handle = h
+
+    @classmethod
+    def load_file(cls, path):
+        h = P()
+        check(load().sphidx_tables_load(str(path).encode(), ctypes.byref(h)), "tables_load")
+        return cls(None, handle=h)
+
+    def save(self, path):
+        check(load().sphidx_tables_save(self.handle, str(path).encode()), "tables_save")
+
+    def __del__(self):
+        try:
+            if self.handle:
+                load().sphidx_tables_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+    def info(self) -> TablesInfo:
+        i = TablesInfo()
+        check(load().sphidx_tables_get_info(self.handle, ctypes.byref(i)))
+        return i
+
+    def export(self, cls):
+        n = U64(0)
+        check(load().sphidx_tables_export(self.handle, int(cls), None, None, ctypes.byref(n)))
+        offs = np.empty((n.value, 3), dtype=np.int32)
+        keys = np.empty(n.value, dtype=np.int64)
+        check(load().sphidx_tables_export(self.handle, int(cls), ctypes.c_void_p(offs.ctypes.data),
+                                          ctypes.c_void_p(keys.ctypes.data), ctypes.byref(n)))
+        return offs, keys
+
+
+@dataclass
+class LaunchConfig:
+    method: int = METHOD_SPHERE
+    schedule: int = SCHED_PERSISTENT
+    waves_per_block: int = 0
+    tile: int = 0
+    blocks_per_cu: int = 0
+    sort_cap: int = 0
+    table_in_lds: int = 0
+    stats: torch.Tensor | None = None
+
+    def c(self) -> LaunchDesc:
+        d = LaunchDesc()
+        d.method, d.schedule = self.method, self.schedule
+        d.waves_per_block, d.tile, d.blocks_per_cu = self.waves_per_block, self.tile, self.blocks_per_cu
+        d.sort_cap, d.table_in_lds = self.sort_cap, self.table_in_lds
+        d.stats_dev = None if self.stats is None else self.stats.data_ptr()
+        return d
+
+
+def make_queries(count, centres=None, radius=None, k=None, mode=MODE_RADIUS, flags=0) -> Queries:
+    """centres: None (all agents) or (x, y, z) device tensors; radius / k:
+    an int (uniform) or a device tensor (per query)."""
+    q = Queries()
+    q.count = int(count)
+    if centres is not None:
+        q.x_dev, q.y_dev, q.z_dev = (c.data_ptr() for c in centres)
+    if isinstance(radius, torch.Tensor):
+        q.radius_fx_dev = radius.data_ptr()
+    else:
+        q.radius_fx = int(radius or 0)
+    if isinstance(k, torch.Tensor):
+        q.k_dev = k.data_ptr()
+    else:
+        q.k = int(k or 0)
+    q.mode, q.flags = int(mode), int(flags)
+    return q
+
+
+class QueryBuffers:
+    """Device outputs and workspace of one query call."""
+
+    def __init__(self, Q, capacity, want_dist2=True, device="cuda"):
+        lib = load()
+        self.Q = int(Q)
+        self.row_ptr = torch.empty(self.Q + 1, dtype=torch.int64, device=device)
+        self.capacity = int(capacity)
+        self.ids = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=device)
+        self.dist2 = torch.empty(max(self.capacity, 1), dtype=torch.int64, device=device) if want_dist2 else None
+        wsb = lib.sphidx_query_workspace_bytes(self.Q)
+        self.workspace = torch.empty(wsb + 256, dtype=torch.uint8, device=device)
+        self._ws = self.workspace.data_ptr() + ((-self.workspace.data_ptr()) % 256)
+        self._wsb = wsb
+
+    def grow(self, capacity):
+        if capacity > self.capacity:
+            dev = self.ids.device
+            self.capacity = int(capacity)
+            self.ids = torch.empty(self.capacity, dtype=torch.int32, device=dev)
+            if self.dist2 is not None:
+                self.dist2 = torch.empty(self.capacity, dtype=torch.int64, device=dev)
+
+    def c(self) -> CSRDesc:
+        d = CSRDesc()
+        d.row_ptr_dev = self.row_ptr.data_ptr()
+        d.ids_dev = self.ids.data_ptr()
+        d.dist2_dev = None if self.dist2 is None else self.dist2.data_ptr()
+        d.capacity = self.capacity
+        d.workspace_dev = self._ws
+        d.workspace_bytes = self._wsb
+        return d
+
+    def host(self):
+        rp = self.row_ptr.cpu().numpy()
+        tot = int(rp[-1])
+        ids = self.ids[:tot].cpu().numpy().view(np.uint32)
+        d2 = self.dist2[:tot].cpu().numpy() if self.dist2 is not None else None
+        return rp, ids, d2
+
+
+def count(lat, tab, q: Queries, buf: QueryBuffers, launch: LaunchConfig | None = None, stream=None):
+    ln = (launch or LaunchConfig()).c()
+    cs = buf.c()
+    check(load().sphidx_count(lat.handle, tab.handle if tab else None, ctypes.byref(q), ctypes.byref(cs),
+                              ctypes.byref(ln), _stream(stream)), "count")
+
+
+def write(lat, tab, q: Queries, buf: QueryBuffers, launch: LaunchConfig | None = None, stream=None):
+    ln = (launch or LaunchConfig()).c()
+    cs = buf.c()
+    check(load().sphidx_write(lat.handle, tab.handle if tab else None, ctypes.byref(q), ctypes.byref(cs),
+                              ctypes.byref(ln), _stream(stream)), "write")
+
+
+def query(lat, tab, q: Queries, buf: QueryBuffers, launch: LaunchConfig | None = None, stream=None):
+    ln = (launch or LaunchConfig()).c()
+    cs = buf.c()
+    check(load().sphidx_query(lat.handle, tab.handle if tab else None, ctypes.byref(q), ctypes.byref(cs),
+                              ctypes.byref(ln), _stream(stream)), "query")
+
+
+def run(lat, tab, q: Queries, launch: LaunchConfig | None = None, want_dist2=True, stream=None):
+    """Count, size the outputs exactly, write; returns host (row_ptr, ids, dist2)."""
+    buf = QueryBuffers(q.count, 0, want_dist2)
+    count(lat, tab, q, buf, launch, stream)
+    total = int(buf.row_ptr[-1].item())
+    buf.grow(max(total, 1))
+    write(lat, tab, q, buf, launch, stream)
+    torch.cuda.synchronize()
+    return buf.host()
+
+
+def move_agents(desc: LatticeDesc, seed, step, x, y, z, stream=None):
+    check(load().sphidx_move_agents(ctypes.byref(desc), int(seed), int(step), _ptr(x), _ptr(y), _ptr(z),
+                                    int(x.numel()), _stream(stream)), "move_agents")
+
+
+def count_checksum(row_ptr, Q, out, stream=None):
+    check(load().sphidx_count_checksum(_ptr(row_ptr), int(Q), _ptr(out), _stream(stream)), "count_checksum")
+
+
+def version() -> str:
+    return load().sphidx_version().decode()

@@ -1,0 +1,414 @@
+"""GPU parity: the HIP path through the C ABI against the oracle, bit for bit.
+
+Every comparison is exact: row pointers, ids and squared distances are
+integers.  Inputs are seeded and synthetic (uniform points, Gaussian
+clusters, hand fixtures, degenerate layouts)."""
+import numpy as np
+import pytest
+
+from goldens import read_hand, read_keyed
+from gpu_util import assert_same, lattice, run, say, tiny_points
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_cs_0608108_amd import sphidx
+    sphidx.load()
+    return sphidx
+
+
+def _launches(sx):
+    L = sx.LaunchConfig
+    return {
+        "sphere-persistent": L(method=sx.METHOD_SPHERE, schedule=sx.SCHED_PERSISTENT),
+        "sphere-plain": L(method=sx.METHOD_SPHERE, schedule=sx.SCHED_PLAIN),
+        "sphere-small-cap": L(method=sx.METHOD_SPHERE, schedule=sx.SCHED_PERSISTENT, sort_cap=64, tile=1,
+                              waves_per_block=2),
+        "sphere-lds-table": L(method=sx.METHOD_SPHERE, schedule=sx.SCHED_PLAIN, table_in_lds=1,
+                              waves_per_block=1, sort_cap=128),
+        "cube": L(method=sx.METHOD_CUBE, schedule=sx.SCHED_PERSISTENT),
+        "cube-plain": L(method=sx.METHOD_CUBE, schedule=sx.SCHED_PLAIN, tile=3),
+    }
+
+
+# ---------------------------------------------------------------------------
+# Lattice rebuild (counting sort)
+
+@pytest.mark.parametrize("mask", [0, 5, 7])
+def test_rebuild_is_the_oracle_counting_sort(sx, orc, mask):
+    say("rebuild mask", mask)
+    rng = np.random.default_rng(40 + mask)
+    log2, F = (4, 3, 5), 10
+    pts = tiny_points(rng, log2, F, mask, 20000, outside=True, invalid=True)
+    lat = lattice(sx, log2, F, mask, pts)
+    h = lat.host_arrays()
+    cs = h["cell_start"]
+    nc = lat.ncells
+    grid = orc.Grid(orc.Lattice(log2, F, mask), pts)
+    counts = grid.counts()
+    np.testing.assert_array_equal(np.diff(cs[: nc + 2]), counts)
+    # unusable objects (clipped coordinate >= 2^30) land in the last cell
+    L = orc.Lattice(log2, F, mask)
+    bad = np.zeros(len(pts[0]), bool)
+    for a in range(3):
+        if not (mask >> a) & 1:
+            bad |= pts[a] >= (1 << 30)
+    assert cs[nc + 2] - cs[nc + 1] == bad.sum() and cs[nc + 2] == len(pts[0])
+    # the sorted arrays are a permutation of the input, normalised
+    ids = h["ids"]
+    assert np.array_equal(np.sort(ids), np.arange(len(pts[0])))
+    for a, key in enumerate(("xs", "ys", "zs")):
+        exp = pts[a][ids].astype(np.uint64)
+        if (mask >> a) & 1:
+            exp = exp % (((1 << log2[a]) << F))
+        np.testing.assert_array_equal(h[key], exp.astype(np.uint32))
+    # every object sits in the cell range of its own cell
+    cellof = np.zeros(len(ids), np.int64)
+    for k in range(nc + 2):
+        cellof[cs[k]:cs[k + 1]] = k
+    xs, ys, zs = h["xs"], h["ys"], h["zs"]
+    inside = np.ones(len(ids), bool)
+    for a, v in enumerate((xs, ys, zs)):
+        if not (mask >> a) & 1:
+            inside &= v < ((1 << log2[a]) << F)
+    inside &= ~bad[ids]
+    exp_cell = ((zs >> F).astype(np.int64) << (log2[0] + log2[1])) | ((ys >> F).astype(np.int64) << log2[0]) | (xs >> F)
+    np.testing.assert_array_equal(cellof[inside], exp_cell[inside])
+    assert (cellof[~inside & ~bad[ids]] == nc).all()
+    code, flags = lat.status()
+    if bad.any():
+        assert flags & sx.FLAG_RANGE and code == sx.ERR_RANGE
+    else:
+        assert flags == 0 and code == sx.OK
+    assert lat.status()[1] == 0  # cleared
+
+
+def test_packed_index_and_outside_cell_follow_the_paper_example(sx):
+    g = read_keyed("swar_example.txt")
+    log2 = tuple(int(v) for v in g["lattice_log2"])
+    F = 4
+    c = [int(v) for v in g["center_cell"]]
+    r = [int(v) for v in g["result_cell"]]
+    e = 1 << F
+    # one object in the centre cell, one in the translated cell, one outside
+    pts = tuple(np.array([c[a] * e + 3, r[a] * e + 5, (1 << log2[a]) * e + 1 if a == 1 else 0],
+                         dtype=np.uint32) for a in range(3))
+    lat = lattice(sx, log2, F, 0, pts)
+    cs = lat.host_arrays()["cell_start"]
+    packed_c = int(g["packed_center"][0].replace("_", ""), 2)
+    packed_r = int(g["packed_result"][0].replace("_", ""), 2)
+    outside = int(g["outside_index"][0].replace("_", ""), 2)
+    assert outside == lat.ncells
+    occupied = set(np.nonzero(np.diff(cs))[0].tolist())
+    assert occupied == {packed_c, packed_r, outside}
+    # the translated cell (offset -5, +4, +3) is found from the centre cell
+    off = [int(v) for v in g["offset_cells"]]
+    d2 = sum(((r[a] * e + 5) - (c[a] * e + 3)) ** 2 for a in range(3))
+    tab = sx.Tables(lat, 2, 8 * e)
+    rp, ids, dd = run(sx, lat, tab, int(np.ceil(np.sqrt(d2))), queries=tuple(
+        np.array([c[a] * e + 3], dtype=np.uint32) for a in range(3)))
+    assert 1 in ids.tolist() and off == [r[a] - c[a] for a in range(3)]
+
+
+# ---------------------------------------------------------------------------
+# Hand fixtures (Section II.A definitions worked by hand)
+
+@pytest.mark.parametrize("name", ["hand_cyclic.txt", "hand_clipped.txt"])
+@pytest.mark.parametrize("launch", ["sphere-persistent", "sphere-plain", "cube"])
+def test_hand_fixtures(sx, name, launch):
+    latd, pts, rows = read_hand(name)
+    lat = lattice(sx, latd["log2_cells"], latd["frac_bits"], latd["cyclic_mask"], pts)
+    tab = sx.Tables(lat, 1, 64)
+    ln = _launches(sx)[launch]
+    n = len(pts[0])
+    for row in rows:
+        r = np.full(n, row["r"], np.uint32)
+        if row["kind"] == "radius":
+            rp, ids, d2 = run(sx, lat, tab, r, flags=row["flags"], launch=ln)
+        else:
+            rp, ids, d2 = run(sx, lat, tab, r, k=row["k"], mode=sx.MODE_KNN, flags=row["flags"], launch=ln)
+        i = row["q"]
+        got = list(zip(d2[rp[i]:rp[i + 1]].tolist(), ids[rp[i]:rp[i + 1]].tolist()))
+        assert got == row["exp"], (row, got)
+
+
+# ---------------------------------------------------------------------------
+# Radius queries on random worlds, every method and schedule
+
+WORLDS = [((2, 2, 2), 4), ((3, 3, 3), 6), ((4, 3, 2), 8), ((5, 5, 5), 16), ((3, 4, 5), 2)]
+
+
+@pytest.mark.parametrize("mask", [0, 3, 6, 7])
+@pytest.mark.parametrize("world", WORLDS)
+def test_radius_random_worlds(sx, orc, mask, world):
+    log2, F = world
+    say("radius world", log2, F, mask)
+    rng = np.random.default_rng(hash((log2, F, mask)) % 2 ** 32)
+    n = 1500
+    pts = tiny_points(rng, log2, F, mask, n, outside=True, invalid=True)
+    lat = lattice(sx, log2, F, mask, pts)
+    e = 1 << F
+    L = orc.Lattice(log2, F, mask)
+    grid = orc.Grid(L, pts)
+    rmax = int(2.5 * e)
+    tabs = {s: sx.Tables(lat, s, rmax) for s in range(0, min(F, 3) + 1)}
+    r = rng.integers(0, 3 * e, n).astype(np.uint32)  # some beyond the tables' cap -> cube fallback
+    r[:20] = 0
+    for flags in (0, 1):
+        ref = grid.radius(r, flags=flags)
+        for name, ln in _launches(sx).items():
+            s = int(rng.integers(0, len(tabs)))
+            if ln.table_in_lds and tabs[s].info().total_entries * 4 > 40000:
+                continue
+            assert_same(run(sx, lat, tabs[s], r, flags=flags, launch=ln), ref, f"{name} s={s} flags={flags}")
+    # explicit centres, some outside the region / unusable on clipped axes
+    qs = tiny_points(rng, log2, F, mask, 300, outside=True, invalid=True)
+    rq = rng.integers(0, 3 * e, 300).astype(np.uint32)
+    ref = grid.radius(rq, queries=qs)
+    for name, ln in _launches(sx).items():
+        if ln.table_in_lds:
+            continue
+        assert_same(run(sx, lat, tabs[min(2, len(tabs) - 1)], rq, queries=qs, launch=ln), ref, f"explicit {name}")
+
+
+def test_radius_uniform_cyclic_32_full_vs_brute_force(sx, orc):
+    from paper_cs_0608108_amd import synth
+    w = synth.radius_uniform_cyclic()
+    say("C1", w.name)
+    L = orc.Lattice(w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask)
+    ref = orc.radius_brute(L, w.pts, w.r_fx)
+    lat = lattice(sx, w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask, w.pts)
+    for s in (0, 2):
+        tab = sx.Tables(lat, s, int(w.r_fx[0]))
+        for name, ln in _launches(sx).items():
+            if ln.table_in_lds and tab.info().total_entries * 4 > 40000:
+                continue
+            assert_same(run(sx, lat, tab, w.r_fx, launch=ln), ref, f"C1 {name} s={s}")
+        # uniform radius passed as a scalar
+        assert_same(run(sx, lat, tab, int(w.r_fx[0])), ref, "C1 scalar radius")
+
+
+def test_radius_uneven_clipped_full_size(sx, orc):
+    from paper_cs_0608108_amd import synth
+    w = synth.radius_uneven_clipped()
+    say("C2", w.name)
+    L = orc.Lattice(w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask)
+    ref = orc.Grid(L, w.pts).radius(w.r_fx)
+    say("C2 oracle pairs", int(ref.row_ptr[-1]))
+    lat = lattice(sx, w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask, w.pts)
+    tab = sx.Tables(lat, 2, 4 * 65536)
+    for name in ("sphere-persistent", "sphere-plain", "cube"):
+        assert_same(run(sx, lat, tab, w.r_fx, launch=_launches(sx)[name]), ref, f"C2 {name}")
+
+
+# ---------------------------------------------------------------------------
+# K nearest
+
+@pytest.mark.parametrize("K", [1, 4, 16, 70, 300])
+def test_knn_clustered(sx, orc, K):
+    from paper_cs_0608108_amd import synth
+    lat_s = synth.LatticeSpec((5, 5, 5), 12, 7)
+    pts = synth.gaussian_cluster_points(lat_s, 30000, 3, 8, 1.5 * lat_s.edge)
+    say("knn K", K)
+    L = orc.Lattice(lat_s.log2_cells, lat_s.frac_bits, 7)
+    grid = orc.Grid(L, pts)
+    rmax = 3 * lat_s.edge
+    ref = grid.knn(np.full(len(pts[0]), K, np.uint32), np.full(len(pts[0]), rmax, np.uint32))
+    lat = lattice(sx, lat_s.log2_cells, lat_s.frac_bits, 7, pts)
+    tab = sx.Tables(lat, 2, rmax)
+    for name in ("sphere-persistent", "sphere-plain", "sphere-small-cap", "cube"):
+        got = run(sx, lat, tab, rmax, k=K, mode=sx.MODE_KNN, launch=_launches(sx)[name])
+        assert_same(got, ref, f"knn K={K} {name}")
+
+
+@pytest.mark.parametrize("mask", [0, 7])
+def test_knn_random_worlds_and_mixed_batches(sx, orc, mask):
+    rng = np.random.default_rng(77 + mask)
+    log2, F = (3, 4, 3), 8
+    e = 1 << F
+    pts = tiny_points(rng, log2, F, mask, 3000, outside=True)
+    lat = lattice(sx, log2, F, mask, pts)
+    L = orc.Lattice(log2, F, mask)
+    grid = orc.Grid(L, pts)
+    tab = sx.Tables(lat, 2, 3 * e)
+    n = len(pts[0])
+    k = rng.integers(0, 40, n).astype(np.uint32)
+    rmax = rng.integers(0, 4 * e, n).astype(np.uint32)
+    for flags in (0, 1):
+        ref = grid.knn(k, rmax, flags=flags)
+        for name in ("sphere-persistent", "sphere-small-cap", "cube-plain"):
+            assert_same(run(sx, lat, tab, rmax, k=k, mode=sx.MODE_KNN, flags=flags, launch=_launches(sx)[name]),
+                        ref, f"knn {name} flags={flags}")
+    # mixed: K-NN where k > 0, radius otherwise; explicit centres
+    qs = tiny_points(rng, log2, F, mask, 500, outside=True)
+    kk = np.where(rng.random(500) < 0.5, rng.integers(1, 30, 500), 0).astype(np.uint32)
+    rr = rng.integers(0, 4 * e, 500).astype(np.uint32)
+    ref = grid.mixed(kk, rr, queries=qs)
+    for name in ("sphere-persistent", "sphere-plain", "cube"):
+        assert_same(run(sx, lat, tab, rr, k=kk, mode=sx.MODE_MIXED, queries=qs, launch=_launches(sx)[name]),
+                    ref, f"mixed {name}")
+
+
+# ---------------------------------------------------------------------------
+# Degenerate inputs
+
+def test_edge_cases(sx, orc):
+    log2, F, mask = (3, 3, 3), 6, 7
+    e = 1 << F
+    L = orc.Lattice(log2, F, mask)
+    empty = tuple(np.zeros(0, np.uint32) for _ in range(3))
+    # N = 0, all agents: Q = 0
+    lat = lattice(sx, log2, F, mask, empty)
+    tab = sx.Tables(lat, 2, 2 * e)
+    rp, ids, d2 = run(sx, lat, tab, e)
+    assert rp.tolist() == [0] and len(ids) == 0
+    # N = 0 with explicit queries: empty rows
+    qs = tuple(np.array([5, 100, 300], np.uint32) for _ in range(3))
+    rp, ids, d2 = run(sx, lat, tab, e, queries=qs)
+    assert rp.tolist() == [0, 0, 0, 0]
+    # N = 1
+    one = tuple(np.array([77], np.uint32) for _ in range(3))
+    lat = lattice(sx, log2, F, mask, one)
+    for flags, exp in ((0, [1]), (1, [0])):
+        rp, ids, d2 = run(sx, lat, tab, 0, flags=flags)
+        assert np.diff(rp).tolist() == exp
+    # K = 0 and K > N
+    rp, ids, d2 = run(sx, lat, tab, e, k=0, mode=sx.MODE_KNN)
+    assert rp.tolist() == [0, 0]
+    rp, ids, d2 = run(sx, lat, tab, e, k=50, mode=sx.MODE_KNN)
+    assert rp.tolist() == [0, 1]
+    # every object in one cell, radius covering them all: rows longer than
+    # the LDS buffer take the windowed path
+    rng = np.random.default_rng(5)
+    n = 1100
+    same = tuple((rng.integers(0, e, n) + 3 * e).astype(np.uint32) for _ in range(3))
+    lat = lattice(sx, log2, F, mask, same)
+    tab = sx.Tables(lat, 1, 2 * e)
+    ref = orc.radius_brute(L, same, np.full(n, 2 * e, np.uint32))
+    assert int(np.diff(ref.row_ptr).max()) == n
+    for name in ("sphere-persistent", "sphere-small-cap", "cube"):
+        assert_same(run(sx, lat, tab, 2 * e, launch=_launches(sx)[name]), ref, f"one cell {name}")
+    refk = orc.radius_brute(L, same, np.full(n, 2 * e, np.uint32))
+    got = run(sx, lat, tab, 2 * e, k=n + 5, mode=sx.MODE_KNN)
+    assert_same(got, refk, "one cell knn K > N")
+    # duplicates everywhere, r = 0: rows are the duplicate groups
+    dup = tuple(np.repeat(rng.integers(0, 8 * e, 40), 5).astype(np.uint32) for _ in range(3))
+    lat = lattice(sx, log2, F, mask, dup)
+    ref = orc.radius_brute(L, dup, np.zeros(200, np.uint32))
+    assert_same(run(sx, lat, tab, 0), ref, "r = 0 duplicates")
+    # positions exactly on cell boundaries and at the world edge
+    edge = tuple(np.array([0, e, 2 * e, 8 * e - 1, 4 * e, 4 * e - 1], np.uint32) for _ in range(3))
+    lat = lattice(sx, log2, F, mask, edge)
+    for r in (0, 1, e, 2 * e - 1, 2 * e):
+        ref = orc.radius_brute(L, edge, np.full(6, r, np.uint32))
+        assert_same(run(sx, lat, tab, r), ref, f"edges r={r}")
+
+
+# ---------------------------------------------------------------------------
+# Cells touched, error paths, movement, checksum, determinism
+
+@pytest.mark.parametrize("mask", [0, 7])
+def test_cells_touched_match_oracle(sx, orc, mask):
+    import torch
+    log2, F = (5, 5, 5), 16
+    e = 1 << F
+    rng = np.random.default_rng(8 + mask)
+    n = 3000
+    pts = tuple(rng.integers(0, 32 * e, n).astype(np.uint32) for _ in range(3))
+    lat = lattice(sx, log2, F, mask, pts)
+    tab = sx.Tables(lat, 2, 4 * e)
+    r = rng.integers(0, 4 * e, n).astype(np.uint32)
+    stats = torch.zeros(4 * n, dtype=torch.int32, device="cuda")
+    run(sx, lat, tab, r, launch=sx.LaunchConfig(stats=stats))
+    st = stats.cpu().numpy().view(np.uint32).reshape(n, 4)
+    kept, inter, cube = orc.cells_touched(orc.Lattice(log2, F, mask), pts, r)
+    # rows are by object id; stats likewise
+    np.testing.assert_array_equal(st[:, 1], kept)
+    np.testing.assert_array_equal(st[:, 3], cube)
+    assert (st[:, 0] >= st[:, 1]).all()  # walked >= kept
+    say("mean kept/cube", st[:, 1].mean() / st[:, 3].mean())
+
+
+def test_capacity_overflow_sets_flag_and_writes_nothing(sx, orc):
+    import torch
+    log2, F, mask = (4, 4, 4), 8, 0
+    rng = np.random.default_rng(3)
+    pts = tuple(rng.integers(0, 16 << 8, 4000).astype(np.uint32) for _ in range(3))
+    lat = lattice(sx, log2, F, mask, pts)
+    tab = sx.Tables(lat, 2, 512)
+    q = sx.make_queries(4000, None, 512)
+    buf = sx.QueryBuffers(4000, 100)
+    buf.ids.fill_(-7)
+    sx.query(lat, tab, q, buf)
+    code, flags = lat.status()
+    assert code == sx.ERR_CAPACITY and flags & sx.FLAG_CAPACITY
+    assert int(buf.row_ptr[-1]) > 100
+    assert (buf.ids.cpu() == -7).all()
+    # exact capacity works
+    tot = int(buf.row_ptr[-1])
+    buf2 = sx.QueryBuffers(4000, tot)
+    sx.query(lat, tab, q, buf2)
+    assert lat.status() == (sx.OK, 0)
+    ref = orc.Grid(orc.Lattice(log2, F, mask), pts).radius(np.full(4000, 512, np.uint32))
+    torch.cuda.synchronize()
+    assert_same(buf2.host(), ref, "exact capacity")
+
+
+def test_range_flag_for_unusable_query_centres(sx, orc):
+    log2, F, mask = (3, 3, 3), 8, 0
+    pts = tuple(np.arange(0, 2000, 7, dtype=np.uint32) for _ in range(3))
+    lat = lattice(sx, log2, F, mask, pts)
+    tab = sx.Tables(lat, 2, 600)
+    qs = tuple(np.array([10, 1 << 30, 500], np.uint32) for _ in range(3))
+    rp, ids, d2 = run(sx, lat, tab, 600, queries=qs)
+    code, flags = lat.status()
+    assert flags & sx.FLAG_RANGE
+    assert rp[2] - rp[1] == 0
+    ref = orc.radius_brute(orc.Lattice(log2, F, mask), pts, np.full(3, 600, np.uint32), queries=qs)
+    assert_same((rp, ids, d2), ref, "range")
+
+
+def test_move_agents_and_checksum_match_oracle(sx, orc):
+    import torch
+    log2, F, mask = (6, 6, 6), 16, 7
+    rng = np.random.default_rng(12)
+    n = 50000
+    pts = tuple(rng.integers(0, 64 << 16, n).astype(np.uint32) for _ in range(3))
+    dev = [sx.to_dev_u32(a) for a in pts]
+    desc = sx.desc_of(log2, F, mask)
+    L = orc.Lattice(log2, F, mask)
+    cur = pts
+    for step in range(3):
+        sx.move_agents(desc, 99, step, *dev)
+        cur = orc.move(L, 99, step, cur)
+    torch.cuda.synchronize()
+    for a in range(3):
+        np.testing.assert_array_equal(sx.to_host_u32(dev[a]), cur[a])
+    lat = sx.Lattice(log2, F, mask, n)
+    lat.build(*dev)
+    tab = sx.Tables(lat, 2, 3 << 16)
+    q = sx.make_queries(n, None, 3 << 16)
+    buf = sx.QueryBuffers(n, 0)
+    sx.count(lat, tab, q, buf)
+    out = torch.zeros(2, dtype=torch.int64, device="cuda")
+    sx.count_checksum(buf.row_ptr, n, out)
+    got = out.cpu().numpy().view(np.uint64)
+    ref = orc.Grid(L, cur).radius(np.full(n, 3 << 16, np.uint32))
+    s, h = orc.count_checksum(ref.row_ptr)
+    assert int(got[0]) == s and int(got[1]) == h
+
+
+def test_runs_are_deterministic(sx):
+    from paper_cs_0608108_amd import synth
+    w = synth.radius_uneven_clipped(n=1 << 17, log2=6)
+    lat = lattice(sx, w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask, w.pts)
+    tab = sx.Tables(lat, 2, 4 * 65536)
+    a = run(sx, lat, tab, w.r_fx)
+    lat.build(*lat._pts_dev)
+    b = run(sx, lat, tab, w.r_fx)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
