@@ -83,8 +83,9 @@ def main():
     shape = dict(workload=w.name, n=n)
     if args.no_tune:
         cache = autotune.load_cache()
-        cfg = next((v["config"] for k, v in cache.items() if f"workload={w.name}" in k and "method=0" in k
-                    and "schedule=1" in k), {})
+        ver = autotune.kernel_version()
+        cfg = next((v["config"] for k, v in cache.items() if ver in k and f"workload={w.name}" in k
+                    and "method=0" in k and "schedule=1" in k), {})
     else:
         cfg = autotune.tune(shape, lambda ln: (lambda: step(ln)), log=log)
     tuned = sphidx.LaunchConfig(method=sphidx.METHOD_SPHERE, schedule=sphidx.SCHED_PERSISTENT, **cfg)

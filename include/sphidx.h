@@ -96,14 +96,11 @@ sphidx_status sphidx_build_lattice(sphidx_lattice* lat, const uint32_t* x_dev, c
 /* Device views of the lattice, for inspection: cell_start has ncells + 3
  * entries (region cells, then the outside cell, then the cell of skipped
  * objects), cell k holding sorted positions [cell_start[k], cell_start[k+1]);
- * xs/ys/zs are normalised coordinates and ids the object ids, by sorted
- * position.  Valid after the build's kernels complete. */
+ * points holds 4 uint32 per sorted position: the normalised x, y, z and the
+ * object id.  Valid after the build's kernels complete. */
 typedef struct {
     const uint32_t* cell_start;
-    const uint32_t* xs;
-    const uint32_t* ys;
-    const uint32_t* zs;
-    const uint32_t* ids;
+    const uint32_t* points;
     uint32_t n;
     uint32_t ncells;
 } sphidx_lattice_view;
@@ -196,8 +193,9 @@ typedef struct {
     uint32_t tile;            /* queries per wave slice / per queue grab; 0 = default */
     uint32_t blocks_per_cu;   /* persistent residency; 0 = default */
     uint32_t sort_cap;        /* per-wave row buffer (64..1024, power of two); 0 = default */
-    uint32_t table_in_lds;    /* 1: stage the whole table in LDS when it fits */
-    uint32_t reserved;
+    uint32_t table_in_lds;    /* 1: stage the whole row table in LDS (CAPACITY if it does not fit) */
+    uint32_t interior;        /* count pass, sphere method: 0 = auto (on when objects per cell >= 1),
+                                 1 = off, 2 = on: cells wholly inside the sphere are counted whole */
     uint32_t* stats_dev; /* optional uint32[4*Q]: per query walked entries, kept cells,
                             candidate objects tested, cube cells (count pass) */
 } sphidx_launch;

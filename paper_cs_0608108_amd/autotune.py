@@ -19,8 +19,16 @@ from . import sphidx
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 
 
+def kernel_version() -> str:
+    """Hash of the query kernels' source: a tuning result is reused only for
+    the kernels it was measured on."""
+    import hashlib
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "query.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:12]
+
+
 def _key(arch, shape: dict) -> str:
-    return arch + "|" + ",".join(f"{k}={shape[k]}" for k in sorted(shape))
+    return arch + "|" + kernel_version() + "|" + ",".join(f"{k}={shape[k]}" for k in sorted(shape))
 
 
 def _arch():
@@ -55,11 +63,11 @@ def time_config(run_once, reps=3):
 
 def candidates(schedule):
     if schedule == sphidx.SCHED_PERSISTENT:
-        for w, t, b, c in itertools.product((2, 4), (1, 4, 16), (4, 8), (128, 256)):
-            yield dict(waves_per_block=w, tile=t, blocks_per_cu=b, sort_cap=c)
+        for w, t, b, l, i in itertools.product((2, 4), (16, 64, 256), (4, 8), (0, 1), (1, 2)):
+            yield dict(waves_per_block=w, tile=t, blocks_per_cu=b, sort_cap=256, table_in_lds=l, interior=i)
     else:
-        for w, t, c in itertools.product((1, 4), (1, 4), (128, 256)):
-            yield dict(waves_per_block=w, tile=t, sort_cap=c)
+        for w, t, l, i in itertools.product((2, 4), (1, 4, 16), (0, 1), (1, 2)):
+            yield dict(waves_per_block=w, tile=t, sort_cap=256, table_in_lds=l, interior=i)
 
 
 def tune(shape: dict, make_runner, method=sphidx.METHOD_SPHERE, schedule=sphidx.SCHED_PERSISTENT,
@@ -74,7 +82,12 @@ def tune(shape: dict, make_runner, method=sphidx.METHOD_SPHERE, schedule=sphidx.
     best = None
     for cfg in candidates(schedule):
         ln = sphidx.LaunchConfig(method=method, schedule=schedule, **cfg)
-        ms = time_config(make_runner(ln))
+        try:
+            ms = time_config(make_runner(ln))
+        except sphidx.SphidxError as err:  # e.g. the row table does not fit in LDS
+            if log:
+                log(f"tune {cfg} -> skipped ({err})")
+            continue
         if log:
             log(f"tune {cfg} -> {ms:.3f} ms")
         if best is None or ms < best[0]:

@@ -34,7 +34,7 @@ uint32_t ncells_of(const sphidx_lattice_desc* d) {
 }
 
 struct Layout {
-    size_t cell_start, xs, ys, zs, ids, rank, scan_tmp, status, total;
+    size_t cell_start, pts, rank, scan_tmp, status, total;
 };
 
 Layout lattice_layout(const sphidx_lattice_desc* d, uint32_t max_points) {
@@ -47,10 +47,7 @@ Layout lattice_layout(const sphidx_lattice_desc* d, uint32_t max_points) {
         return o;
     };
     L.cell_start = take((nc + 4) * 4);
-    L.xs = take((size_t)max_points * 4);
-    L.ys = take((size_t)max_points * 4);
-    L.zs = take((size_t)max_points * 4);
-    L.ids = take((size_t)max_points * 4);
+    L.pts = take((size_t)max_points * 16);
     L.rank = take((size_t)max_points * 4);
     L.scan_tmp = take(scan_u32_tmp_words(nc + 2) * 4);
     L.status = take(64 * 4);
@@ -66,10 +63,7 @@ LatArgs lat_args(const sphidx_lattice* lat) {
     L.ncells = lat->ncells;
     L.n = lat->n;
     L.cs = lat->cell_start;
-    L.xs = lat->xs;
-    L.ys = lat->ys;
-    L.zs = lat->zs;
-    L.ids = lat->ids;
+    L.pts = lat->pts;
     L.status = lat->status;
     return L;
 }
@@ -78,21 +72,21 @@ TabArgs tab_args(const sphidx_tables* t) {
     TabArgs T;
     std::memset(&T, 0, sizeof(T));
     if (!t) return T;
-    T.off = t->d_off;
-    T.key = t->d_key;
-    T.cstart = t->d_class_start;
-    T.rindex = t->d_rindex;
+    T.rows = t->d_rows;
+    T.rkey = t->d_rkey;
+    T.cstart = t->d_rclass_start;
+    T.rindex = t->d_rrindex;
     T.s = t->s;
     T.rshift = t->rshift;
     T.nr = t->nr;
     T.rmax = t->rmax_fx;
-    T.total = (uint32_t)t->total;
+    T.total = (uint32_t)t->h_rows.size();
     T.has = 1;
     return T;
 }
 
 struct Launch {
-    uint32_t method, persistent, waves, tile, bpc, cap, tab_lds;
+    uint32_t method, persistent, waves, tile, bpc, cap, tab_lds, interior;
     uint32_t* stats;
 };
 
@@ -104,6 +98,8 @@ sphidx_status resolve_launch(const sphidx_launch* in, const sphidx_tables* tab, 
     o.bpc = (in && in->blocks_per_cu) ? in->blocks_per_cu : 8u;
     o.cap = (in && in->sort_cap) ? in->sort_cap : 256u;
     o.tab_lds = in ? in->table_in_lds : 0u;
+    o.interior = in ? in->interior : 0u;
+    if (o.interior > 2) return SPHIDX_ERR_INVALID_ARG;
     o.stats = in ? in->stats_dev : nullptr;
     if (in && in->schedule > SPHIDX_SCHED_PERSISTENT) return SPHIDX_ERR_INVALID_ARG;
     if (o.method > SPHIDX_METHOD_CUBE) return SPHIDX_ERR_INVALID_ARG;
@@ -111,15 +107,35 @@ sphidx_status resolve_launch(const sphidx_launch* in, const sphidx_tables* tab, 
     if (o.cap < 64 || o.cap > 1024 || (o.cap & (o.cap - 1))) return SPHIDX_ERR_INVALID_ARG;
     if (o.tile > 4096 || o.bpc > 64) return SPHIDX_ERR_INVALID_ARG;
     if (o.method == SPHIDX_METHOD_SPHERE && !tab) return SPHIDX_ERR_INVALID_ARG;
-    size_t wave_bytes = (size_t)o.cap * 24 + 64 * 12;
-    size_t tab_bytes = (o.tab_lds && tab) ? ((size_t)tab->total * 4 + 15) / 16 * 16 : 0;
-    if ((size_t)o.waves * wave_bytes > kMaxBlockLds) return SPHIDX_ERR_INVALID_ARG;
-    if (o.tab_lds && (!tab || tab_bytes + (size_t)o.waves * wave_bytes > kMaxBlockLds)) return SPHIDX_ERR_CAPACITY;
     if (o.method == SPHIDX_METHOD_CUBE) o.tab_lds = 0;
+    size_t tab_bytes = (o.tab_lds && tab) ? (tab->h_rows.size() * 4 + 15) / 16 * 16 : 0;
+    if (query_lds_bytes(2, o.cap, o.waves, 0) > kMaxBlockLds) return SPHIDX_ERR_INVALID_ARG;
+    if (o.tab_lds && query_lds_bytes(2, o.cap, o.waves, tab_bytes) > kMaxBlockLds) return SPHIDX_ERR_CAPACITY;
     return SPHIDX_OK;
 }
 
-size_t query_ws_bytes(uint32_t Q) { return align_up(SPHIDX_NQUEUE * 8) + align_up(scan_i64_tmp_bytes(Q)); }
+// Query workspace: counters | descriptors[Q] | longq[Q] | scan partials.
+struct QLayout {
+    size_t counters, desc, longq, scan, total;
+};
+
+QLayout query_layout(uint32_t Q) {
+    QLayout l;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align_up(bytes ? bytes : 4);
+        return o;
+    };
+    l.counters = take(SPHIDX_COUNTER_WORDS * 4);
+    l.desc = take((size_t)Q * 64);
+    l.longq = take((size_t)Q * 4);
+    l.scan = take(scan_i64_tmp_bytes(Q));
+    l.total = off;
+    return l;
+}
+
+size_t query_ws_bytes(uint32_t Q) { return query_layout(Q).total; }
 
 sphidx_status check_queries(const sphidx_lattice* lat, const sphidx_queries* q, const sphidx_csr* csr) {
     if (!lat || !q || !csr || !csr->row_ptr_dev) return SPHIDX_ERR_INVALID_ARG;
@@ -151,7 +167,12 @@ QArgs q_args(const sphidx_queries* q, sphidx_csr* csr, const Launch& ln) {
     A.out_ids = csr->ids_dev;
     A.out_d2 = csr->dist2_dev;
     A.capacity = csr->capacity;
-    A.queues = (uint32_t*)csr->workspace_dev;
+    const QLayout ql = query_layout(q->count);
+    char* ws = (char*)csr->workspace_dev;
+    A.queues = (uint32_t*)(ws + ql.counters);
+    A.long_count = A.queues + 3 * SPHIDX_NQUEUE * SPHIDX_QSTRIDE;
+    A.longq = (uint32_t*)(ws + ql.longq);
+    A.desc = (uint4*)(ws + ql.desc);
     A.stats = ln.stats;
     A.method = ln.method;
     A.persistent = ln.persistent;
@@ -160,7 +181,7 @@ QArgs q_args(const sphidx_queries* q, sphidx_csr* csr, const Launch& ln) {
     return A;
 }
 
-void* scan_tmp_of(sphidx_csr* csr) { return (char*)csr->workspace_dev + align_up(SPHIDX_NQUEUE * 8); }
+void* scan_tmp_of(sphidx_csr* csr, uint32_t Q) { return (char*)csr->workspace_dev + query_layout(Q).scan; }
 
 sphidx_status dev_err(hipError_t e) { return e == hipSuccess ? SPHIDX_OK : SPHIDX_ERR_DEVICE; }
 
@@ -182,7 +203,7 @@ sphidx_status run_pass(int pass, const sphidx_lattice* lat, const sphidx_tables*
     if (s != SPHIDX_OK) return s;
     if (pass == 1 && csr->capacity > 0 && !csr->ids_dev) return SPHIDX_ERR_INVALID_ARG;
     if (tab && tab->F != lat->desc.frac_bits) return SPHIDX_ERR_INVALID_ARG;
-    if (tab && ln.method == SPHIDX_METHOD_SPHERE && !tab->d_off) {
+    if (tab && ln.method == SPHIDX_METHOD_SPHERE && !tab->d_rows) {
         s = tables_upload(const_cast<sphidx_tables*>(tab));
         if (s != SPHIDX_OK) return s;
     }
@@ -190,12 +211,13 @@ sphidx_status run_pass(int pass, const sphidx_lattice* lat, const sphidx_tables*
     TabArgs T = tab_args(ln.method == SPHIDX_METHOD_SPHERE ? tab : nullptr);
     T.lds = ln.tab_lds;
     QArgs A = q_args(q, csr, ln);
+    // counting wholly-inside cells whole saves object reads but costs a
+    // second extent per row: worth it once cells hold an object or more
+    A.interior = ln.interior == 2 || (ln.interior == 0 && (uint64_t)lat->n >= (uint64_t)lat->ncells);
     if (pass == 0) {
-        if (q->count > 0) {
-            s = dev_err(launch_query_pass(0, L, T, A, ln.waves, ln.bpc, st));
-            if (s != SPHIDX_OK) return s;
-        }
-        return dev_err(launch_scan_i64(csr->row_ptr_dev, q->count, scan_tmp_of(csr), st));
+        s = dev_err(launch_query_pass(0, L, T, A, ln.waves, ln.bpc, st));
+        if (s != SPHIDX_OK) return s;
+        return dev_err(launch_scan_i64(csr->row_ptr_dev, q->count, scan_tmp_of(csr, q->count), st));
     }
     return dev_err(launch_query_pass(1, L, T, A, ln.waves, ln.bpc, st));
 }
@@ -225,10 +247,7 @@ sphidx_status sphidx_lattice_create(const sphidx_lattice_desc* desc, uint32_t ma
     lat->n = 0;
     lat->ncells = ncells_of(desc);
     lat->cell_start = (uint32_t*)(b + ly.cell_start);
-    lat->xs = (uint32_t*)(b + ly.xs);
-    lat->ys = (uint32_t*)(b + ly.ys);
-    lat->zs = (uint32_t*)(b + ly.zs);
-    lat->ids = (uint32_t*)(b + ly.ids);
+    lat->pts = (uint4*)(b + ly.pts);
     lat->rank = (uint32_t*)(b + ly.rank);
     lat->scan_tmp = (uint32_t*)(b + ly.scan_tmp);
     lat->status = (uint32_t*)(b + ly.status);
@@ -260,10 +279,7 @@ sphidx_status sphidx_build_lattice(sphidx_lattice* lat, const uint32_t* x_dev, c
 sphidx_status sphidx_lattice_get_view(const sphidx_lattice* lat, sphidx_lattice_view* out) {
     if (!lat || !out) return SPHIDX_ERR_INVALID_ARG;
     out->cell_start = lat->cell_start;
-    out->xs = lat->xs;
-    out->ys = lat->ys;
-    out->zs = lat->zs;
-    out->ids = lat->ids;
+    out->points = (const uint32_t*)lat->pts;
     out->n = lat->n;
     out->ncells = lat->ncells;
     return SPHIDX_OK;

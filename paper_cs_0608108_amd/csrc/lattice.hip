@@ -3,7 +3,8 @@
 //   fill    count[0 .. ncells+2) = 0
 //   hist    per object: normalise, cell id, slot = atomicAdd(count[cell], 1)
 //   scan    exclusive prefix over ncells + 2 counts -> cell_start (+ total)
-//   scatter per object: position = cell_start[cell] + slot; SoA store
+//   scatter per object: position = cell_start[cell] + slot; one 16-byte
+//           record {x, y, z, id} per object, so a candidate is one load
 // plus the reduce-then-scan used for cell_start and for query row pointers.
 #include "sphidx_internal.h"
 
@@ -30,10 +31,7 @@ struct BuildArgs {
     const uint32_t* z;
     uint32_t* count;  // == cell_start storage
     uint32_t* rank;
-    uint32_t* xs;
-    uint32_t* ys;
-    uint32_t* zs;
-    uint32_t* ids;
+    uint4* pts;
     uint32_t* status;
 };
 
@@ -82,10 +80,7 @@ __global__ __launch_bounds__(256) void scatter_kernel(BuildArgs a) {
     bool bad;
     uint32_t cell = object_cell(a, vx, vy, vz, bad);
     uint32_t pos = a.count[cell] + a.rank[i];
-    a.xs[pos] = vx;
-    a.ys[pos] = vy;
-    a.zs[pos] = vz;
-    a.ids[pos] = i;
+    a.pts[pos] = make_uint4(vx, vy, vz, i);
 }
 
 // ---------------------------------------------------------------------------
@@ -212,10 +207,7 @@ hipError_t launch_build(const sphidx_lattice* lat, const uint32_t* x, const uint
     a.z = z;
     a.count = lat->cell_start;
     a.rank = lat->rank;
-    a.xs = lat->xs;
-    a.ys = lat->ys;
-    a.zs = lat->zs;
-    a.ids = lat->ids;
+    a.pts = lat->pts;
     a.status = lat->status;
     size_t ncount = (size_t)lat->ncells + 2;
     hipError_t e = launch_fill_u32(lat->cell_start, 0u, ncount + 1, st);

@@ -1,27 +1,34 @@
-// Neighbourhood query kernels for gfx950 (wave64), one wavefront per query.
+// Neighbourhood query kernels for gfx950 (wave64): one wavefront per query.
 //
-// Per query (all values wave-uniform):
-//   setup   cell = q >> F, sub-cell class = top s bits of q's position inside
-//           its cell, r^2; the class table's prefix end from the radius index
-//           (Section II.A: a single lookup gives where to stop; Section III.A:
-//           the sub-cell position selects a specialised table).
-//   walk    the 64 lanes take 64 consecutive table entries (cells sorted by
-//           increasing key, centre to edge).  Each lane translates its offset
-//           to an absolute cell (wrap on cyclic axes, region test on clipped
-//           ones, Section II.B), applies the exact run-time test min-dist^2 <=
-//           r^2 (Eq. 1, applied to every entry) and, in the count pass, the
-//           unconditional inclusion of cells wholly inside the sphere
-//           (Section III.A, last paragraph).
-//   scan    the kept cells' objects are flattened over the lanes (inclusive
-//           scan of per-lane counts + a 6-step search for the owning lane),
-//           so a wave tests 64 candidates per step whatever the cell loads.
-//   output  pass 0 counts hits per row (K-NN: min(K, hits within the cap),
-//           stopping as soon as K are found).  Pass 1 collects the row in LDS
-//           (ballot + mbcnt compaction), sorts it by (dist^2, id) and writes
-//           it; K-NN rows (and radius rows longer than the LDS buffer) keep a
-//           sorted top-M in LDS, shrink the bound to the M-th distance once M
-//           are held and stop at the first table entry whose key exceeds it
-//           (Section II.A, K nearest).
+// Per query:
+//   setup   (one thread per query, setup_kernel) home cell = q >> F, sub-cell
+//           class = the top s bits of q's position inside its cell (Section
+//           III.A: the position inside the cell selects a specialised table),
+//           the method, and the class table's prefix end from the radius
+//           index (Section II.A: one lookup tells where to stop in the sorted
+//           offset array), stored as a 64-byte descriptor.
+//   walk    (one wavefront per query, all values wave-uniform) 64 x EPL
+//           consecutive table entries per step, EPL per lane, sorted by
+//           increasing key: centre to edge.  A lane translates its offset to
+//           an absolute cell (wrap on cyclic axes, region test on clipped
+//           ones, Section II.B), applies the exact run-time test
+//           min-dist^2 <= r^2 (Eq. 1, to every entry) and, when counting,
+//           includes whole the cells that lie wholly inside the sphere
+//           (Section III.A, last paragraph).  The next step's entries are
+//           prefetched while this step's cells are read.
+//   scan    the objects of the kept cells are spread over the lanes: a DPP
+//           prefix sum of per-lane counts, an LDS map of where each lane's
+//           range starts and a DPP max-scan give every slot its owner, so a
+//           wave tests 64 candidates per step whatever the cell loads.  One
+//           16-byte load fetches a candidate's coordinates and id.
+//   output  count pass: hits per row (K-NN: min(K, hits within the cap),
+//           stopping once K are found).  Write pass: radius rows are
+//           compacted into LDS with ballot + mbcnt, sorted by (dist^2, id)
+//           and stored; K-NN rows, and radius rows longer than the LDS
+//           buffer, go to the top-M kernel, which keeps the M best in LDS,
+//           shrinks the bound to the M-th distance once M are held and stops
+//           at the first table entry whose key exceeds it (Section II.A,
+//           K nearest).
 // Queries whose radius exceeds the tables' cap or the cyclic limit, or whose
 // centre is outside the region, and every query of the cube method, scan the
 // bin-lattice bounding cube instead (Section I; Section III.C).
@@ -31,6 +38,10 @@ namespace {
 
 constexpr uint32_t kMaxId = 0xFFFFFFFFu;
 constexpr uint64_t kMaxD2 = ~0ull;
+constexpr int kSphere = 0, kCube = 1;
+
+// ---------------------------------------------------------------------------
+// Wave primitives
 
 __device__ __forceinline__ uint32_t lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
@@ -46,29 +57,43 @@ __device__ __forceinline__ uint64_t uni64(uint64_t v) {
     return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
 }
 __device__ __forceinline__ uint32_t lane_val(uint32_t v, uint32_t l) { return __builtin_amdgcn_readlane(v, l); }
-// LDS ordering point for one wavefront (its LDS operations execute in order;
-// this keeps the compiler from moving them across the point).
+// LDS ordering point for one wavefront: its LDS operations execute in order;
+// this keeps the compiler from moving them across the point.
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-    const uint32_t l = lane_id();
-#pragma unroll
-    for (uint32_t d = 1; d < 64; d <<= 1) {
-        uint32_t t = __shfl_up(v, d);
-        if (l >= d) v += t;
-    }
+template <int CTRL, int ROWS, bool BOUND>
+__device__ __forceinline__ uint32_t dpp(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, BOUND);
+}
+
+// Inclusive prefix sum over the 64 lanes: shifts by 1, 2, 4, 8 inside each
+// row of 16 lanes, then row 0's total into row 1 and row 2's into row 3
+// (row_bcast:15), then rows 0-1's total into rows 2-3 (row_bcast:31).
+__device__ __forceinline__ uint32_t scan_add(uint32_t v) {
+    v += dpp<0x111, 0xF, true>(v);
+    v += dpp<0x112, 0xF, true>(v);
+    v += dpp<0x114, 0xF, true>(v);
+    v += dpp<0x118, 0xF, true>(v);
+    v += dpp<0x142, 0xA, false>(v);
+    v += dpp<0x143, 0xC, false>(v);
     return v;
 }
 
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-    for (uint32_t d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d);
-    return uni(v);
+__device__ __forceinline__ uint32_t scan_max(uint32_t v) {
+    v = max(v, dpp<0x111, 0xF, true>(v));
+    v = max(v, dpp<0x112, 0xF, true>(v));
+    v = max(v, dpp<0x114, 0xF, true>(v));
+    v = max(v, dpp<0x118, 0xF, true>(v));
+    v = max(v, dpp<0x142, 0xA, false>(v));
+    v = max(v, dpp<0x143, 0xC, false>(v));
+    return v;
 }
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) { return lane_val(scan_add(v), 63); }
 
 __device__ __forceinline__ bool key_less(uint64_t da, uint32_t ia, uint64_t db, uint32_t ib) {
     return da < db || (da == db && ia < ib);
@@ -95,423 +120,342 @@ __device__ __forceinline__ void wave_sort64(uint64_t& d, uint32_t& id) {
     }
 }
 
-// Exact u32 quotient (a < 2^31, 1 <= b < 2^31) from a double reciprocal and
-// one correction step.
-__device__ __forceinline__ uint32_t small_div(uint32_t a, uint32_t b, double inv_b) {
+// Exact quotient (a < 2^31, 1 <= b < 2^31) from a double reciprocal and one
+// correction step.
+__device__ __forceinline__ uint32_t exact_div(uint32_t a, uint32_t b, double inv_b) {
     uint32_t q = (uint32_t)((double)a * inv_b);
     if ((uint64_t)q * b > a) --q;
     if ((uint64_t)(q + 1) * b <= a) ++q;
     return q;
 }
 
-struct QState {
-    uint32_t row;    // output row
-    uint32_t self;   // sorted position excluded (EXCLUDE_SELF, all agents) or ~0
-    uint32_t q[3];   // normalised centre
-    uint32_t r;      // radius or K-NN cap
+__device__ __forceinline__ uint64_t sq(uint32_t g) { return (uint64_t)g * (uint64_t)g; }
+
+
+// ---------------------------------------------------------------------------
+// Query descriptors
+
+enum : uint32_t { F_VALID = 1u, F_KNN = 2u, F_SPHERE = 4u, F_OUTSIDE = 8u };
+
+struct Query {
+    uint32_t q[3];  // normalised centre
+    uint32_t row;   // output row
+    uint32_t r;     // radius, or the K-NN cap
+    uint32_t k;
+    uint32_t flags;
+    uint32_t tb;    // sphere: first entry of the class table
+    uint32_t tend;  // sphere: prefix length
+    uint32_t ncube; // cube: cells of the bounding cube
+    uint32_t nn[3]; // cube: cells per axis
+    int32_t lo[3];  // cube: first cell per axis
+    uint32_t self;  // sorted position excluded (EXCLUDE_SELF, all agents) or ~0
+    uint32_t c[3];  // home cell
+    uint32_t f[3];  // position inside the home cell
     uint64_t r2;
-    uint32_t k;      // K for K-NN rows
-    bool knn;
-    bool valid;
-    bool sphere;
-    bool outside;    // objects of the outside cell may be within r
-    // sphere walk
-    uint32_t c[3];   // home cell
-    uint32_t f[3];   // position inside the home cell
-    uint32_t tb;     // first entry of the class table
-    uint32_t tend;   // prefix length
-    // bounding cube
-    int32_t lo[3];
-    uint32_t nn[3];
-    uint32_t ncube;
-    double inv_nx, inv_nxy;
 };
 
 __device__ __forceinline__ uint32_t pack_cell(const LatArgs& L, uint32_t x, uint32_t y, uint32_t z) {
     return (z << (L.lg[0] + L.lg[1])) | (y << L.lg[0]) | x;
 }
 
-__device__ void setup_query(const LatArgs& L, const TabArgs& T, const QArgs& A, uint32_t qi, QState& s) {
-    uint32_t v[3];
-    s.valid = true;
-    if (A.qx == nullptr) {
-        s.row = uni(L.ids[qi]);
-        s.self = (A.flags & SPHIDX_EXCLUDE_SELF) ? qi : kMaxId;
-        v[0] = uni(L.xs[qi]);
-        v[1] = uni(L.ys[qi]);
-        v[2] = uni(L.zs[qi]);
-        // objects left out by the build (clipped coordinate >= 2^30) sit
-        // after the outside cell; their rows stay empty
-        s.valid = qi < uni(L.cs[L.ncells + 1]);
-    } else {
-        s.row = qi;
-        s.self = kMaxId;
-        v[0] = uni(A.qx[qi]);
-        v[1] = uni(A.qy[qi]);
-        v[2] = uni(A.qz[qi]);
-        for (int a = 0; a < 3; ++a) {
-            if ((L.cyc >> a) & 1u)
-                v[a] &= (1u << (L.lg[a] + L.F)) - 1u;
-            else if (v[a] >= (1u << 30))
-                s.valid = false;
+// One thread per query: centre, radius, K, method and walk extent.
+template <int METHOD>
+__global__ __launch_bounds__(256) void setup_kernel(LatArgs L, TabArgs T, QArgs A) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool range_bad = false, fallback = false;
+    if (i < A.Q) {
+        uint32_t q[3], row, r, k;
+        bool valid = true;
+        if (A.qx == nullptr) {
+            const uint4 P = L.pts[i];
+            q[0] = P.x;
+            q[1] = P.y;
+            q[2] = P.z;
+            row = P.w;
+            // objects left out by the build (clipped coordinate >= 2^30) sit
+            // after the outside cell; their rows stay empty
+            valid = i < L.cs[L.ncells + 1];
+        } else {
+            q[0] = A.qx[i];
+            q[1] = A.qy[i];
+            q[2] = A.qz[i];
+            row = i;
+            for (int a = 0; a < 3; ++a) {
+                if ((L.cyc >> a) & 1u)
+                    q[a] &= (1u << (L.lg[a] + L.F)) - 1u;
+                else if (q[a] >= (1u << 30))
+                    valid = false;
+            }
+            range_bad = !valid;
         }
-        if (!s.valid) atomicOr(L.status, SPHIDX_FLAG_RANGE);
+        r = A.rad ? A.rad[row] : A.rad_u;
+        k = A.kk ? A.kk[row] : A.k_u;
+        const bool knn = A.mode == SPHIDX_MODE_KNN || (A.mode == SPHIDX_MODE_MIXED && k > 0);
+        if (knn && k == 0) valid = false;
+        const uint32_t e = 1u << L.F;
+        bool inside = true, cyc_ok = true, outside = false;
+        uint32_t ncube = 1, nn[3] = {0, 0, 0};
+        int32_t lo3[3] = {0, 0, 0};
+        for (int a = 0; a < 3; ++a) {
+            const uint32_t La = 1u << L.lg[a];
+            int64_t lo = ((int64_t)q[a] - (int64_t)r) >> L.F;
+            int64_t hi = ((int64_t)q[a] + (int64_t)r) >> L.F;
+            if ((L.cyc >> a) & 1u) {
+                // the sphere walk needs ceil(r/e) <= L/2 - 1 (no offset repeats a cell)
+                if (La < 4 || (uint64_t)r > (uint64_t)(La / 2 - 1) * e) cyc_ok = false;
+                if (hi - lo + 1 >= (int64_t)La) {
+                    lo = 0;
+                    hi = La - 1;
+                }
+            } else {
+                if (q[a] >= (La << L.F)) inside = false;
+                if (hi >= (int64_t)La) outside = true;
+                if (lo < 0) lo = 0;
+                if (hi > (int64_t)La - 1) hi = (int64_t)La - 1;
+            }
+            lo3[a] = (int32_t)lo;
+            nn[a] = hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
+            ncube *= nn[a];
+        }
+        const bool sphere = METHOD == kSphere && inside && cyc_ok && r <= T.rmax;
+        fallback = valid && METHOD == kSphere && !sphere;
+        uint32_t tb = 0, tend = 0;
+        if (sphere && valid) {
+            // row tables are specialised on the (y, z) sub-cell position
+            const uint32_t cls = ((q[1] & (e - 1u)) >> (L.F - T.s)) | (((q[2] & (e - 1u)) >> (L.F - T.s)) << T.s);
+            const uint32_t j = (uint32_t)(((uint64_t)r + (1u << T.rshift) - 1u) >> T.rshift);
+            tb = T.cstart[cls];
+            tend = T.rindex[(size_t)cls * T.nr + j];
+        }
+        const uint32_t flags = (valid ? F_VALID : 0u) | (knn ? F_KNN : 0u) | (sphere ? F_SPHERE : 0u) |
+                               (outside ? F_OUTSIDE : 0u);
+        uint4* d = A.desc + 4 * (size_t)i;
+        d[0] = make_uint4(q[0], q[1], q[2], row);
+        d[1] = make_uint4(r, k, flags, tb);
+        d[2] = make_uint4(tend, ncube, nn[0], nn[1]);
+        d[3] = make_uint4((uint32_t)lo3[0], (uint32_t)lo3[1], (uint32_t)lo3[2], nn[2]);
     }
-    s.r = A.rad ? uni(A.rad[s.row]) : A.rad_u;
-    s.r2 = (uint64_t)s.r * (uint64_t)s.r;
-    uint32_t kk = A.kk ? uni(A.kk[s.row]) : A.k_u;
-    s.knn = (A.mode == SPHIDX_MODE_KNN) || (A.mode == SPHIDX_MODE_MIXED && kk > 0);
-    s.k = kk;
-    if (s.knn && kk == 0) s.valid = false;
+    if (__ballot(range_bad) && lane_id() == 0) atomicOr(L.status, SPHIDX_FLAG_RANGE);
+    if (__ballot(fallback) && lane_id() == 0) atomicOr(L.status, SPHIDX_FLAG_FALLBACK);
+}
+
+// Descriptors are read through the scalar cache (the address is uniform and
+// the array was written by an earlier kernel).
+typedef __attribute__((address_space(4))) const uint32_t const_u32;
+
+__device__ __forceinline__ Query load_query(const LatArgs& L, const QArgs& A, uint32_t qi) {
+    Query s;
+    const const_u32* d = (const const_u32*)(A.desc + 4 * (size_t)uni(qi));
+    s.q[0] = d[0];
+    s.q[1] = d[1];
+    s.q[2] = d[2];
+    s.row = d[3];
+    s.r = d[4];
+    s.k = d[5];
+    s.flags = d[6];
+    s.tb = d[7];
+    s.tend = d[8];
+    s.ncube = d[9];
+    if (!(s.flags & F_SPHERE)) {
+        s.nn[0] = d[10];
+        s.nn[1] = d[11];
+        s.nn[2] = d[15];
+        s.lo[0] = (int32_t)d[12];
+        s.lo[1] = (int32_t)d[13];
+        s.lo[2] = (int32_t)d[14];
+    }
+    s.self = (A.qx == nullptr && (A.flags & SPHIDX_EXCLUDE_SELF)) ? qi : kMaxId;
     const uint32_t e = 1u << L.F;
-    bool inside = true, cyc_ok = true;
-    s.outside = false;
-    s.ncube = 1;
     for (int a = 0; a < 3; ++a) {
-        s.q[a] = v[a];
-        const uint32_t La = 1u << L.lg[a];
-        const bool cyc = (L.cyc >> a) & 1u;
-        // bounding cube along a: cells floor((q-r)/e) .. floor((q+r)/e)
-        int64_t lo = ((int64_t)v[a] - (int64_t)s.r) >> L.F;
-        int64_t hi = ((int64_t)v[a] + (int64_t)s.r) >> L.F;
-        if (cyc) {
-            if (hi - lo + 1 >= (int64_t)La) {
+        s.c[a] = s.q[a] >> L.F;
+        s.f[a] = s.q[a] & (e - 1u);
+    }
+    s.r2 = (uint64_t)s.r * (uint64_t)s.r;
+    return s;
+}
+
+// Cells of the bounding cube of query s (in-region cells only), for stats.
+__device__ __forceinline__ uint32_t cube_cells(const LatArgs& L, const Query& s) {
+    uint32_t n = 1;
+    for (int a = 0; a < 3; ++a) {
+        const int64_t La = (int64_t)1 << L.lg[a];
+        int64_t lo = ((int64_t)s.q[a] - (int64_t)s.r) >> L.F;
+        int64_t hi = ((int64_t)s.q[a] + (int64_t)s.r) >> L.F;
+        if ((L.cyc >> a) & 1u) {
+            if (hi - lo + 1 >= La) {
                 lo = 0;
                 hi = La - 1;
             }
-            // limit of the sphere walk: ceil(r/e) <= L/2 - 1 (no offset repeats a cell)
-            uint64_t lim = La >= 2 ? (uint64_t)(La / 2 - 1) * e : 0;
-            if (La < 4 || (uint64_t)s.r > lim) cyc_ok = false;
         } else {
-            if (hi >= (int64_t)La) s.outside = true;
             if (lo < 0) lo = 0;
-            if (hi > (int64_t)La - 1) hi = (int64_t)La - 1;
-            if (v[a] >= (La << L.F)) inside = false;
+            if (hi > La - 1) hi = La - 1;
         }
-        s.lo[a] = (int32_t)lo;
-        s.nn[a] = hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
-        s.ncube *= s.nn[a];
-        s.c[a] = v[a] >> L.F;
-        s.f[a] = v[a] & (e - 1u);
+        n *= hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
     }
-    s.inv_nx = s.nn[0] ? 1.0 / (double)s.nn[0] : 0.0;
-    s.inv_nxy = (s.nn[0] * s.nn[1]) ? 1.0 / (double)(s.nn[0] * s.nn[1]) : 0.0;
-    s.sphere = (A.method == SPHIDX_METHOD_SPHERE) && T.has && inside && cyc_ok && s.r <= T.rmax;
-    if (A.method == SPHIDX_METHOD_SPHERE && !s.sphere && s.valid) atomicOr(L.status, SPHIDX_FLAG_FALLBACK);
-    s.tb = 0;
-    s.tend = 0;
-    if (s.sphere) {
-        uint32_t cls = 0;
-        for (int a = 0; a < 3; ++a) cls |= (s.f[a] >> (L.F - T.s)) << (a * T.s);
-        s.tb = uni(T.cstart[cls]);
-        uint32_t j = (uint32_t)(((uint64_t)s.r + (1u << T.rshift) - 1u) >> T.rshift);
-        s.tend = uni(T.rindex[(size_t)cls * T.nr + j]);
-    }
+    return n;
 }
 
-// Per-axis distances from the query (position f inside its cell) to the
-// nearest and farthest positions of the cell at offset o along that axis.
-__device__ __forceinline__ void axis_gap(int o, uint32_t f, uint32_t F, uint32_t& gmin, uint32_t& gmax) {
-    const uint32_t e = 1u << F;
-    if (o > 0) {
-        gmin = ((uint32_t)o << F) - f;
-        gmax = gmin + e - 1u;
-    } else if (o < 0) {
-        uint32_t a = (uint32_t)(-o);
-        gmin = f + ((a - 1u) << F) + 1u;
-        gmax = f + (a << F);
-    } else {
-        gmin = 0u;
-        gmax = max(f, e - 1u - f);
-    }
-}
+// ---------------------------------------------------------------------------
+// Rows of the walk
 
-__device__ __forceinline__ uint64_t sq(uint32_t g) { return (uint64_t)g * (uint64_t)g; }
-
-// One cell of the query's list.  `kept`: the cell is in the region and must
-// be scanned; `interior`: every position of the cell is within r.
-struct CellRef {
-    uint32_t cell;
-    bool kept;
-    bool interior;
+// Per lane, one x-row of cells: up to two object ranges to test (two when
+// the run of cells wraps around a cyclic x axis), a range of objects in cells
+// wholly inside the sphere (counted without reading them), and the number
+// of cells of the row the sphere meets.
+struct RowRef {
+    uint32_t st0, cnt0, st1, cnt1;
+    uint32_t ist, icnt;
+    uint32_t kept;
 };
 
-__device__ __forceinline__ CellRef sphere_entry(const LatArgs& L, const TabArgs& T, const uint32_t* tab_lds,
-                                                const QState& s, uint32_t e, uint64_t bound2) {
-    CellRef c;
-    uint32_t w = tab_lds ? tab_lds[s.tb + e] : T.off[s.tb + e];
-    int o[3];
-    o[0] = ((int)(w << 22)) >> 22;
-    o[1] = ((int)(w << 12)) >> 22;
-    o[2] = ((int)(w << 2)) >> 22;
-    uint64_t mind2 = 0, maxd2 = 0;
-    bool in = true;
-    uint32_t t[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        uint32_t gmin, gmax;
-        axis_gap(o[a], s.f[a], L.F, gmin, gmax);
-        mind2 += sq(gmin);
-        maxd2 += sq(gmax);
-        int ta = (int)s.c[a] + o[a];
-        const uint32_t La = 1u << L.lg[a];
-        if ((L.cyc >> a) & 1u)
-            t[a] = (uint32_t)ta & (La - 1u);
-        else {
-            in = in && (uint32_t)ta < La;
-            t[a] = (uint32_t)ta;
+// Per-axis distances from a position f inside the home cell to the nearest
+// and to the farthest position of the cell at offset o along that axis.
+__device__ __forceinline__ uint32_t axis_gap(int o, uint32_t f, uint32_t F) {
+    if (o > 0) return ((uint32_t)o << F) - f;
+    if (o < 0) return f + (((uint32_t)(-o) - 1u) << F) + 1u;
+    return 0u;
+}
+__device__ __forceinline__ uint32_t axis_far(int o, uint32_t f, uint32_t F) {
+    const uint32_t e = 1u << F;
+    if (o > 0) return (((uint32_t)o + 1u) << F) - 1u - f;
+    if (o < 0) return f + ((uint32_t)(-o) << F);
+    return max(f, e - 1u - f);
+}
+
+// floor(sqrt(v)) for v < 2^62.
+__device__ __forceinline__ uint32_t isqrt64(uint64_t v) {
+    uint64_t x = (uint64_t)__builtin_sqrt((double)v);
+    if (x * x > v) --x;
+    if (x * x > v) --x;
+    if ((x + 1) * (x + 1) <= v) ++x;
+    return (uint32_t)x;
+}
+
+// Turn an unwrapped x-run [a, b] of row `base` (and its wholly-inside part
+// [ia, ib], empty when ia > ib) into object ranges.  On a cyclic axis the
+// run (shorter than the axis) may cross the world edge once: it is then two
+// pieces and is tested whole; on a clipped axis it is clamped to the region.
+__device__ __forceinline__ RowRef row_ranges(const LatArgs& L, uint32_t base, int a, int b, int ia, int ib) {
+    RowRef r = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    const int Lx = 1 << L.lg[0];
+    int p0, p1, p2, p3;
+    bool has_int = ia <= ib, wrap = false;
+    if (L.cyc & 1u) {
+        if (a < 0 || b >= Lx) {
+            wrap = true;
+            has_int = false;
+            if (a < 0) {
+                p0 = 0;
+                p1 = b + 1;
+                p2 = a + Lx;
+                p3 = Lx;
+            } else {
+                p0 = a;
+                p1 = Lx;
+                p2 = 0;
+                p3 = b - Lx + 1;
+            }
+        }
+    } else {
+        a = max(a, 0);
+        b = min(b, Lx - 1);
+        if (a > b) return r;
+        ia = max(ia, a);
+        ib = min(ib, b);
+        has_int = has_int && ia <= ib;
+    }
+    if (!wrap) {
+        ia = max(ia, a);
+        ib = min(ib, b);
+        has_int = has_int && ia <= ib;
+        p0 = a;
+        p1 = has_int ? ia : a;
+        p2 = has_int ? ib + 1 : a;
+        p3 = b + 1;
+    }
+    const uint32_t v0 = L.cs[base + p0];
+    const uint32_t v3 = L.cs[base + p3];
+    uint32_t v1 = v0, v2 = v0;
+    if (p1 != p0) v1 = L.cs[base + p1];
+    if (p2 != p0) v2 = L.cs[base + p2];
+    r.st0 = v0;
+    r.cnt0 = v1 - v0;
+    r.st1 = v2;
+    r.cnt1 = v3 - v2;
+    if (has_int) {
+        r.ist = v1;
+        r.icnt = v2 - v1;
+    }
+    r.kept = (uint32_t)(wrap ? (p1 - p0) + (p3 - p2) : (p3 - p0));
+    return r;
+}
+
+// Row (oy, oz) of the sphere table: the cells it meets are those whose
+// x-gap satisfies gx^2 <= bound^2 - gy^2 - gz^2 -- the exact test of Eq. 1
+// solved for x, so one contiguous run; the wholly-inside cells solve the
+// same with the far distances (Section III.A, last paragraph).
+template <bool INTERIOR>
+__device__ __forceinline__ RowRef sphere_row(const LatArgs& L, const Query& s, uint32_t w, bool has, uint64_t bound2) {
+    const RowRef none = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    const int oy = ((int)(w << 16)) >> 16, oz = ((int)w) >> 16;
+    int ty = (int)s.c[1] + oy, tz = (int)s.c[2] + oz;
+    const int Ly = 1 << L.lg[1], Lz = 1 << L.lg[2];
+    bool in = has;
+    if (L.cyc & 2u)
+        ty &= Ly - 1;
+    else
+        in = in && (uint32_t)ty < (uint32_t)Ly;
+    if (L.cyc & 4u)
+        tz &= Lz - 1;
+    else
+        in = in && (uint32_t)tz < (uint32_t)Lz;
+    const uint64_t gyz = sq(axis_gap(oy, s.f[1], L.F)) + sq(axis_gap(oz, s.f[2], L.F));
+    if (!in || gyz > bound2) return none;
+    const uint32_t X = isqrt64(bound2 - gyz);
+    const uint32_t fx = s.f[0];
+    const int npos = (int)((X + fx) >> L.F);
+    const int nneg = X >= fx + 1u ? (int)((X - fx - 1u) >> L.F) + 1 : 0;
+    int ia = 1, ib = 0;
+    if (INTERIOR) {
+        const uint64_t hyz = sq(axis_far(oy, s.f[1], L.F)) + sq(axis_far(oz, s.f[2], L.F));
+        if (hyz <= s.r2) {
+            const uint32_t Xi = isqrt64(s.r2 - hyz);
+            if (Xi >= fx && Xi + fx + 1u >= (1u << L.F)) {
+                ib = (int)s.c[0] + (int)((Xi + fx + 1u) >> L.F) - 1;
+                ia = (int)s.c[0] - (int)((Xi - fx) >> L.F);
+            }
         }
     }
-    c.kept = in && mind2 <= bound2;
-    c.interior = maxd2 <= s.r2;
-    c.cell = c.kept ? pack_cell(L, t[0], t[1], t[2]) : 0u;
-    return c;
+    const uint32_t base = ((uint32_t)tz << (L.lg[0] + L.lg[1])) | ((uint32_t)ty << L.lg[0]);
+    return row_ranges(L, base, (int)s.c[0] - nneg, (int)s.c[0] + npos, ia, ib);
 }
 
-__device__ __forceinline__ CellRef cube_entry(const LatArgs& L, const QState& s, uint32_t e) {
-    CellRef c;
-    uint32_t iz = small_div(e, s.nn[0] * s.nn[1], s.inv_nxy);
-    uint32_t rem = e - iz * s.nn[0] * s.nn[1];
-    uint32_t iy = small_div(rem, s.nn[0], s.inv_nx);
-    uint32_t ix = rem - iy * s.nn[0];
-    uint32_t i3[3] = {ix, iy, iz};
-    uint32_t t[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        uint32_t ta = (uint32_t)(s.lo[a] + (int32_t)i3[a]);
-        if ((L.cyc >> a) & 1u) ta &= (1u << L.lg[a]) - 1u;
-        t[a] = ta;
-    }
-    c.kept = true;
-    c.interior = false;
-    c.cell = pack_cell(L, t[0], t[1], t[2]);
-    return c;
+// Row e of the bounding cube (no test: the bin-lattice scans every cell).
+__device__ __forceinline__ RowRef cube_row(const LatArgs& L, const Query& s, uint32_t e, bool has, double inv_ny) {
+    const RowRef none = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    if (!has) return none;
+    const uint32_t iz = exact_div(e, s.nn[1], inv_ny);
+    const uint32_t iy = e - iz * s.nn[1];
+    uint32_t ty = (uint32_t)(s.lo[1] + (int32_t)iy), tz = (uint32_t)(s.lo[2] + (int32_t)iz);
+    if (L.cyc & 2u) ty &= (1u << L.lg[1]) - 1u;
+    if (L.cyc & 4u) tz &= (1u << L.lg[2]) - 1u;
+    const uint32_t base = (tz << (L.lg[0] + L.lg[1])) | (ty << L.lg[0]);
+    return row_ranges(L, base, s.lo[0], s.lo[0] + (int)s.nn[0] - 1, 1, 0);
 }
 
-// Minimum-image squared distance between a stored object and the centre.
+// Minimum-image squared distance of an object to the centre: on a cyclic
+// axis ((p - q + W/2) mod W) - W/2; on a clipped axis plain p - q (both below
+// 2^30, so the difference fits an int).
 struct AxisWrap {
     uint32_t half[3];
     uint32_t mask[3];
 };
 
-__device__ __forceinline__ uint64_t obj_dist2(const LatArgs& L, const AxisWrap& w, const QState& s, uint32_t p) {
-    uint32_t pv[3] = {L.xs[p], L.ys[p], L.zs[p]};
-    uint64_t d2 = 0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        int32_t dd = (int32_t)(((pv[a] - s.q[a]) + w.half[a]) & w.mask[a]) - (int32_t)w.half[a];
-        uint32_t ad = (uint32_t)(dd < 0 ? -dd : dd);
-        d2 += sq(ad);
-    }
-    return d2;
-}
-
-// Per-wave LDS layout of the write pass.
-struct WaveLds {
-    uint64_t* td;
-    uint64_t* ud;
-    uint64_t* bd;
-    uint32_t* ti;
-    uint32_t* ui;
-    uint32_t* bi;
-};
-
-__host__ __device__ constexpr size_t wave_lds_bytes(uint32_t cap) { return (size_t)cap * 24 + 64 * 12; }
-
-__device__ __forceinline__ WaveLds wave_lds(char* base, uint32_t cap) {
-    WaveLds w;
-    w.td = (uint64_t*)base;
-    w.ud = w.td + cap;
-    w.bd = w.ud + cap;
-    w.ti = (uint32_t*)(w.bd + 64);
-    w.ui = w.ti + cap;
-    w.bi = w.ui + cap;
-    return w;
-}
-
-// Candidate visitor modes.
-enum { V_COUNT = 0, V_APPEND = 1, V_TOPM = 2 };
-
-struct Walk {
-    // pass-0 accumulators
-    uint32_t hits;        // uniform
-    uint32_t interior;    // per lane
-    uint32_t kept;        // per lane (stats)
-    uint32_t cand;        // uniform (stats)
-    uint32_t walked;      // uniform (stats)
-    bool stop;            // uniform: K-NN count reached K
-    // append mode
-    uint32_t n;           // uniform: collected so far
-    // top-M mode
-    uint32_t m, M;        // uniform
-    uint64_t bd;          // uniform bound (d2, id) once m == M
-    uint32_t bi;
-    bool has_lower;
-    uint64_t ld;
-    uint32_t li;
-};
-
-// Visit the objects of the cells held by the lanes (one cell range per lane).
-template <int MODE>
-__device__ __forceinline__ void visit_candidates(const LatArgs& L, const AxisWrap& aw, const QState& s,
-                                                 uint32_t start, uint32_t cnt, Walk& wk, WaveLds& lds,
-                                                 uint32_t cap) {
-    const uint32_t lane = lane_id();
-    uint32_t incl = wave_incl_scan(cnt);
-    uint32_t total = lane_val(incl, 63);
-    wk.cand += total;
-    uint32_t smx = start - (incl - cnt);
-    for (uint32_t cb = 0; cb < total; cb += 64) {
-        uint32_t g = cb + lane;
-        // owner lane: number of lanes whose inclusive count is <= g
-        uint32_t pos = 0;
-#pragma unroll
-        for (uint32_t st = 32; st >= 1; st >>= 1) {
-            uint32_t v = bperm(incl, pos + st - 1);
-            if (v <= g) pos += st;
-        }
-        uint32_t p = bperm(smx, pos) + g;
-        bool act = g < total;
-        uint64_t d2 = kMaxD2;
-        if (act) d2 = obj_dist2(L, aw, s, p);
-        if (MODE == V_COUNT) {
-            bool hit = act && d2 <= s.r2 && p != s.self;
-            uint64_t hm = __ballot(hit);
-            wk.hits += (uint32_t)__popcll(hm);
-            if (s.knn && wk.hits >= s.k) {
-                wk.stop = true;
-                return;
-            }
-        } else if (MODE == V_APPEND) {
-            bool hit = act && d2 <= s.r2 && p != s.self;
-            uint64_t hm = __ballot(hit);
-            if (hit) {
-                uint32_t slot = wk.n + lanes_below(hm);
-                if (slot < cap) {
-                    lds.td[slot] = d2;
-                    lds.ti[slot] = L.ids[p];
-                }
-            }
-            wk.n += (uint32_t)__popcll(hm);
-        } else {
-            bool c = act && d2 <= s.r2 && p != s.self;
-            uint32_t id = kMaxId;
-            if (c) {
-                id = L.ids[p];
-                if (wk.has_lower) c = key_less(wk.ld, wk.li, d2, id);
-                if (c && wk.m == wk.M) c = key_less(d2, id, wk.bd, wk.bi);
-            }
-            uint64_t bm = __ballot(c);
-            if (bm == 0) continue;
-            uint32_t nb = (uint32_t)__popcll(bm);
-            uint64_t cd = c ? d2 : kMaxD2;
-            uint32_t ci = c ? id : kMaxId;
-            wave_sort64(cd, ci);
-            lds.bd[lane] = cd;
-            lds.bi[lane] = ci;
-            wave_sync();
-            const uint32_t m = wk.m;
-            const uint32_t nm = min(wk.M, m + nb);
-            for (uint32_t t = lane; t < m; t += 64) {
-                uint64_t xd = lds.td[t];
-                uint32_t xi = lds.ti[t];
-                uint32_t lo = 0, hi = nb;
-                while (lo < hi) {
-                    uint32_t mid = (lo + hi) >> 1;
-                    if (key_less(lds.bd[mid], lds.bi[mid], xd, xi))
-                        lo = mid + 1;
-                    else
-                        hi = mid;
-                }
-                uint32_t dst = t + lo;
-                if (dst < nm) {
-                    lds.ud[dst] = xd;
-                    lds.ui[dst] = xi;
-                }
-            }
-            if (lane < nb) {
-                uint32_t lo = 0, hi = m;
-                while (lo < hi) {
-                    uint32_t mid = (lo + hi) >> 1;
-                    if (key_less(lds.td[mid], lds.ti[mid], cd, ci))
-                        lo = mid + 1;
-                    else
-                        hi = mid;
-                }
-                uint32_t dst = lane + lo;
-                if (dst < nm) {
-                    lds.ud[dst] = cd;
-                    lds.ui[dst] = ci;
-                }
-            }
-            wave_sync();
-            uint64_t* sd = lds.td;
-            lds.td = lds.ud;
-            lds.ud = sd;
-            uint32_t* si = lds.ti;
-            lds.ti = lds.ui;
-            lds.ui = si;
-            wk.m = nm;
-            if (nm == wk.M) {
-                wk.bd = uni64(lds.td[nm - 1]);
-                wk.bi = uni(lds.ti[nm - 1]);
-            }
-        }
-    }
-}
-
-// Walk the query's cell list (outside cell first, then table entries or cube
-// cells) and feed the candidates to the visitor.
-template <int MODE>
-__device__ void walk(const LatArgs& L, const TabArgs& T, const uint32_t* tab_lds, const AxisWrap& aw,
-                     const QState& s, Walk& wk, WaveLds& lds, uint32_t cap, bool use_interior) {
-    const uint32_t lane = lane_id();
-    if (s.outside) {
-        uint32_t st = 0, cnt = 0;
-        if (lane == 0) {
-            st = L.cs[L.ncells];
-            cnt = L.cs[L.ncells + 1] - st;
-        }
-        visit_candidates<MODE>(L, aw, s, st, cnt, wk, lds, cap);
-        if (wk.stop) return;
-    }
-    const uint32_t nent = s.sphere ? s.tend : s.ncube;
-    for (uint32_t base = 0; base < nent; base += 64) {
-        uint64_t bound2 = s.r2;
-        if (MODE == V_TOPM && wk.m == wk.M) {
-            bound2 = wk.bd;
-            // entries are sorted by key: none further can hold a closer object
-            if (s.sphere && uni64((uint64_t)T.key[s.tb + base]) > bound2) break;
-        }
-        uint32_t e = base + lane;
-        CellRef c;
-        c.kept = false;
-        c.interior = false;
-        c.cell = 0;
-        if (e < nent) c = s.sphere ? sphere_entry(L, T, tab_lds, s, e, bound2) : cube_entry(L, s, e);
-        wk.walked += min(64u, nent - base);
-        uint32_t st = 0, cnt = 0;
-        if (c.kept) {
-            st = L.cs[c.cell];
-            cnt = L.cs[c.cell + 1] - st;
-            wk.kept += 1;
-        }
-        if (use_interior && c.kept && c.interior && s.sphere) {
-            wk.interior += cnt;
-            // the query's own object is inside its own (interior) cell only
-            // when that cell is the home cell; exclusion handled by caller
-            cnt = 0;
-        }
-        visit_candidates<MODE>(L, aw, s, st, cnt, wk, lds, cap);
-        if (wk.stop) return;
-    }
-}
-
 __device__ __forceinline__ AxisWrap axis_wrap(const LatArgs& L) {
     AxisWrap w;
     for (int a = 0; a < 3; ++a) {
         if ((L.cyc >> a) & 1u) {
-            uint32_t W = 1u << (L.lg[a] + L.F);
+            const uint32_t W = 1u << (L.lg[a] + L.F);
             w.half[a] = W >> 1;
             w.mask[a] = W - 1u;
         } else {
@@ -522,247 +466,521 @@ __device__ __forceinline__ AxisWrap axis_wrap(const LatArgs& L) {
     return w;
 }
 
-// Pass 0: row sizes.
-__device__ void count_query(const LatArgs& L, const TabArgs& T, const uint32_t* tab_lds, const QArgs& A,
-                            uint32_t qi) {
-    QState s;
-    setup_query(L, T, A, qi, s);
-    const AxisWrap aw = axis_wrap(L);
-    Walk wk = {};
-    WaveLds lds = {};
-    uint32_t total = 0;
-    if (s.valid) {
-        walk<V_COUNT>(L, T, tab_lds, aw, s, wk, lds, 0, !s.knn);
-        total = wk.hits + wave_sum(wk.interior);
-        // interior cells were counted whole, including the query's own object
-        if (!s.knn && s.self != kMaxId) {
-            // the self object is in the home cell; if that cell was counted as
-            // interior it was not excluded by the candidate test
-            bool home_interior = false;
-            if (s.sphere) {
-                uint32_t e = L.F;
-                uint64_t mx = 0;
-                for (int a = 0; a < 3; ++a) {
-                    uint32_t f = s.f[a];
-                    uint32_t g = max(f, (1u << e) - 1u - f);
-                    mx += sq(g);
-                }
-                home_interior = mx <= s.r2;
-            }
-            if (home_interior) total -= 1;
-        }
-        if (s.knn && total > s.k) total = s.k;
+__device__ __forceinline__ uint64_t obj_dist2(const AxisWrap& w, const Query& s, const uint4& P) {
+    const uint32_t pv[3] = {P.x, P.y, P.z};
+    uint64_t d2 = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int32_t dd = (int32_t)(((pv[a] - s.q[a]) + w.half[a]) & w.mask[a]) - (int32_t)w.half[a];
+        d2 += sq((uint32_t)(dd < 0 ? -dd : dd));
     }
-    if (lane_id() == 0) {
-        A.row_ptr[s.row] = (int64_t)total;
-        if (A.stats) {
-            uint32_t* st = A.stats + 4 * (size_t)s.row;
-            st[0] = wk.walked;
-            st[3] = s.ncube;
-        }
-    }
-    if (A.stats) {
-        uint32_t kept = wave_sum(wk.kept);
-        if (lane_id() == 0) {
-            uint32_t* st = A.stats + 4 * (size_t)s.row;
-            st[1] = kept;
-            st[2] = wk.cand;
-        }
-    }
+    return d2;
 }
 
-// Write `n` sorted (d2, id) pairs from LDS td/ti to the row at `dst`.
-__device__ __forceinline__ void emit(const QArgs& A, const WaveLds& lds, uint32_t n, int64_t dst) {
-    for (uint32_t t = lane_id(); t < n; t += 64) {
-        A.out_ids[dst + t] = lds.ti[t];
-        if (A.out_d2) A.out_d2[dst + t] = (int64_t)lds.td[t];
-    }
-}
+// ---------------------------------------------------------------------------
+// Candidate distribution: each lane holds two object ranges [st0, st0+cnt0)
+// and [st1, st1+cnt1); every object becomes one slot, 64 slots per step.
+// visit(active, position, record) returns true to stop (uniformly).
 
-// Pass 1: row contents.
-__device__ void write_query(const LatArgs& L, const TabArgs& T, const uint32_t* tab_lds, const QArgs& A,
-                            uint32_t qi, char* lds_base) {
-    QState s;
-    setup_query(L, T, A, qi, s);
-    const int64_t rb = A.row_ptr[s.row];
-    const uint32_t rowlen = (uint32_t)(A.row_ptr[s.row + 1] - rb);
-    if (!s.valid || rowlen == 0) return;
-    const AxisWrap aw = axis_wrap(L);
-    const uint32_t cap = A.sort_cap;
-    WaveLds lds = wave_lds(lds_base, cap);
+template <typename V>
+__device__ __forceinline__ bool for_candidates(const LatArgs& L, uint32_t st0, uint32_t cnt0, uint32_t st1,
+                                               uint32_t cnt1, uint32_t* own, uint32_t& total_out, V&& visit) {
     const uint32_t lane = lane_id();
-    if (!s.knn && rowlen <= cap) {
-        Walk wk = {};
-        walk<V_APPEND>(L, T, tab_lds, aw, s, wk, lds, cap, false);
+    const uint32_t tl = cnt0 + cnt1;
+    const uint32_t incl = scan_add(tl);
+    const uint32_t total = lane_val(incl, 63);
+    total_out += total;
+    if (total == 0) return false;
+    const uint32_t excl = incl - tl;
+    const uint32_t smx0 = st0 - excl;
+    const uint32_t bnd = excl + cnt0;
+    const uint32_t smx1 = st1 - bnd;
+    for (uint32_t cb = 0; cb < total; cb += 64) {
+        // mark where each lane's range starts inside this step's 64 slots,
+        // then a max-scan hands every slot to the lane that owns it
+        own[lane] = 0;
         wave_sync();
-        const uint32_t n = min(wk.n, rowlen);
-        if (n <= 64) {
-            // rank sort: lane i holds pair i, its rank is the number of smaller pairs
-            uint64_t d = kMaxD2;
-            uint32_t id = kMaxId;
-            if (lane < n) {
-                d = lds.td[lane];
-                id = lds.ti[lane];
-            }
-            uint32_t rank = 0;
-            for (uint32_t j = 0; j < n; ++j) {
-                uint64_t dj = ((uint64_t)lane_val((uint32_t)(d >> 32), j) << 32) | lane_val((uint32_t)d, j);
-                uint32_t ij = lane_val(id, j);
-                rank += key_less(dj, ij, d, id) ? 1u : 0u;
-            }
-            if (lane < n) {
-                A.out_ids[rb + rank] = id;
-                if (A.out_d2) A.out_d2[rb + rank] = (int64_t)d;
-            }
+        if (tl > 0 && excl < cb + 64 && incl > cb) own[excl > cb ? excl - cb : 0] = lane + 1;
+        wave_sync();
+        const uint32_t o = scan_max(own[lane]) - 1u;
+        const uint32_t g = cb + lane;
+        const uint32_t b = bperm(bnd, o);
+        const uint32_t p0 = bperm(smx0, o) + g;
+        const uint32_t p1 = bperm(smx1, o) + g;
+        const uint32_t p = g < b ? p0 : p1;
+        const bool act = g < total;
+        uint4 P = make_uint4(0u, 0u, 0u, kMaxId);
+        if (act) P = L.pts[p];
+        if (visit(act, p, P)) return true;
+    }
+    return false;
+}
+
+// Walk the query's rows: the outside cell first (when objects there may be
+// within r), then sphere-table rows or bounding-cube rows, 64 per step.
+// on_step(row) returns true to stop.  bound2_now() is re-read before every
+// step (top-M shrinks it); KEY_STOP enables the cut-off on sorted row keys.
+template <int METHOD, bool TLDS, bool INTERIOR, bool KEY_STOP, typename B, typename S>
+__device__ __forceinline__ void walk(const LatArgs& L, const TabArgs& T, const uint32_t* tab_lds, const Query& s,
+                                     uint32_t& walked, B&& bound2_now, S&& on_step) {
+    const uint32_t lane = lane_id();
+    if (s.flags & F_OUTSIDE) {
+        // every object outside the region lives in one cell (Section II.B)
+        RowRef r = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
+        if (lane == 0) {
+            r.st0 = L.cs[L.ncells];
+            r.cnt0 = L.cs[L.ncells + 1] - r.st0;
+        }
+        if (on_step(r)) return;
+    }
+    const bool sphere = METHOD == kSphere && (s.flags & F_SPHERE);
+    const uint32_t nent = sphere ? s.tend : s.nn[1] * s.nn[2];
+    const uint32_t* rows = TLDS ? tab_lds + s.tb : T.rows + s.tb;
+    uint32_t nxt = 0;
+    if (sphere && lane < nent) nxt = rows[lane];
+    const double inv_ny = (!sphere && s.nn[1]) ? 1.0 / (double)s.nn[1] : 0.0;
+    for (uint32_t base = 0; base < nent; base += 64) {
+        const uint32_t idx = base + lane;
+        RowRef r;
+        if (sphere) {
+            const uint64_t bound2 = bound2_now();
+            // rows are sorted by key: once the key exceeds the bound no
+            // further row can hold anything closer
+            if (KEY_STOP && uni64((uint64_t)T.rkey[s.tb + base]) > bound2) break;
+            const uint32_t w = nxt;
+            if (idx + 64 < nent) nxt = rows[idx + 64];
+            r = sphere_row<INTERIOR>(L, s, w, idx < nent, bound2);
         } else {
-            uint32_t np = 64;
-            while (np < n) np <<= 1;
-            for (uint32_t t = n + lane; t < np; t += 64) {
-                lds.td[t] = kMaxD2;
-                lds.ti[t] = kMaxId;
-            }
-            wave_sync();
-            for (uint32_t k = 2; k <= np; k <<= 1) {
-                for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-                    for (uint32_t t = lane; t < (np >> 1); t += 64) {
-                        uint32_t i = ((t & ~(j - 1u)) << 1) | (t & (j - 1u));
-                        uint32_t pj = i + j;
-                        uint64_t di = lds.td[i], dp = lds.td[pj];
-                        uint32_t ii = lds.ti[i], ip = lds.ti[pj];
-                        bool up = (i & k) == 0;
-                        bool sw = up ? key_less(dp, ip, di, ii) : key_less(di, ii, dp, ip);
-                        if (sw) {
-                            lds.td[i] = dp;
-                            lds.td[pj] = di;
-                            lds.ti[i] = ip;
-                            lds.ti[pj] = ii;
-                        }
-                    }
-                    wave_sync();
-                }
-            }
-            emit(A, lds, n, rb);
+            r = cube_row(L, s, idx, idx < nent, inv_ny);
         }
-        return;
-    }
-    // top-M windows: K-NN rows, and radius rows longer than the LDS buffer
-    Walk wk = {};
-    uint32_t written = 0;
-    while (written < rowlen) {
-        wk.M = min(cap, rowlen - written);
-        wk.m = 0;
-        wk.bd = kMaxD2;
-        wk.bi = kMaxId;
-        walk<V_TOPM>(L, T, tab_lds, aw, s, wk, lds, cap, false);
-        wave_sync();
-        const uint32_t got = min(wk.m, wk.M);
-        emit(A, lds, got, rb + written);
-        if (got == 0) break;
-        wk.has_lower = true;
-        wk.ld = uni64(lds.td[got - 1]);
-        wk.li = uni(lds.ti[got - 1]);
-        written += got;
-        wave_sync();
+        walked += min(64u, nent - base);
+        if (on_step(r)) return;
     }
 }
 
-template <int PASS>
-__global__ __launch_bounds__(256) void query_kernel(LatArgs L, TabArgs T, QArgs A) {
-    extern __shared__ __align__(16) char smem[];
-    const uint32_t wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const uint32_t* tab_lds = nullptr;
-    size_t tab_bytes = 0;
-    if (T.lds) {
-        // the whole offset table, shared by the block's waves
-        uint32_t* t = (uint32_t*)smem;
-        for (uint32_t i = threadIdx.x; i < T.total; i += blockDim.x) t[i] = T.off[i];
-        __syncthreads();
-        tab_lds = t;
-        tab_bytes = ((size_t)T.total * 4 + 15) & ~(size_t)15;
-    }
-    char* lds_base = smem + tab_bytes + (PASS == 1 ? (size_t)wave * wave_lds_bytes(A.sort_cap) : 0);
-    if (PASS == 1) {
-        int64_t tot = A.row_ptr[A.Q];
-        if (tot > A.capacity) {
-            if (threadIdx.x == 0) atomicOr(L.status, SPHIDX_FLAG_CAPACITY);
-            return;
-        }
-    }
+// ---------------------------------------------------------------------------
+// Query scheduling: plain (each wave owns a fixed slice of `tile` queries,
+// XCD-aware block order) or persistent (per-XCD work queues).
+
+template <typename F>
+__device__ __forceinline__ void for_each_query(uint32_t Q, const QArgs& A, uint32_t* queues, F&& f) {
+    if (Q == 0) return;
     const uint32_t lane = lane_id();
+    const uint32_t wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     if (!A.persistent) {
-        // XCD-aware order: consecutive block ids go round-robin over the 8
-        // XCDs; give each XCD a contiguous range of query slices instead
+        // consecutive block ids go round-robin over the 8 XCDs: give each XCD
+        // a contiguous range of slices so neighbouring queries share its L2
         const uint32_t G = gridDim.x, b = blockIdx.x;
         const uint32_t full = G / SPHIDX_NQUEUE, rem = G % SPHIDX_NQUEUE;
         const uint32_t x = b % SPHIDX_NQUEUE, i = b / SPHIDX_NQUEUE;
         const uint32_t lb = x * full + min(x, rem) + i;
         const uint64_t q0 = ((uint64_t)lb * nw + wave) * A.tile;
         for (uint32_t t = 0; t < A.tile; ++t) {
-            uint64_t qi = q0 + t;
-            if (qi >= A.Q) break;
-            if (PASS == 0)
-                count_query(L, T, tab_lds, A, (uint32_t)qi);
-            else
-                write_query(L, T, tab_lds, A, (uint32_t)qi, lds_base);
+            const uint64_t qi = q0 + t;
+            if (qi >= Q) break;
+            f((uint32_t)qi);
         }
-    } else {
-        // persistent: one work queue per XCD over a contiguous range of the
-        // queries; drain the own queue, then take from the others
-        uint32_t x = blockIdx.x % SPHIDX_NQUEUE;
-        uint32_t misses = 0;
-        while (misses < SPHIDX_NQUEUE) {
-            const uint32_t qs = (uint32_t)(((uint64_t)x * A.Q) / SPHIDX_NQUEUE);
-            const uint32_t qe = (uint32_t)(((uint64_t)(x + 1) * A.Q) / SPHIDX_NQUEUE);
-            uint32_t t = 0;
-            if (lane == 0) t = atomicAdd(&A.queues[x], A.tile);
-            t = uni(t);
-            if ((uint64_t)qs + t >= qe) {
-                x = (x + 1) % SPHIDX_NQUEUE;
-                ++misses;
-                continue;
-            }
-            misses = 0;
-            const uint32_t end = (uint32_t)min((uint64_t)qe, (uint64_t)qs + t + A.tile);
-            for (uint32_t qi = qs + t; qi < end; ++qi) {
-                if (PASS == 0)
-                    count_query(L, T, tab_lds, A, qi);
-                else
-                    write_query(L, T, tab_lds, A, qi, lds_base);
-            }
-        }
+        return;
     }
+    // one queue per XCD over a contiguous range of queries: drain the own
+    // queue, then take from the others; a queue found empty stays empty, so
+    // every wave stops after one empty round
+    uint32_t x = blockIdx.x % SPHIDX_NQUEUE;
+    uint32_t misses = 0;
+    while (misses < SPHIDX_NQUEUE) {
+        const uint32_t qs = (uint32_t)(((uint64_t)x * Q) / SPHIDX_NQUEUE);
+        const uint32_t qe = (uint32_t)(((uint64_t)(x + 1) * Q) / SPHIDX_NQUEUE);
+        uint32_t* qc = queues + x * SPHIDX_QSTRIDE;
+        uint32_t t = 0;
+        if (lane == 0) {
+            // an exhausted queue is skipped with a plain read, not an atomic
+            t = __hip_atomic_load(qc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((uint64_t)qs + t < qe) t = atomicAdd(qc, A.tile);
+        }
+        t = uni(t);
+        if ((uint64_t)qs + t >= qe) {
+            x = (x + 1) % SPHIDX_NQUEUE;
+            ++misses;
+            continue;
+        }
+        misses = 0;
+        const uint32_t end = (uint32_t)min((uint64_t)qe, (uint64_t)qs + t + A.tile);
+        for (uint32_t qi = qs + t; qi < end; ++qi) f(qi);
+    }
+}
+
+// Stage the whole row table in LDS (shared by the block's waves).
+template <bool TLDS>
+__device__ __forceinline__ const uint32_t* stage_table(const TabArgs& T, char* smem) {
+    if (!TLDS) return nullptr;
+    uint32_t* t = (uint32_t*)smem;
+    for (uint32_t i = threadIdx.x; i < T.total; i += blockDim.x) t[i] = T.rows[i];
+    __syncthreads();
+    return t;
+}
+
+template <bool TLDS>
+__device__ __forceinline__ size_t table_lds_bytes(const TabArgs& T) {
+    return TLDS ? (((size_t)T.total * 4 + 15) & ~(size_t)15) : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Pass 0: row sizes
+
+template <int METHOD, bool TLDS>
+__global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs A) {
+    extern __shared__ __align__(16) char smem[];
+    const uint32_t* tab_lds = stage_table<TLDS>(T, smem);
+    uint32_t* own = (uint32_t*)(smem + table_lds_bytes<TLDS>(T)) + (threadIdx.x >> 6) * 64;
+    const AxisWrap aw = axis_wrap(L);
+    const uint32_t lane = lane_id();
+    for_each_query(A.Q, A, A.queues, [&](uint32_t qi) {
+        const Query s = load_query(L, A, qi);
+        const bool knn = s.flags & F_KNN;
+        uint32_t hits = 0, inner = 0, kept = 0, cand = 0, walked = 0;
+        bool self_inner = false;
+        auto visit = [&](bool act, uint32_t p, const uint4& P) -> bool {
+            const bool hit = act && obj_dist2(aw, s, P) <= s.r2 && p != s.self;
+            hits += (uint32_t)__popcll(__ballot(hit));
+            return knn && hits >= s.k;
+        };
+        auto on_row = [&](const RowRef& r) -> bool {
+            kept += r.kept;
+            // cells wholly inside: counted without reading objects; note when
+            // the excluded own object was among them
+            if (r.icnt && s.self - r.ist < r.icnt) self_inner = true;
+            inner += r.icnt;
+            return for_candidates(L, r.st0, r.cnt0, r.st1, r.cnt1, own, cand, visit);
+        };
+        if (s.flags & F_VALID) {
+            if (knn || !A.interior)
+                walk<METHOD, TLDS, false, false>(L, T, tab_lds, s, walked, [&]() { return s.r2; }, on_row);
+            else
+                walk<METHOD, TLDS, true, false>(L, T, tab_lds, s, walked, [&]() { return s.r2; }, on_row);
+            uint32_t total = hits + wave_sum(inner);
+            if (__ballot(self_inner) != 0) total -= 1;
+            if (knn && total > s.k) total = s.k;
+            hits = total;
+        }
+        if (lane == 0) A.row_ptr[s.row] = (int64_t)hits;
+        if (A.stats) {
+            const uint32_t kept_all = wave_sum(kept);
+            const uint32_t ncube = (s.flags & F_VALID) ? cube_cells(L, s) : 0u;
+            if (lane == 0) {
+                uint32_t* stp = A.stats + 4 * (size_t)s.row;
+                stp[0] = walked;
+                stp[1] = kept_all;
+                stp[2] = cand;
+                stp[3] = ncube;
+            }
+        }
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Pass 1, radius rows that fit the LDS buffer: collect, sort, store.
+
+__device__ __forceinline__ void store_sorted(const QArgs& A, const uint64_t* td, const uint32_t* ti, uint32_t n,
+                                             int64_t dst) {
+    for (uint32_t t = lane_id(); t < n; t += 64) {
+        A.out_ids[dst + t] = ti[t];
+        if (A.out_d2) A.out_d2[dst + t] = (int64_t)td[t];
+    }
+}
+
+template <int METHOD, bool TLDS>
+__global__ __launch_bounds__(256) void write_kernel(LatArgs L, TabArgs T, QArgs A) {
+    extern __shared__ __align__(16) char smem[];
+    const uint32_t* tab_lds = stage_table<TLDS>(T, smem);
+    const uint32_t wave = threadIdx.x >> 6;
+    const uint32_t cap = A.sort_cap;
+    char* wb = smem + table_lds_bytes<TLDS>(T) + (size_t)wave * ((size_t)cap * 12 + 256);
+    uint64_t* td = (uint64_t*)wb;
+    uint32_t* ti = (uint32_t*)(td + cap);
+    uint32_t* own = ti + cap;
+    if (A.row_ptr[A.Q] > A.capacity) {
+        if (threadIdx.x == 0) atomicOr(L.status, SPHIDX_FLAG_CAPACITY);
+        return;
+    }
+    const AxisWrap aw = axis_wrap(L);
+    const uint32_t lane = lane_id();
+    for_each_query(A.Q, A, A.queues + SPHIDX_NQUEUE * SPHIDX_QSTRIDE, [&](uint32_t qi) {
+        const Query s = load_query(L, A, qi);
+        const int64_t rb = A.row_ptr[s.row];
+        const uint32_t rowlen = (uint32_t)(A.row_ptr[s.row + 1] - rb);
+        if (rowlen == 0 || !(s.flags & F_VALID)) return;
+        if ((s.flags & F_KNN) || rowlen > cap) {
+            // handled by the top-M kernel
+            if (lane == 0) A.longq[atomicAdd(A.long_count, 1u)] = qi;
+            return;
+        }
+        uint32_t n = 0, cand = 0, walked = 0;
+        auto visit = [&](bool act, uint32_t p, const uint4& P) -> bool {
+            const uint64_t d2 = obj_dist2(aw, s, P);
+            const bool hit = act && d2 <= s.r2 && p != s.self;
+            const uint64_t hm = __ballot(hit);
+            if (hit) {
+                const uint32_t slot = n + lanes_below(hm);
+                if (slot < cap) {
+                    td[slot] = d2;
+                    ti[slot] = P.w;
+                }
+            }
+            n += (uint32_t)__popcll(hm);
+            return false;
+        };
+        walk<METHOD, TLDS, false, false>(L, T, tab_lds, s, walked, [&]() { return s.r2; },
+                                         [&](const RowRef& r) -> bool {
+            return for_candidates(L, r.st0, r.cnt0, r.st1, r.cnt1, own, cand, visit);
+        });
+        wave_sync();
+        n = min(n, rowlen);
+        if (n <= 64) {
+            // rank sort: lane i holds pair i; its rank is the number of smaller pairs
+            uint64_t d = kMaxD2;
+            uint32_t id = kMaxId;
+            if (lane < n) {
+                d = td[lane];
+                id = ti[lane];
+            }
+            uint32_t rank = 0;
+#pragma unroll 4
+            for (uint32_t j = 0; j < n; ++j) rank += key_less(td[j], ti[j], d, id) ? 1u : 0u;
+            if (lane < n) {
+                A.out_ids[rb + rank] = id;
+                if (A.out_d2) A.out_d2[rb + rank] = (int64_t)d;
+            }
+        } else {
+            uint32_t np = 128;
+            while (np < n) np <<= 1;
+            for (uint32_t t = n + lane; t < np; t += 64) {
+                td[t] = kMaxD2;
+                ti[t] = kMaxId;
+            }
+            wave_sync();
+            for (uint32_t k = 2; k <= np; k <<= 1) {
+                for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                    for (uint32_t t = lane; t < (np >> 1); t += 64) {
+                        const uint32_t i = ((t & ~(j - 1u)) << 1) | (t & (j - 1u));
+                        const uint32_t pj = i + j;
+                        const uint64_t di = td[i], dp = td[pj];
+                        const uint32_t ii = ti[i], ip = ti[pj];
+                        const bool up = (i & k) == 0;
+                        if (up ? key_less(dp, ip, di, ii) : key_less(di, ii, dp, ip)) {
+                            td[i] = dp;
+                            td[pj] = di;
+                            ti[i] = ip;
+                            ti[pj] = ii;
+                        }
+                    }
+                    wave_sync();
+                }
+            }
+            store_sorted(A, td, ti, n, rb);
+        }
+        wave_sync();
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Pass 1, K-NN rows and long radius rows: sorted top-M in LDS with the
+// shrinking bound, in windows of at most `cap` entries (each window takes
+// the M smallest pairs above the previous window's last one).
+
+template <int METHOD, bool TLDS, bool FROM_LIST>
+__global__ __launch_bounds__(256) void topm_kernel(LatArgs L, TabArgs T, QArgs A) {
+    extern __shared__ __align__(16) char smem[];
+    const uint32_t* tab_lds = stage_table<TLDS>(T, smem);
+    const uint32_t wave = threadIdx.x >> 6;
+    const uint32_t cap = A.sort_cap;
+    char* wb = smem + table_lds_bytes<TLDS>(T) + (size_t)wave * ((size_t)cap * 24 + 64 * 12 + 256);
+    uint64_t* tdA = (uint64_t*)wb;
+    uint64_t* tdB = tdA + cap;
+    uint64_t* bd = tdB + cap;
+    uint32_t* tiA = (uint32_t*)(bd + 64);
+    uint32_t* tiB = tiA + cap;
+    uint32_t* bi = tiB + cap;
+    uint32_t* own = bi + 64;
+    if (A.row_ptr[A.Q] > A.capacity) {
+        if (threadIdx.x == 0) atomicOr(L.status, SPHIDX_FLAG_CAPACITY);
+        return;
+    }
+    const AxisWrap aw = axis_wrap(L);
+    const uint32_t lane = lane_id();
+    const uint32_t nq = FROM_LIST ? uni(*A.long_count) : A.Q;
+    for_each_query(nq, A, A.queues + 2 * SPHIDX_NQUEUE * SPHIDX_QSTRIDE, [&](uint32_t ti_) {
+        const uint32_t qi = FROM_LIST ? uni(A.longq[ti_]) : ti_;
+        const Query s = load_query(L, A, qi);
+        if (!FROM_LIST && !(s.flags & F_KNN)) return;
+        const int64_t rb = A.row_ptr[s.row];
+        const uint32_t rowlen = (uint32_t)(A.row_ptr[s.row + 1] - rb);
+        if (rowlen == 0 || !(s.flags & F_VALID)) return;
+        uint64_t* td = tdA;
+        uint64_t* ud = tdB;
+        uint32_t* tix = tiA;
+        uint32_t* uix = tiB;
+        bool has_lower = false;
+        uint64_t ld = 0;
+        uint32_t li = 0;
+        uint32_t written = 0;
+        while (written < rowlen) {
+            const uint32_t M = min(cap, rowlen - written);
+            uint32_t m = 0;
+            uint64_t bdd = kMaxD2;
+            uint32_t bii = kMaxId;
+            uint32_t cand = 0, walked = 0;
+            auto visit = [&](bool act, uint32_t p, const uint4& P) -> bool {
+                const uint64_t d2 = obj_dist2(aw, s, P);
+                const uint32_t id = P.w;
+                bool cv = act && d2 <= s.r2 && p != s.self;
+                if (cv && has_lower) cv = key_less(ld, li, d2, id);
+                if (cv && m == M) cv = key_less(d2, id, bdd, bii);
+                const uint64_t bm = __ballot(cv);
+                if (bm == 0) return false;
+                const uint32_t nb = (uint32_t)__popcll(bm);
+                uint64_t cd = cv ? d2 : kMaxD2;
+                uint32_t ci = cv ? id : kMaxId;
+                wave_sort64(cd, ci);
+                bd[lane] = cd;
+                bi[lane] = ci;
+                wave_sync();
+                const uint32_t nm = min(M, m + nb);
+                // merge: an element's place = own index + elements of the
+                // other sorted list that are smaller (ids are unique)
+                for (uint32_t t = lane; t < m; t += 64) {
+                    const uint64_t xd = td[t];
+                    const uint32_t xi = tix[t];
+                    uint32_t lo = 0, hi = nb;
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (key_less(bd[mid], bi[mid], xd, xi))
+                            lo = mid + 1;
+                        else
+                            hi = mid;
+                    }
+                    if (t + lo < nm) {
+                        ud[t + lo] = xd;
+                        uix[t + lo] = xi;
+                    }
+                }
+                if (lane < nb) {
+                    uint32_t lo = 0, hi = m;
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (key_less(td[mid], tix[mid], cd, ci))
+                            lo = mid + 1;
+                        else
+                            hi = mid;
+                    }
+                    if (lane + lo < nm) {
+                        ud[lane + lo] = cd;
+                        uix[lane + lo] = ci;
+                    }
+                }
+                wave_sync();
+                uint64_t* sd = td;
+                td = ud;
+                ud = sd;
+                uint32_t* si = tix;
+                tix = uix;
+                uix = si;
+                m = nm;
+                if (m == M) {
+                    bdd = uni64(td[M - 1]);
+                    bii = uni(tix[M - 1]);
+                }
+                return false;
+            };
+            walk<METHOD, TLDS, false, true>(L, T, tab_lds, s, walked, [&]() { return m == M ? bdd : s.r2; },
+                                            [&](const RowRef& r) -> bool {
+                return for_candidates(L, r.st0, r.cnt0, r.st1, r.cnt1, own, cand, visit);
+            });
+            wave_sync();
+            const uint32_t got = min(m, M);
+            store_sorted(A, td, tix, got, rb + written);
+            if (got == 0) break;
+            has_lower = true;
+            ld = uni64(td[got - 1]);
+            li = uni(tix[got - 1]);
+            written += got;
+            wave_sync();
+        }
+    });
+}
+
+__global__ void clear_counters_kernel(uint32_t* c) {
+    for (uint32_t i = threadIdx.x; i < SPHIDX_COUNTER_WORDS; i += blockDim.x) c[i] = 0u;
+}
+
+// Kernel choice by variant: cube, sphere, sphere with the row table in LDS.
+#define SPHIDX_PICK(KERNEL, variant, ...)                                          \
+    ((variant) == 0 ? (const void*)KERNEL<kCube, false __VA_ARGS__>                \
+     : (variant) == 1 ? (const void*)KERNEL<kSphere, false __VA_ARGS__>            \
+                      : (const void*)KERNEL<kSphere, true __VA_ARGS__>)
+
+hipError_t launch_ptr(const void* fn, uint32_t nq, const QArgs& q, uint32_t waves, uint32_t bpc, size_t shmem,
+                      hipStream_t st, const LatArgs& L, const TabArgs& T) {
+    uint32_t blocks;
+    if (q.persistent) {
+        blocks = (uint32_t)device_cu_count() * bpc;
+    } else {
+        const uint64_t per = (uint64_t)waves * q.tile;
+        blocks = (uint32_t)((nq + per - 1) / per);
+        if (blocks == 0) blocks = 1;
+    }
+    LatArgs l = L;
+    TabArgs t = T;
+    QArgs a = q;
+    void* args[] = {&l, &t, &a};
+    return hipLaunchKernel(fn, dim3(blocks), dim3(waves * 64), args, shmem, st);
 }
 
 }  // namespace
 
 int device_cu_count() {
+    static int cached = 0;
+    if (cached) return cached;
     int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 256;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    cached = cus;
     return cus;
+}
+
+size_t query_lds_bytes(int pass, uint32_t cap, uint32_t waves, size_t table_bytes) {
+    size_t per = pass == 0 ? 256 : (pass == 1 ? (size_t)cap * 12 + 256 : (size_t)cap * 24 + 64 * 12 + 256);
+    return table_bytes + per * waves;
 }
 
 hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const QArgs& q,
                              uint32_t waves_per_block, uint32_t blocks_per_cu, hipStream_t st) {
-    if (q.Q == 0) return hipSuccess;
-    const uint32_t threads = waves_per_block * 64;
-    size_t shmem = 0;
-    if (T.lds) shmem += ((size_t)T.total * 4 + 15) & ~(size_t)15;
-    if (pass == 1) shmem += (size_t)waves_per_block * wave_lds_bytes(q.sort_cap);
-    uint32_t blocks;
-    if (q.persistent) {
-        blocks = (uint32_t)device_cu_count() * blocks_per_cu;
-        hipError_t e = launch_fill_u32(q.queues, 0u, SPHIDX_NQUEUE, st);
-        if (e != hipSuccess) return e;
-    } else {
-        uint64_t per_block = (uint64_t)waves_per_block * q.tile;
-        blocks = (uint32_t)((q.Q + per_block - 1) / per_block);
-    }
-    if (pass == 0)
-        hipLaunchKernelGGL(query_kernel<0>, dim3(blocks), dim3(threads), shmem, st, L, T, q);
+    const size_t tb = T.lds ? (((size_t)T.total * 4 + 15) & ~(size_t)15) : 0;
+    const int variant = !T.has ? 0 : (T.lds ? 2 : 1);
+    clear_counters_kernel<<<1, 256, 0, st>>>(q.queues);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || q.Q == 0) return e;
+    // per-query descriptors
+    if (variant == 0)
+        setup_kernel<kCube><<<(q.Q + 255) / 256, 256, 0, st>>>(L, T, q);
     else
-        hipLaunchKernelGGL(query_kernel<1>, dim3(blocks), dim3(threads), shmem, st, L, T, q);
-    return hipGetLastError();
+        setup_kernel<kSphere><<<(q.Q + 255) / 256, 256, 0, st>>>(L, T, q);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const uint32_t w = waves_per_block, b = blocks_per_cu;
+    if (pass == 0)
+        return launch_ptr(SPHIDX_PICK(count_kernel, variant), q.Q, q, w, b, query_lds_bytes(0, q.sort_cap, w, tb),
+                          st, L, T);
+    const size_t sh1 = query_lds_bytes(1, q.sort_cap, w, tb);
+    const size_t sh2 = query_lds_bytes(2, q.sort_cap, w, tb);
+    if (q.mode != SPHIDX_MODE_KNN) {
+        e = launch_ptr(SPHIDX_PICK(write_kernel, variant), q.Q, q, w, b, sh1, st, L, T);
+        if (e != hipSuccess) return e;
+        // K-NN rows of a mixed batch and long radius rows, from the list
+        QArgs ql = q;
+        ql.persistent = 1;
+        ql.tile = 1;
+        return launch_ptr(SPHIDX_PICK(topm_kernel, variant, , true), 0, ql, w, b, sh2, st, L, T);
+    }
+    return launch_ptr(SPHIDX_PICK(topm_kernel, variant, , false), q.Q, q, w, b, sh2, st, L, T);
 }
-
-size_t query_wave_lds_bytes(uint32_t cap) { return wave_lds_bytes(cap); }

@@ -17,10 +17,7 @@ struct sphidx_lattice {
     uint32_t n;       // objects of the last build
     uint32_t ncells;  // region cells; index ncells = outside cell, ncells + 1 = skipped objects
     uint32_t* cell_start;  // ncells + 3
-    uint32_t* xs;
-    uint32_t* ys;
-    uint32_t* zs;
-    uint32_t* ids;
+    uint4* pts;         // by sorted position: normalised x, y, z and the object id
     uint32_t* rank;     // per input object: its slot inside its cell (build scratch)
     uint32_t* scan_tmp; // scan partial sums
     uint32_t* status;   // device status word
@@ -32,21 +29,29 @@ struct sphidx_tables {
     uint32_t s;        // sub-cell bits per axis
     uint32_t F;        // frac bits of the lattice the tables were built for
     uint32_t rmax_fx;  // radius cap
-    uint32_t nclasses; // 2^(3s)
+    uint32_t nclasses; // 2^(3s) cell-table classes
     uint32_t rshift;   // radius-index bucket = 2^rshift units
     uint32_t nr;       // radius-index entries per class
     uint32_t max_off;  // largest |offset| component
     uint64_t total;
-    // host copies (also what save/load serialise)
-    std::vector<uint32_t> h_off;         // packed offsets, class-major, key-sorted
-    std::vector<int64_t> h_key;          // keys, same order
+    // cell table (host; what export, save and load use): packed offsets,
+    // class-major, key-sorted, with their keys
+    std::vector<uint32_t> h_off;
+    std::vector<int64_t> h_key;
     std::vector<uint32_t> h_class_start; // nclasses + 1
     std::vector<uint32_t> h_rindex;      // nclasses * nr
-    // device copies
-    uint32_t* d_off = nullptr;
-    int64_t* d_key = nullptr;
-    uint32_t* d_class_start = nullptr;
-    uint32_t* d_rindex = nullptr;
+    // row table (what the kernels walk): per (y, z) sub-cell class, the
+    // x-rows (oy, oz) of cells, sorted by the row's key
+    uint32_t nrclasses;                   // 2^(2s)
+    std::vector<uint32_t> h_rows;         // (oy & 0xffff) | (oz << 16)
+    std::vector<int64_t> h_rkey;
+    std::vector<uint32_t> h_rclass_start; // nrclasses + 1
+    std::vector<uint32_t> h_rrindex;      // nrclasses * nr
+    // device copies of the row table
+    uint32_t* d_rows = nullptr;
+    int64_t* d_rkey = nullptr;
+    uint32_t* d_rclass_start = nullptr;
+    uint32_t* d_rrindex = nullptr;
     size_t device_bytes = 0;
 };
 
@@ -60,25 +65,22 @@ struct LatArgs {
     uint32_t ncells;
     uint32_t n;
     const uint32_t* cs;   // cell_start
-    const uint32_t* xs;
-    const uint32_t* ys;
-    const uint32_t* zs;
-    const uint32_t* ids;
+    const uint4* pts;     // sorted objects {x, y, z, id}
     uint32_t* status;
 };
 
 struct TabArgs {
-    const uint32_t* off;
-    const int64_t* key;
-    const uint32_t* cstart;
-    const uint32_t* rindex;
+    const uint32_t* rows;   // packed (oy, oz), class-major, key-sorted
+    const int64_t* rkey;    // row keys, same order
+    const uint32_t* cstart; // first row of each class
+    const uint32_t* rindex; // per class and radius bucket: rows with key <= bucket^2
     uint32_t s;
     uint32_t rshift;
     uint32_t nr;
     uint32_t rmax;
-    uint32_t total;
-    uint32_t has;   // 0: no tables (cube only)
-    uint32_t lds;   // 1: stage off[] in LDS
+    uint32_t total;  // rows over all classes
+    uint32_t has;    // 0: no tables (cube only)
+    uint32_t lds;    // 1: stage the row table in LDS
 };
 
 struct QArgs {
@@ -96,15 +98,21 @@ struct QArgs {
     uint32_t* out_ids;
     int64_t* out_d2;
     int64_t capacity;
-    uint32_t* queues;   // persistent work counters (NQUEUE)
+    uint32_t* queues;   // work counters: 3 x NQUEUE, then the long-row count
+    uint32_t* long_count;
+    uint32_t* longq;    // rows handed from the write kernel to the top-M kernel
+    uint4* desc;        // per query (processing order): 4 x uint4 set up by the setup kernel
     uint32_t* stats;
     uint32_t method;
     uint32_t persistent;
     uint32_t tile;
     uint32_t sort_cap;
+    uint32_t interior;  // count pass: count wholly-inside cells without reading them
 };
 
-#define SPHIDX_NQUEUE 8  // one work queue per XCD of the MI355X
+#define SPHIDX_NQUEUE 8         // one work queue per XCD of the MI355X
+#define SPHIDX_QSTRIDE 32       // counters 128 bytes apart: one L2 line each
+#define SPHIDX_COUNTER_WORDS (3 * SPHIDX_NQUEUE * SPHIDX_QSTRIDE + SPHIDX_QSTRIDE)
 #define SPHIDX_MAX_LOG2_SUM 30
 
 // ---------------------------------------------------------------------------
@@ -121,3 +129,4 @@ hipError_t launch_move_agents(const sphidx_lattice_desc& d, uint64_t seed, uint3
                               uint32_t* y, uint32_t* z, uint32_t n, hipStream_t st);
 hipError_t launch_count_checksum(const int64_t* row_ptr, uint32_t Q, uint64_t* out, hipStream_t st);
 int device_cu_count();
+size_t query_lds_bytes(int pass, uint32_t cap, uint32_t waves, size_t table_bytes);

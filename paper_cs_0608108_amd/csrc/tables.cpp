@@ -17,6 +17,7 @@
 // number of entries with key <= (j * 2^rshift)^2: an upper bound of the
 // prefix that a single lookup returns (the paper indexes by floor(d^2)).
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <numeric>
@@ -44,9 +45,9 @@ uint64_t fnv1a(const void* data, size_t n, uint64_t h) {
 
 }  // namespace
 
-// Copy the host tables to device memory (once).
+// Copy the row table to device memory (once).
 sphidx_status tables_upload(sphidx_tables* t) {
-    if (t->d_off) return SPHIDX_OK;
+    if (t->d_rows) return SPHIDX_OK;
     t->device_bytes = 0;
     auto put = [&](void** dst, const void* src, size_t bytes) -> bool {
         size_t b = bytes ? bytes : 4;
@@ -55,27 +56,83 @@ sphidx_status tables_upload(sphidx_tables* t) {
         if (bytes && hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return false;
         return true;
     };
-    bool ok = put((void**)&t->d_off, t->h_off.data(), t->h_off.size() * 4) &&
-              put((void**)&t->d_key, t->h_key.data(), t->h_key.size() * 8) &&
-              put((void**)&t->d_class_start, t->h_class_start.data(), t->h_class_start.size() * 4) &&
-              put((void**)&t->d_rindex, t->h_rindex.data(), t->h_rindex.size() * 4);
+    bool ok = put((void**)&t->d_rows, t->h_rows.data(), t->h_rows.size() * 4) &&
+              put((void**)&t->d_rkey, t->h_rkey.data(), t->h_rkey.size() * 8) &&
+              put((void**)&t->d_rclass_start, t->h_rclass_start.data(), t->h_rclass_start.size() * 4) &&
+              put((void**)&t->d_rrindex, t->h_rrindex.data(), t->h_rrindex.size() * 4);
     return ok ? SPHIDX_OK : SPHIDX_ERR_OUT_OF_MEMORY;
 }
 
 namespace {
 
 void free_device(sphidx_tables* t) {
-    if (t->d_off) (void)hipFree(t->d_off);
-    if (t->d_key) (void)hipFree(t->d_key);
-    if (t->d_class_start) (void)hipFree(t->d_class_start);
-    if (t->d_rindex) (void)hipFree(t->d_rindex);
-    t->d_off = nullptr;
-    t->d_key = nullptr;
-    t->d_class_start = nullptr;
-    t->d_rindex = nullptr;
+    if (t->d_rows) (void)hipFree(t->d_rows);
+    if (t->d_rkey) (void)hipFree(t->d_rkey);
+    if (t->d_rclass_start) (void)hipFree(t->d_rclass_start);
+    if (t->d_rrindex) (void)hipFree(t->d_rrindex);
+    t->d_rows = nullptr;
+    t->d_rkey = nullptr;
+    t->d_rclass_start = nullptr;
+    t->d_rrindex = nullptr;
 }
 
 }  // namespace
+
+// Row table.  The packed cell index puts the cells of one x-row next to
+// each other, so their objects are one contiguous range (Section II.B).  A
+// query meets, in row (oy, oz), exactly the cells whose x-gap satisfies
+// gx^2 <= r^2 - gy^2 - gz^2: a contiguous run found per query.  The table
+// therefore lists rows instead of cells: for (y, z) sub-cell class (cy, cz)
+// every row whose key -- the smallest gy^2 + gz^2 over the class box -- is
+// <= rmax^2, sorted by key (centre to edge), with the same radius index.
+void tables_build_rows(sphidx_tables* t) {
+    const int64_t e = (int64_t)1 << t->F, w = (int64_t)1 << (t->F - t->s);
+    const int m = (int)(((int64_t)t->rmax_fx + e - 1) / e) + 1;
+    const uint64_t r2 = (uint64_t)t->rmax_fx * (uint64_t)t->rmax_fx;
+    const uint32_t nsub = 1u << t->s;
+    t->nrclasses = nsub * nsub;
+    t->h_rows.clear();
+    t->h_rkey.clear();
+    t->h_rclass_start.assign(t->nrclasses + 1, 0);
+    t->h_rrindex.assign((size_t)t->nrclasses * t->nr, 0);
+    auto gap2 = [&](int64_t c, int o) -> uint64_t {
+        int64_t g = 0;
+        if (o > 0)
+            g = (int64_t)o * e - ((c + 1) * w - 1);
+        else if (o < 0)
+            g = c * w + ((int64_t)(-o) - 1) * e + 1;
+        return (uint64_t)(g * g);
+    };
+    struct Row {
+        uint64_t key;
+        uint32_t packed;
+    };
+    std::vector<Row> rows;
+    for (uint32_t cls = 0; cls < t->nrclasses; ++cls) {
+        const int64_t cy = cls & (nsub - 1), cz = cls >> t->s;
+        rows.clear();
+        for (int oz = -m; oz <= m; ++oz)
+            for (int oy = -m; oy <= m; ++oy) {
+                const uint64_t k = gap2(cy, oy) + gap2(cz, oz);
+                if (k <= r2) rows.push_back({k, ((uint32_t)oy & 0xFFFFu) | ((uint32_t)oz << 16)});
+            }
+        std::sort(rows.begin(), rows.end(), [](const Row& x, const Row& y) {
+            return x.key < y.key || (x.key == y.key && x.packed < y.packed);
+        });
+        t->h_rclass_start[cls] = (uint32_t)t->h_rows.size();
+        for (const Row& r : rows) {
+            t->h_rows.push_back(r.packed);
+            t->h_rkey.push_back((int64_t)r.key);
+        }
+        size_t p = 0;
+        for (uint32_t j = 0; j < t->nr; ++j) {
+            const uint64_t rj = (uint64_t)j << t->rshift;
+            while (p < rows.size() && rows[p].key <= rj * rj) ++p;
+            t->h_rrindex[(size_t)cls * t->nr + j] = (uint32_t)p;
+        }
+    }
+    t->h_rclass_start[t->nrclasses] = (uint32_t)t->h_rows.size();
+}
 
 // Build on the host (validation of s / F / rmax is done by the caller).
 sphidx_status tables_build_host(uint32_t F, uint32_t s, uint32_t rmax_fx, sphidx_tables* t) {
@@ -152,6 +209,7 @@ sphidx_status tables_build_host(uint32_t F, uint32_t s, uint32_t rmax_fx, sphidx
     }
     t->h_class_start[ncls] = (uint32_t)t->h_off.size();
     t->total = t->h_off.size();
+    tables_build_rows(t);
     return SPHIDX_OK;
 }
 
@@ -234,5 +292,7 @@ sphidx_status tables_load_file(const char* path, sphidx_tables* t) {
         for (uint32_t j = 0; j < t->nr; ++j)
             if (t->h_rindex[(size_t)c * t->nr + j] > en - b) return SPHIDX_ERR_IO;
     }
+    if (t->s > t->F || t->F > 30) return SPHIDX_ERR_IO;
+    tables_build_rows(t);
     return SPHIDX_OK;
 }

@@ -33,7 +33,7 @@ class LatticeDesc(ctypes.Structure):
 
 
 class LatticeView(ctypes.Structure):
-    _fields_ = [("cell_start", P), ("xs", P), ("ys", P), ("zs", P), ("ids", P), ("n", U32), ("ncells", U32)]
+    _fields_ = [("cell_start", P), ("points", P), ("n", U32), ("ncells", U32)]
 
 
 class TablesInfo(ctypes.Structure):
@@ -53,7 +53,7 @@ class CSRDesc(ctypes.Structure):
 
 class LaunchDesc(ctypes.Structure):
     _fields_ = [("method", U32), ("schedule", U32), ("waves_per_block", U32), ("tile", U32),
-                ("blocks_per_cu", U32), ("sort_cap", U32), ("table_in_lds", U32), ("reserved", U32),
+                ("blocks_per_cu", U32), ("sort_cap", U32), ("table_in_lds", U32), ("interior", U32),
                 ("stats_dev", P)]
 
 
@@ -209,8 +209,9 @@ class Lattice:
             return t.cpu().numpy().view(np.uint32)
 
         torch.cuda.synchronize()
-        return dict(cell_start=grab(v.cell_start, v.ncells + 3), xs=grab(v.xs, v.n), ys=grab(v.ys, v.n),
-                    zs=grab(v.zs, v.n), ids=grab(v.ids, v.n))
+        pts = grab(v.points, 4 * v.n).reshape(v.n, 4)
+        return dict(cell_start=grab(v.cell_start, v.ncells + 3), xs=pts[:, 0].copy(), ys=pts[:, 1].copy(),
+                    zs=pts[:, 2].copy(), ids=pts[:, 3].copy())
 
 
 class Tables:
@@ -266,6 +267,7 @@ class LaunchConfig:
     blocks_per_cu: int = 0
     sort_cap: int = 0
     table_in_lds: int = 0
+    interior: int = 0
     stats: torch.Tensor | None = None
 
     def c(self) -> LaunchDesc:
@@ -273,6 +275,7 @@ class LaunchConfig:
         d.method, d.schedule = self.method, self.schedule
         d.waves_per_block, d.tile, d.blocks_per_cu = self.waves_per_block, self.tile, self.blocks_per_cu
         d.sort_cap, d.table_in_lds = self.sort_cap, self.table_in_lds
+        d.interior = self.interior
         d.stats_dev = None if self.stats is None else self.stats.data_ptr()
         return d
 

@@ -162,7 +162,7 @@ def test_radius_random_worlds(sx, orc, mask, world):
         ref = grid.radius(r, flags=flags)
         for name, ln in _launches(sx).items():
             s = int(rng.integers(0, len(tabs)))
-            if ln.table_in_lds and tabs[s].info().total_entries * 4 > 40000:
+            if ln.table_in_lds and tabs[s].info().total_entries * 16 > 60000:
                 continue
             assert_same(run(sx, lat, tabs[s], r, flags=flags, launch=ln), ref, f"{name} s={s} flags={flags}")
     # explicit centres, some outside the region / unusable on clipped axes
@@ -185,7 +185,7 @@ def test_radius_uniform_cyclic_32_full_vs_brute_force(sx, orc):
     for s in (0, 2):
         tab = sx.Tables(lat, s, int(w.r_fx[0]))
         for name, ln in _launches(sx).items():
-            if ln.table_in_lds and tab.info().total_entries * 4 > 40000:
+            if ln.table_in_lds and tab.info().total_entries * 16 > 60000:
                 continue
             assert_same(run(sx, lat, tab, w.r_fx, launch=ln), ref, f"C1 {name} s={s}")
         # uniform radius passed as a scalar
@@ -329,7 +329,8 @@ def test_cells_touched_match_oracle(sx, orc, mask):
     # rows are by object id; stats likewise
     np.testing.assert_array_equal(st[:, 1], kept)
     np.testing.assert_array_equal(st[:, 3], cube)
-    assert (st[:, 0] >= st[:, 1]).all()  # walked >= kept
+    # the walk visits x-rows of cells: at least one row wherever a cell is kept
+    assert ((st[:, 0] > 0) | (st[:, 1] == 0)).all()
     say("mean kept/cube", st[:, 1].mean() / st[:, 3].mean())
 
 
