@@ -192,7 +192,8 @@ typedef struct {
     uint32_t waves_per_block; /* 1, 2, 4, 8 or 16; 0 = default */
     uint32_t tile;            /* queries per wave slice / per queue grab; 0 = default */
     uint32_t blocks_per_cu;   /* persistent residency; 0 = default */
-    uint32_t sort_cap;        /* per-wave row buffer (64..1024, power of two); 0 = default */
+    uint32_t sort_cap;        /* per-wave LDS row buffer (64, 128 or 256); longer rows take the
+                                 windowed top-M path; 0 = 256 */
     uint32_t table_in_lds;    /* 1: stage the whole row table in LDS (CAPACITY if it does not fit) */
     uint32_t interior;        /* count pass, sphere method: 0 = auto (on when objects per cell >= 1),
                                  1 = off, 2 = on: cells wholly inside the sphere are counted whole */

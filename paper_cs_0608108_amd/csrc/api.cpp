@@ -94,7 +94,7 @@ sphidx_status resolve_launch(const sphidx_launch* in, const sphidx_tables* tab, 
     o.method = in ? in->method : SPHIDX_METHOD_SPHERE;
     o.persistent = in ? (in->schedule == SPHIDX_SCHED_PERSISTENT) : 1u;
     o.waves = (in && in->waves_per_block) ? in->waves_per_block : 4u;
-    o.tile = (in && in->tile) ? in->tile : (o.persistent ? 4u : 1u);
+    o.tile = (in && in->tile) ? in->tile : (o.persistent ? 64u : 1u);
     o.bpc = (in && in->blocks_per_cu) ? in->blocks_per_cu : 8u;
     o.cap = (in && in->sort_cap) ? in->sort_cap : 256u;
     o.tab_lds = in ? in->table_in_lds : 0u;
@@ -104,7 +104,7 @@ sphidx_status resolve_launch(const sphidx_launch* in, const sphidx_tables* tab, 
     if (in && in->schedule > SPHIDX_SCHED_PERSISTENT) return SPHIDX_ERR_INVALID_ARG;
     if (o.method > SPHIDX_METHOD_CUBE) return SPHIDX_ERR_INVALID_ARG;
     if (!(o.waves == 1 || o.waves == 2 || o.waves == 4)) return SPHIDX_ERR_INVALID_ARG;
-    if (o.cap < 64 || o.cap > 1024 || (o.cap & (o.cap - 1))) return SPHIDX_ERR_INVALID_ARG;
+    if (o.cap < 64 || o.cap > 256 || (o.cap & (o.cap - 1))) return SPHIDX_ERR_INVALID_ARG;
     if (o.tile > 4096 || o.bpc > 64) return SPHIDX_ERR_INVALID_ARG;
     if (o.method == SPHIDX_METHOD_SPHERE && !tab) return SPHIDX_ERR_INVALID_ARG;
     if (o.method == SPHIDX_METHOD_CUBE) o.tab_lds = 0;
@@ -114,9 +114,9 @@ sphidx_status resolve_launch(const sphidx_launch* in, const sphidx_tables* tab, 
     return SPHIDX_OK;
 }
 
-// Query workspace: counters | descriptors[Q] | longq[Q] | scan partials.
+// Query workspace: counters | descriptors[Q] | longq[Q] | fbq[Q] | scan partials.
 struct QLayout {
-    size_t counters, desc, longq, scan, total;
+    size_t counters, desc, longq, fbq, scan, total;
 };
 
 QLayout query_layout(uint32_t Q) {
@@ -130,6 +130,7 @@ QLayout query_layout(uint32_t Q) {
     l.counters = take(SPHIDX_COUNTER_WORDS * 4);
     l.desc = take((size_t)Q * 64);
     l.longq = take((size_t)Q * 4);
+    l.fbq = take((size_t)Q * 4);
     l.scan = take(scan_i64_tmp_bytes(Q));
     l.total = off;
     return l;
@@ -170,8 +171,10 @@ QArgs q_args(const sphidx_queries* q, sphidx_csr* csr, const Launch& ln) {
     const QLayout ql = query_layout(q->count);
     char* ws = (char*)csr->workspace_dev;
     A.queues = (uint32_t*)(ws + ql.counters);
-    A.long_count = A.queues + 3 * SPHIDX_NQUEUE * SPHIDX_QSTRIDE;
+    A.long_count = A.queues + SPHIDX_NQSETS * SPHIDX_NQUEUE * SPHIDX_QSTRIDE;
+    A.fb_count = A.long_count + SPHIDX_QSTRIDE;
     A.longq = (uint32_t*)(ws + ql.longq);
+    A.fbq = (uint32_t*)(ws + ql.fbq);
     A.desc = (uint4*)(ws + ql.desc);
     A.stats = ln.stats;
     A.method = ln.method;

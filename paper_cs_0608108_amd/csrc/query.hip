@@ -38,7 +38,8 @@ namespace {
 
 constexpr uint32_t kMaxId = 0xFFFFFFFFu;
 constexpr uint64_t kMaxD2 = ~0ull;
-constexpr int kSphere = 0, kCube = 1;
+// Walk kinds: sphere rows only, cube rows only, or either (chosen per query).
+constexpr int kSphere = 0, kCube = 1, kEither = 2;
 
 // ---------------------------------------------------------------------------
 // Wave primitives
@@ -151,6 +152,8 @@ struct Query {
     uint32_t self;  // sorted position excluded (EXCLUDE_SELF, all agents) or ~0
     uint32_t c[3];  // home cell
     uint32_t f[3];  // position inside the home cell
+    uint32_t up[3]; // e - f: distance to the next cell up
+    uint32_t dn[3]; // f + 1: distance to the last position of the cell below
     uint64_t r2;
 };
 
@@ -219,6 +222,7 @@ __global__ __launch_bounds__(256) void setup_kernel(LatArgs L, TabArgs T, QArgs 
         }
         const bool sphere = METHOD == kSphere && inside && cyc_ok && r <= T.rmax;
         fallback = valid && METHOD == kSphere && !sphere;
+        if (fallback) A.fbq[atomicAdd(A.fb_count, 1u)] = i;
         uint32_t tb = 0, tend = 0;
         if (sphere && valid) {
             // row tables are specialised on the (y, z) sub-cell position
@@ -269,6 +273,8 @@ __device__ __forceinline__ Query load_query(const LatArgs& L, const QArgs& A, ui
     for (int a = 0; a < 3; ++a) {
         s.c[a] = s.q[a] >> L.F;
         s.f[a] = s.q[a] & (e - 1u);
+        s.up[a] = e - s.f[a];
+        s.dn[a] = s.f[a] + 1u;
     }
     s.r2 = (uint64_t)s.r * (uint64_t)s.r;
     return s;
@@ -331,40 +337,35 @@ __device__ __forceinline__ uint32_t isqrt64(uint64_t v) {
     return (uint32_t)x;
 }
 
-// Turn an unwrapped x-run [a, b] of row `base` (and its wholly-inside part
-// [ia, ib], empty when ia > ib) into object ranges.  On a cyclic axis the
-// run (shorter than the axis) may cross the world edge once: it is then two
-// pieces and is tested whole; on a clipped axis it is clamped to the region.
-__device__ __forceinline__ RowRef row_ranges(const LatArgs& L, uint32_t base, int a, int b, int ia, int ib) {
-    RowRef r = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
+// Turn an unwrapped x-run [a, b] of the row starting at cell `base` (and its
+// wholly-inside part [ia, ib], empty when ia > ib) into object ranges.  On a
+// cyclic axis the run (shorter than the axis) may cross the world edge once:
+// it is then two pieces and is tested whole; on a clipped axis it is clamped
+// to the region.  Lanes with `live` false get empty ranges (their loads read
+// the row start, always a valid index).
+__device__ __forceinline__ RowRef row_ranges(const LatArgs& L, uint32_t base, int a, int b, int ia, int ib,
+                                             bool live) {
     const int Lx = 1 << L.lg[0];
     int p0, p1, p2, p3;
-    bool has_int = ia <= ib, wrap = false;
+    bool has_int = ia <= ib;
+    bool wrap = false;
     if (L.cyc & 1u) {
-        if (a < 0 || b >= Lx) {
-            wrap = true;
-            has_int = false;
-            if (a < 0) {
-                p0 = 0;
-                p1 = b + 1;
-                p2 = a + Lx;
-                p3 = Lx;
-            } else {
-                p0 = a;
-                p1 = Lx;
-                p2 = 0;
-                p3 = b - Lx + 1;
-            }
-        }
+        const bool lo_out = a < 0, hi_out = b >= Lx;
+        wrap = lo_out || hi_out;
+        // pieces in memory order when wrapped: [0, e0) then [s1, Lx)
+        const int e0 = lo_out ? b + 1 : b - Lx + 1;
+        const int s1 = lo_out ? a + Lx : a;
+        ia = max(ia, a);
+        ib = min(ib, b);
+        has_int = has_int && !wrap && ia <= ib;
+        p0 = wrap ? 0 : a;
+        p1 = wrap ? e0 : (has_int ? ia : a);
+        p2 = wrap ? s1 : (has_int ? ib + 1 : a);
+        p3 = wrap ? Lx : b + 1;
     } else {
         a = max(a, 0);
         b = min(b, Lx - 1);
-        if (a > b) return r;
-        ia = max(ia, a);
-        ib = min(ib, b);
-        has_int = has_int && ia <= ib;
-    }
-    if (!wrap) {
+        live = live && a <= b;
         ia = max(ia, a);
         ib = min(ib, b);
         has_int = has_int && ia <= ib;
@@ -373,74 +374,81 @@ __device__ __forceinline__ RowRef row_ranges(const LatArgs& L, uint32_t base, in
         p2 = has_int ? ib + 1 : a;
         p3 = b + 1;
     }
-    const uint32_t v0 = L.cs[base + p0];
-    const uint32_t v3 = L.cs[base + p3];
-    uint32_t v1 = v0, v2 = v0;
-    if (p1 != p0) v1 = L.cs[base + p1];
-    if (p2 != p0) v2 = L.cs[base + p2];
+    if (!live) p0 = p1 = p2 = p3 = 0;
+    const uint32_t* row = L.cs + base;
+    const uint32_t v0 = row[p0], v1 = row[p1], v2 = row[p2], v3 = row[p3];
+    RowRef r;
     r.st0 = v0;
     r.cnt0 = v1 - v0;
     r.st1 = v2;
     r.cnt1 = v3 - v2;
-    if (has_int) {
-        r.ist = v1;
-        r.icnt = v2 - v1;
-    }
+    r.ist = v1;
+    r.icnt = has_int ? v2 - v1 : 0u;
     r.kept = (uint32_t)(wrap ? (p1 - p0) + (p3 - p2) : (p3 - p0));
     return r;
 }
 
+// Squared distance along one axis from the query to the nearest position of
+// the cell at offset o: 0 for o = 0, else (|o| - 1) cells plus the distance
+// to the shared face (up = e - f above, dn = f + 1 below).
+__device__ __forceinline__ uint64_t axis_gap2(int o, uint32_t up, uint32_t dn, uint32_t F) {
+    const uint32_t ao = (uint32_t)(o < 0 ? -o : o);
+    const uint32_t g = o == 0 ? 0u : ((ao - 1u) << F) + (o > 0 ? up : dn);
+    return sq(g);
+}
+
 // Row (oy, oz) of the sphere table: the cells it meets are those whose
 // x-gap satisfies gx^2 <= bound^2 - gy^2 - gz^2 -- the exact test of Eq. 1
-// solved for x, so one contiguous run; the wholly-inside cells solve the
-// same with the far distances (Section III.A, last paragraph).
+// solved for x, one contiguous run; the wholly-inside cells solve the same
+// with the far distances (Section III.A, last paragraph).
 template <bool INTERIOR>
 __device__ __forceinline__ RowRef sphere_row(const LatArgs& L, const Query& s, uint32_t w, bool has, uint64_t bound2) {
-    const RowRef none = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
     const int oy = ((int)(w << 16)) >> 16, oz = ((int)w) >> 16;
-    int ty = (int)s.c[1] + oy, tz = (int)s.c[2] + oz;
-    const int Ly = 1 << L.lg[1], Lz = 1 << L.lg[2];
-    bool in = has;
+    const uint32_t Ly = 1u << L.lg[1], Lz = 1u << L.lg[2];
+    uint32_t ty = (uint32_t)((int)s.c[1] + oy), tz = (uint32_t)((int)s.c[2] + oz);
+    bool live = has;
     if (L.cyc & 2u)
-        ty &= Ly - 1;
+        ty &= Ly - 1u;
     else
-        in = in && (uint32_t)ty < (uint32_t)Ly;
+        live = live && ty < Ly;
     if (L.cyc & 4u)
-        tz &= Lz - 1;
+        tz &= Lz - 1u;
     else
-        in = in && (uint32_t)tz < (uint32_t)Lz;
-    const uint64_t gyz = sq(axis_gap(oy, s.f[1], L.F)) + sq(axis_gap(oz, s.f[2], L.F));
-    if (!in || gyz > bound2) return none;
-    const uint32_t X = isqrt64(bound2 - gyz);
+        live = live && tz < Lz;
+    const uint64_t gyz = axis_gap2(oy, s.up[1], s.dn[1], L.F) + axis_gap2(oz, s.up[2], s.dn[2], L.F);
+    live = live && gyz <= bound2;
+    const uint32_t X = isqrt64(live ? bound2 - gyz : 0u);
     const uint32_t fx = s.f[0];
     const int npos = (int)((X + fx) >> L.F);
-    const int nneg = X >= fx + 1u ? (int)((X - fx - 1u) >> L.F) + 1 : 0;
+    const int nneg = X > fx ? (int)((X - fx - 1u) >> L.F) + 1 : 0;
     int ia = 1, ib = 0;
     if (INTERIOR) {
-        const uint64_t hyz = sq(axis_far(oy, s.f[1], L.F)) + sq(axis_far(oz, s.f[2], L.F));
-        if (hyz <= s.r2) {
-            const uint32_t Xi = isqrt64(s.r2 - hyz);
-            if (Xi >= fx && Xi + fx + 1u >= (1u << L.F)) {
-                ib = (int)s.c[0] + (int)((Xi + fx + 1u) >> L.F) - 1;
-                ia = (int)s.c[0] - (int)((Xi - fx) >> L.F);
-            }
+        const uint32_t hy = axis_far(oy, s.f[1], L.F), hz = axis_far(oz, s.f[2], L.F);
+        const uint64_t hyz = sq(hy) + sq(hz);
+        const uint32_t Xi = isqrt64(hyz <= s.r2 ? s.r2 - hyz : 0u);
+        if (hyz <= s.r2 && Xi >= fx && Xi + fx + 1u >= (1u << L.F)) {
+            ib = (int)s.c[0] + (int)((Xi + fx + 1u) >> L.F) - 1;
+            ia = (int)s.c[0] - (int)((Xi - fx) >> L.F);
         }
     }
-    const uint32_t base = ((uint32_t)tz << (L.lg[0] + L.lg[1])) | ((uint32_t)ty << L.lg[0]);
-    return row_ranges(L, base, (int)s.c[0] - nneg, (int)s.c[0] + npos, ia, ib);
+    if (!live) {
+        ty = 0;
+        tz = 0;
+    }
+    const uint32_t base = (tz << (L.lg[0] + L.lg[1])) | (ty << L.lg[0]);
+    return row_ranges(L, base, (int)s.c[0] - nneg, (int)s.c[0] + npos, ia, ib, live);
 }
 
 // Row e of the bounding cube (no test: the bin-lattice scans every cell).
 __device__ __forceinline__ RowRef cube_row(const LatArgs& L, const Query& s, uint32_t e, bool has, double inv_ny) {
-    const RowRef none = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
-    if (!has) return none;
+    if (!has) e = 0;
     const uint32_t iz = exact_div(e, s.nn[1], inv_ny);
     const uint32_t iy = e - iz * s.nn[1];
     uint32_t ty = (uint32_t)(s.lo[1] + (int32_t)iy), tz = (uint32_t)(s.lo[2] + (int32_t)iz);
     if (L.cyc & 2u) ty &= (1u << L.lg[1]) - 1u;
     if (L.cyc & 4u) tz &= (1u << L.lg[2]) - 1u;
     const uint32_t base = (tz << (L.lg[0] + L.lg[1])) | (ty << L.lg[0]);
-    return row_ranges(L, base, s.lo[0], s.lo[0] + (int)s.nn[0] - 1, 1, 0);
+    return row_ranges(L, base, s.lo[0], s.lo[0] + (int)s.nn[0] - 1, 1, 0, has);
 }
 
 // Minimum-image squared distance of an object to the centre: on a cyclic
@@ -533,7 +541,7 @@ __device__ __forceinline__ void walk(const LatArgs& L, const TabArgs& T, const u
         }
         if (on_step(r)) return;
     }
-    const bool sphere = METHOD == kSphere && (s.flags & F_SPHERE);
+    const bool sphere = METHOD == kSphere || (METHOD == kEither && (s.flags & F_SPHERE));
     const uint32_t nent = sphere ? s.tend : s.nn[1] * s.nn[2];
     const uint32_t* rows = TLDS ? tab_lds + s.tb : T.rows + s.tb;
     uint32_t nxt = 0;
@@ -542,7 +550,7 @@ __device__ __forceinline__ void walk(const LatArgs& L, const TabArgs& T, const u
     for (uint32_t base = 0; base < nent; base += 64) {
         const uint32_t idx = base + lane;
         RowRef r;
-        if (sphere) {
+        if (METHOD == kSphere || (METHOD == kEither && sphere)) {
             const uint64_t bound2 = bound2_now();
             // rows are sorted by key: once the key exceeds the bound no
             // further row can hold anything closer
@@ -627,15 +635,27 @@ __device__ __forceinline__ size_t table_lds_bytes(const TabArgs& T) {
 // ---------------------------------------------------------------------------
 // Pass 0: row sizes
 
-template <int METHOD, bool TLDS>
+// Queue sets of the work counters.
+constexpr int kQCount = 0, kQWrite = 1, kQTopm = 2, kQFbCount = 3, kQFbWrite = 4;
+
+__device__ __forceinline__ uint32_t* queue_set(const QArgs& A, int set) {
+    return A.queues + (size_t)set * SPHIDX_NQUEUE * SPHIDX_QSTRIDE;
+}
+
+// FROM_LIST: the queries of the sphere method that the tables do not cover,
+// scanned with the bounding cube.
+template <int METHOD, bool TLDS, bool FROM_LIST>
 __global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs A) {
     extern __shared__ __align__(16) char smem[];
     const uint32_t* tab_lds = stage_table<TLDS>(T, smem);
     uint32_t* own = (uint32_t*)(smem + table_lds_bytes<TLDS>(T)) + (threadIdx.x >> 6) * 64;
     const AxisWrap aw = axis_wrap(L);
     const uint32_t lane = lane_id();
-    for_each_query(A.Q, A, A.queues, [&](uint32_t qi) {
+    const uint32_t nq = FROM_LIST ? uni(*A.fb_count) : A.Q;
+    for_each_query(nq, A, queue_set(A, FROM_LIST ? kQFbCount : kQCount), [&](uint32_t ti_) {
+        const uint32_t qi = FROM_LIST ? uni(A.fbq[ti_]) : ti_;
         const Query s = load_query(L, A, qi);
+        if (METHOD == kSphere && (s.flags & F_VALID) && !(s.flags & F_SPHERE)) return;  // fallback list
         const bool knn = s.flags & F_KNN;
         uint32_t hits = 0, inner = 0, kept = 0, cand = 0, walked = 0;
         bool self_inner = false;
@@ -688,24 +708,91 @@ __device__ __forceinline__ void store_sorted(const QArgs& A, const uint64_t* td,
     }
 }
 
-template <int METHOD, bool TLDS>
+// Sort the n <= cap pairs (td, ti) of one row by (dist^2, id) and store them
+// at row offset rb.  Every pair has dist^2 <= r2, so the bucket
+// floor(n * dist^2 / r2) (float arithmetic: monotone in dist^2) never puts a
+// larger distance in an earlier bucket; a histogram, its prefix sum and a
+// scatter order the buckets, and each pair's place inside its bucket (about
+// one pair per bucket) is the number of smaller pairs there.
+__device__ __forceinline__ uint32_t sort_bucket(uint64_t d2, float scale, uint32_t n) {
+    return min((uint32_t)((float)d2 * scale), n - 1u);
+}
+
+__device__ void bucket_sort_store(const QArgs& A, const uint64_t* td, const uint32_t* ti, uint64_t* sd,
+                                  uint32_t* si, uint32_t* hist, uint32_t n, uint64_t r2, int64_t rb) {
+    const uint32_t lane = lane_id();
+    if (n == 0) return;
+    const float scale = r2 > 0 ? (float)n / (float)r2 : 0.0f;
+    for (uint32_t t = lane; t < n; t += 64) hist[t] = 0u;
+    wave_sync();
+    uint32_t slot[4];  // n <= 256 = 4 pairs per lane
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t t = lane + 64u * k;
+        if (t < n) slot[k] = atomicAdd(&hist[sort_bucket(td[t], scale, n)], 1u);
+    }
+    wave_sync();
+    // exclusive prefix over the buckets, each lane owning a run of them
+    const uint32_t per = (n + 63u) >> 6;
+    const uint32_t b0 = lane * per;
+    uint32_t sum = 0;
+    for (uint32_t k = 0; k < per; ++k)
+        if (b0 + k < n) sum += hist[b0 + k];
+    uint32_t run = scan_add(sum) - sum;
+    wave_sync();
+    for (uint32_t k = 0; k < per; ++k)
+        if (b0 + k < n) {
+            const uint32_t c = hist[b0 + k];
+            hist[b0 + k] = run;
+            run += c;
+        }
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t t = lane + 64u * k;
+        if (t < n) {
+            const uint32_t dst = hist[sort_bucket(td[t], scale, n)] + slot[k];
+            sd[dst] = td[t];
+            si[dst] = ti[t];
+        }
+    }
+    wave_sync();
+    for (uint32_t t = lane; t < n; t += 64) {
+        const uint64_t d = sd[t];
+        const uint32_t id = si[t];
+        const uint32_t b = sort_bucket(d, scale, n);
+        const uint32_t lo = hist[b], hi = b + 1 < n ? hist[b + 1] : n;
+        uint32_t rank = lo;
+        for (uint32_t j = lo; j < hi; ++j) rank += key_less(sd[j], si[j], d, id) ? 1u : 0u;
+        A.out_ids[rb + rank] = id;
+        if (A.out_d2) A.out_d2[rb + rank] = (int64_t)d;
+    }
+}
+
+template <int METHOD, bool TLDS, bool FROM_LIST>
 __global__ __launch_bounds__(256) void write_kernel(LatArgs L, TabArgs T, QArgs A) {
     extern __shared__ __align__(16) char smem[];
     const uint32_t* tab_lds = stage_table<TLDS>(T, smem);
     const uint32_t wave = threadIdx.x >> 6;
     const uint32_t cap = A.sort_cap;
-    char* wb = smem + table_lds_bytes<TLDS>(T) + (size_t)wave * ((size_t)cap * 12 + 256);
+    char* wb = smem + table_lds_bytes<TLDS>(T) + (size_t)wave * ((size_t)cap * 28 + 256);
     uint64_t* td = (uint64_t*)wb;
-    uint32_t* ti = (uint32_t*)(td + cap);
-    uint32_t* own = ti + cap;
+    uint64_t* sd = td + cap;
+    uint32_t* ti = (uint32_t*)(sd + cap);
+    uint32_t* si = ti + cap;
+    uint32_t* hist = si + cap;
+    uint32_t* own = hist + cap;
     if (A.row_ptr[A.Q] > A.capacity) {
         if (threadIdx.x == 0) atomicOr(L.status, SPHIDX_FLAG_CAPACITY);
         return;
     }
     const AxisWrap aw = axis_wrap(L);
     const uint32_t lane = lane_id();
-    for_each_query(A.Q, A, A.queues + SPHIDX_NQUEUE * SPHIDX_QSTRIDE, [&](uint32_t qi) {
+    const uint32_t nq = FROM_LIST ? uni(*A.fb_count) : A.Q;
+    for_each_query(nq, A, queue_set(A, FROM_LIST ? kQFbWrite : kQWrite), [&](uint32_t ti_) {
+        const uint32_t qi = FROM_LIST ? uni(A.fbq[ti_]) : ti_;
         const Query s = load_query(L, A, qi);
+        if (METHOD == kSphere && (s.flags & F_VALID) && !(s.flags & F_SPHERE)) return;  // fallback list
         const int64_t rb = A.row_ptr[s.row];
         const uint32_t rowlen = (uint32_t)(A.row_ptr[s.row + 1] - rb);
         if (rowlen == 0 || !(s.flags & F_VALID)) return;
@@ -734,50 +821,7 @@ __global__ __launch_bounds__(256) void write_kernel(LatArgs L, TabArgs T, QArgs 
             return for_candidates(L, r.st0, r.cnt0, r.st1, r.cnt1, own, cand, visit);
         });
         wave_sync();
-        n = min(n, rowlen);
-        if (n <= 64) {
-            // rank sort: lane i holds pair i; its rank is the number of smaller pairs
-            uint64_t d = kMaxD2;
-            uint32_t id = kMaxId;
-            if (lane < n) {
-                d = td[lane];
-                id = ti[lane];
-            }
-            uint32_t rank = 0;
-#pragma unroll 4
-            for (uint32_t j = 0; j < n; ++j) rank += key_less(td[j], ti[j], d, id) ? 1u : 0u;
-            if (lane < n) {
-                A.out_ids[rb + rank] = id;
-                if (A.out_d2) A.out_d2[rb + rank] = (int64_t)d;
-            }
-        } else {
-            uint32_t np = 128;
-            while (np < n) np <<= 1;
-            for (uint32_t t = n + lane; t < np; t += 64) {
-                td[t] = kMaxD2;
-                ti[t] = kMaxId;
-            }
-            wave_sync();
-            for (uint32_t k = 2; k <= np; k <<= 1) {
-                for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-                    for (uint32_t t = lane; t < (np >> 1); t += 64) {
-                        const uint32_t i = ((t & ~(j - 1u)) << 1) | (t & (j - 1u));
-                        const uint32_t pj = i + j;
-                        const uint64_t di = td[i], dp = td[pj];
-                        const uint32_t ii = ti[i], ip = ti[pj];
-                        const bool up = (i & k) == 0;
-                        if (up ? key_less(dp, ip, di, ii) : key_less(di, ii, dp, ip)) {
-                            td[i] = dp;
-                            td[pj] = di;
-                            ti[i] = ip;
-                            ti[pj] = ii;
-                        }
-                    }
-                    wave_sync();
-                }
-            }
-            store_sorted(A, td, ti, n, rb);
-        }
+        bucket_sort_store(A, td, ti, sd, si, hist, min(n, rowlen), s.r2, rb);
         wave_sync();
     });
 }
@@ -808,7 +852,7 @@ __global__ __launch_bounds__(256) void topm_kernel(LatArgs L, TabArgs T, QArgs A
     const AxisWrap aw = axis_wrap(L);
     const uint32_t lane = lane_id();
     const uint32_t nq = FROM_LIST ? uni(*A.long_count) : A.Q;
-    for_each_query(nq, A, A.queues + 2 * SPHIDX_NQUEUE * SPHIDX_QSTRIDE, [&](uint32_t ti_) {
+    for_each_query(nq, A, queue_set(A, kQTopm), [&](uint32_t ti_) {
         const uint32_t qi = FROM_LIST ? uni(A.longq[ti_]) : ti_;
         const Query s = load_query(L, A, qi);
         if (!FROM_LIST && !(s.flags & F_KNN)) return;
@@ -913,10 +957,10 @@ __global__ void clear_counters_kernel(uint32_t* c) {
 }
 
 // Kernel choice by variant: cube, sphere, sphere with the row table in LDS.
-#define SPHIDX_PICK(KERNEL, variant, ...)                                          \
+#define SPHIDX_PICK(KERNEL, variant, SPH, ...)                                     \
     ((variant) == 0 ? (const void*)KERNEL<kCube, false __VA_ARGS__>                \
-     : (variant) == 1 ? (const void*)KERNEL<kSphere, false __VA_ARGS__>            \
-                      : (const void*)KERNEL<kSphere, true __VA_ARGS__>)
+     : (variant) == 1 ? (const void*)KERNEL<SPH, false __VA_ARGS__>                \
+                      : (const void*)KERNEL<SPH, true __VA_ARGS__>)
 
 hipError_t launch_ptr(const void* fn, uint32_t nq, const QArgs& q, uint32_t waves, uint32_t bpc, size_t shmem,
                       hipStream_t st, const LatArgs& L, const TabArgs& T) {
@@ -949,7 +993,7 @@ int device_cu_count() {
 }
 
 size_t query_lds_bytes(int pass, uint32_t cap, uint32_t waves, size_t table_bytes) {
-    size_t per = pass == 0 ? 256 : (pass == 1 ? (size_t)cap * 12 + 256 : (size_t)cap * 24 + 64 * 12 + 256);
+    size_t per = pass == 0 ? 256 : (pass == 1 ? (size_t)cap * 28 + 256 : (size_t)cap * 24 + 64 * 12 + 256);
     return table_bytes + per * waves;
 }
 
@@ -960,7 +1004,7 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
     clear_counters_kernel<<<1, 256, 0, st>>>(q.queues);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || q.Q == 0) return e;
-    // per-query descriptors
+    // per-query descriptors (and, for the sphere method, the fallback list)
     if (variant == 0)
         setup_kernel<kCube><<<(q.Q + 255) / 256, 256, 0, st>>>(L, T, q);
     else
@@ -968,19 +1012,28 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const uint32_t w = waves_per_block, b = blocks_per_cu;
-    if (pass == 0)
-        return launch_ptr(SPHIDX_PICK(count_kernel, variant), q.Q, q, w, b, query_lds_bytes(0, q.sort_cap, w, tb),
-                          st, L, T);
+    QArgs ql = q;  // list-driven launches: persistent, one query per grab
+    ql.persistent = 1;
+    ql.tile = 1;
+    if (pass == 0) {
+        e = launch_ptr(SPHIDX_PICK(count_kernel, variant, kSphere, , false), q.Q, q, w, b,
+                       query_lds_bytes(0, q.sort_cap, w, tb), st, L, T);
+        if (e != hipSuccess || variant == 0) return e;
+        return launch_ptr((const void*)count_kernel<kCube, false, true>, 0, ql, w, b,
+                          query_lds_bytes(0, q.sort_cap, w, 0), st, L, T);
+    }
     const size_t sh1 = query_lds_bytes(1, q.sort_cap, w, tb);
     const size_t sh2 = query_lds_bytes(2, q.sort_cap, w, tb);
     if (q.mode != SPHIDX_MODE_KNN) {
-        e = launch_ptr(SPHIDX_PICK(write_kernel, variant), q.Q, q, w, b, sh1, st, L, T);
+        e = launch_ptr(SPHIDX_PICK(write_kernel, variant, kSphere, , false), q.Q, q, w, b, sh1, st, L, T);
         if (e != hipSuccess) return e;
+        if (variant != 0) {
+            e = launch_ptr((const void*)write_kernel<kCube, false, true>, 0, ql, w, b,
+                           query_lds_bytes(1, q.sort_cap, w, 0), st, L, T);
+            if (e != hipSuccess) return e;
+        }
         // K-NN rows of a mixed batch and long radius rows, from the list
-        QArgs ql = q;
-        ql.persistent = 1;
-        ql.tile = 1;
-        return launch_ptr(SPHIDX_PICK(topm_kernel, variant, , true), 0, ql, w, b, sh2, st, L, T);
+        return launch_ptr(SPHIDX_PICK(topm_kernel, variant, kEither, , true), 0, ql, w, b, sh2, st, L, T);
     }
-    return launch_ptr(SPHIDX_PICK(topm_kernel, variant, , false), q.Q, q, w, b, sh2, st, L, T);
+    return launch_ptr(SPHIDX_PICK(topm_kernel, variant, kEither, , false), q.Q, q, w, b, sh2, st, L, T);
 }

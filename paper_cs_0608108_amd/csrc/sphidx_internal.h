@@ -98,9 +98,11 @@ struct QArgs {
     uint32_t* out_ids;
     int64_t* out_d2;
     int64_t capacity;
-    uint32_t* queues;   // work counters: 3 x NQUEUE, then the long-row count
+    uint32_t* queues;   // work counters: 5 x NQUEUE, then the list counts
     uint32_t* long_count;
-    uint32_t* longq;    // rows handed from the write kernel to the top-M kernel
+    uint32_t* longq;    // rows handed from the write kernels to the top-M kernel
+    uint32_t* fb_count;
+    uint32_t* fbq;      // sphere method: queries the tables do not cover (cube scan)
     uint4* desc;        // per query (processing order): 4 x uint4 set up by the setup kernel
     uint32_t* stats;
     uint32_t method;
@@ -112,7 +114,8 @@ struct QArgs {
 
 #define SPHIDX_NQUEUE 8         // one work queue per XCD of the MI355X
 #define SPHIDX_QSTRIDE 32       // counters 128 bytes apart: one L2 line each
-#define SPHIDX_COUNTER_WORDS (3 * SPHIDX_NQUEUE * SPHIDX_QSTRIDE + SPHIDX_QSTRIDE)
+#define SPHIDX_NQSETS 5         // count, write, top-M, fallback count, fallback write
+#define SPHIDX_COUNTER_WORDS (SPHIDX_NQSETS * SPHIDX_NQUEUE * SPHIDX_QSTRIDE + 2 * SPHIDX_QSTRIDE)
 #define SPHIDX_MAX_LOG2_SUM 30
 
 // ---------------------------------------------------------------------------
