@@ -1,7 +1,7 @@
 #!/usr/bin/env python
 """Throughput of the all-agents neighbourhood query on one MI355X.
 
-Workload (the configuration the headline metric is quoted on): N = 1,048,576
+Headline workload (the configuration the metric is quoted on): N = 1,048,576
 points uniform in a clipped 128^3 lattice (cell edge 2^16 fixed-point
 units); every point queries its own radius, uniform in [0.5, 4] cells in
 steps of 1/64 cell.  One step is the whole hot path on that input:
@@ -17,7 +17,18 @@ the plain per-query-set launch and the bin-lattice cube scan are timed on
 the same GPU and reported beside it.  The CPU oracle is timed on the host
 cores on the same workload and its result checks the GPU output.
 
-Prints one JSON line.
+Further legs, reported under their own keys of the same JSON line:
+
+    knn        4,194,304 clustered points in a cyclic 256^3 lattice, K = 16,
+               cap 8 cells (sphere tables vs the cube scan on a subsample)
+    timestep   8,388,608 moving agents in a cyclic 256^3 lattice, radius 3
+               cells, 100 steps replayed from one captured HIP graph
+    serving    16,777,216 points in a cyclic 512^3 lattice; Poisson batches
+               of log-uniform size mixing radius and K-NN queries; p50/p99
+               latency of continuous batching vs one plain launch per batch
+
+Prints one JSON line.  `--copy-bytes B` instead times a plain device copy of
+B bytes (the calibration run for the HBM byte counters).
 """
 from __future__ import annotations
 
@@ -33,32 +44,47 @@ sys.path.insert(0, ROOT)
 
 METRIC = "all-agents neighbor queries/sec and HBM GB/s at 1 GPU; p99 latency vs plain launch"
 HBM_PEAK_GBS = 8000.0
+LEGS = ("c2", "knn", "timestep", "serving")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-tune", action="store_true", help="use the cached/default launch configuration")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg (profiling runs)")
-    ap.add_argument("--no-baselines", action="store_true", help="skip the plain-launch and cube-scan legs")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path; run with --gpus 1",
-              file=sys.stderr)
-        sys.exit(2)
+def sample_rows(rp, ids_dev, rows):
+    """(row_ptr, ids) of the given rows, gathered from device ids."""
+    import numpy as np
+    import torch
+    lens = rp[rows + 1] - rp[rows]
+    idx = np.concatenate([np.arange(rp[r], rp[r + 1]) for r in rows]) if len(rows) else np.zeros(0, np.int64)
+    got = ids_dev[torch.from_numpy(idx).to(ids_dev.device)].cpu().numpy().view(np.uint32)
+    srp = np.zeros(len(rows) + 1, dtype=np.int64)
+    srp[1:] = np.cumsum(lens)
+    return srp, got
 
+
+def same_rows(srp, sids, ref):
+    import numpy as np
+    return bool(np.array_equal(srp, ref.row_ptr) and np.array_equal(sids, ref.ids))
+
+
+def sample_of(n, count, seed):
+    from paper_cs_0608108_amd import synth
+    import numpy as np
+    if n <= count:
+        return np.arange(n, dtype=np.int64)
+    return np.unique(synth.uniform_int(seed, 44, np.arange(count, dtype=np.uint64), 0, n - 1))
+
+
+# ---------------------------------------------------------------------------
+# Headline: batched uneven-radius all-agents query
+
+def leg_c2(args, out):
     import numpy as np
     import torch
 
     from paper_cs_0608108_amd import autotune, sphidx, synth
 
-    torch.cuda.set_device(0)
     w = synth.radius_uneven_clipped()
     n = w.n
     log(f"workload {w.name}: n={n}")
@@ -118,7 +144,6 @@ def main():
     ids = buf.ids[: int(rp[-1])].cpu().numpy().view(np.uint32)
     log(f"persistent: {ms:.3f} ms/step; build {phases[0]:.3f} count {phases[1]:.3f} write {phases[2]:.3f} ms")
 
-    extra = {}
     if not args.no_baselines:
         k2 = max(3, args.steps // 2)
         plain = sphidx.LaunchConfig(method=sphidx.METHOD_SPHERE, schedule=sphidx.SCHED_PLAIN)
@@ -128,18 +153,18 @@ def main():
         rp_c = buf.row_ptr.cpu().numpy()
         ids_c = buf.ids[: int(rp_c[-1])].cpu().numpy().view(np.uint32)
         same = bool(np.array_equal(rp_c, rp) and np.array_equal(ids_c, ids))
-        extra = {
+        out.update({
             "plain_launch": {"ms_per_step": round(ms_plain, 4), "queries_per_s": n / (ms_plain * 1e-3),
                              "query_ms": round(float(ph_plain[1] + ph_plain[2]), 4)},
             "cube_scan": {"ms_per_step": round(ms_cube, 4), "queries_per_s": n / (ms_cube * 1e-3),
                           "query_ms": round(float(ph_cube[1] + ph_cube[2]), 4), "same_result": same},
             "speedup_vs_plain": round(ms_plain / ms, 3),
             "speedup_vs_cube": round(ms_cube / ms, 3),
-        }
+        })
         log(f"plain: {ms_plain:.3f} ms/step; cube: {ms_cube:.3f} ms/step; cube result identical: {same}")
 
     # roofline of the dominant kernel (the write pass): algorithmic bytes =
-    # SoA points 16 B/pt + cell_start 4 B/cell + row_ptr 8 B/row + radius
+    # point records 16 B/pt + cell_start 4 B/cell + row_ptr 8 B/row + radius
     # 4 B/query + ids 4 B/pair, over the write launch's event-timed duration
     ncells = lat.ncells
     write_bytes = 16 * n + 4 * (ncells + 2) + 8 * (n + 1) + 4 * n + 4 * total
@@ -147,8 +172,8 @@ def main():
     traffic = _stored_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                "kernel": "query_kernel<1> (write pass)", "algorithmic_bytes": write_bytes,
-                "kernel_ms": round(float(phases[2]), 4)}
+                "kernel": "write pass (write_kernel + its fallback/long-row kernels)",
+                "algorithmic_bytes": write_bytes, "kernel_ms": round(float(phases[2]), 4)}
 
     cpu = None
     exact = None
@@ -169,19 +194,11 @@ def main():
         exact = bool(np.array_equal(ref.row_ptr, rp) and np.array_equal(ref.ids, ids))
         log(f"cpu oracle: {cpu['value']:.0f} queries/s on {cpu['cores']} threads; GPU bit-exact: {exact}")
 
-    out = {
+    out.update({
         "metric": METRIC,
         "value": round(n / (ms * 1e-3), 1),
         "unit": "queries/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
         "ms_per_step": round(ms, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int64",
-        "data": "synthetic",
         "config": {"workload": w.name, "points": n, "lattice": "128^3 clipped, cell edge 2^16 units",
                    "radius": "per point, uniform [0.5, 4] cells, 1/64-cell steps", "subcell_bits": 2,
                    "launch": dict(cfg, schedule="persistent")},
@@ -192,8 +209,279 @@ def main():
         "bit_exact_vs_oracle": exact,
         "roofline": roofline,
         "cpu_baseline": cpu,
-    }
-    out.update(extra)
+    })
+    del buf, lat, tab, dev, rad
+    torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------------------
+# K-NN under heavy load
+
+def leg_knn(args, out):
+    import numpy as np
+    import torch
+
+    from paper_cs_0608108_amd import sphidx, synth
+
+    w = synth.knn_clustered()
+    n, K = w.n, int(w.k[0])
+    cap = int(w.r_fx[0])
+    log(f"workload {w.name}: n={n} K={K} cap={cap}")
+    lat = sphidx.Lattice(w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask, n)
+    dev = [sphidx.to_dev_u32(a) for a in w.pts]
+    tab = sphidx.Tables(lat, 2, cap)
+    lat.build(*dev)
+    q = sphidx.make_queries(n, None, cap, K, sphidx.MODE_KNN, 0)
+    buf = sphidx.QueryBuffers(n, n * K, want_dist2=False)
+    ln = sphidx.LaunchConfig()
+
+    def step():
+        lat.build(*dev)
+        sphidx.query(lat, tab, q, buf, ln)
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    rp = buf.row_ptr.cpu().numpy()
+    log(f"knn sphere: {ms:.3f} ms/step, pairs {int(rp[-1])}")
+
+    # sphere vs cube on the same subsample of query centres (the cube scan
+    # looks at every object of the 17^3-cell cap cube, so all N would take long)
+    rows = sample_of(n, 65536, 3)
+    cen = tuple(sphidx.to_dev_u32(np.asarray(a)[rows]) for a in w.pts)
+    qs = sphidx.make_queries(len(rows), cen, cap, K, sphidx.MODE_KNN, 0)
+    bs = sphidx.QueryBuffers(len(rows), len(rows) * K, want_dist2=False)
+    sub = {}
+    for name, meth in (("sphere", sphidx.METHOD_SPHERE), ("cube", sphidx.METHOD_CUBE)):
+        lq = sphidx.LaunchConfig(method=meth)
+        sphidx.query(lat, tab, qs, bs, lq)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            sphidx.query(lat, tab, qs, bs, lq)
+        torch.cuda.synchronize()
+        sub[name] = (time.perf_counter() - t0) * 1e3 / 3
+        sub[name + "_rows"] = bs.host()[:2]
+    same_sub = bool(np.array_equal(sub["sphere_rows"][0], sub["cube_rows"][0])
+                    and np.array_equal(sub["sphere_rows"][1], sub["cube_rows"][1]))
+    srp, sids = sample_rows(rp, buf.ids, rows)
+    exact = None
+    if not args.no_cpu:
+        import oracle
+        L = oracle.Lattice(w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask)
+        g = oracle.Grid(L, w.pts)
+        ref = g.knn(K, cap, queries=tuple(np.asarray(a)[rows] for a in w.pts))
+        g.close()
+        exact = same_rows(srp, sids, ref)
+    log(f"knn subsample {len(rows)}: sphere {sub['sphere']:.3f} ms, cube {sub['cube']:.3f} ms, "
+        f"same {same_sub}, oracle rows bit-exact {exact}")
+    out["knn"] = {"workload": w.name, "ms_per_step": round(ms, 4), "queries_per_s": round(n / (ms * 1e-3), 1),
+                  "step": "rebuild + K-NN query (top-K rows, sorted by (dist2, id))",
+                  "subsample": {"queries": int(len(rows)), "sphere_ms": round(sub["sphere"], 4),
+                                "cube_ms": round(sub["cube"], 4),
+                                "speedup_vs_cube": round(sub["cube"] / sub["sphere"], 3),
+                                "sphere_equals_cube": same_sub},
+                  "sampled_rows_bit_exact_vs_oracle": exact}
+    del buf, bs, lat, tab, dev, cen
+    torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------------------
+# Moving-agent timesteps (one captured HIP graph per step)
+
+def leg_timestep(args, out):
+    import numpy as np
+    import torch
+
+    from paper_cs_0608108_amd import sphidx, synth, timestep
+
+    w = synth.agents_timestep()
+    n, seed, r = w.n, w.extra["seed"], int(w.r_fx[0])
+    log(f"workload {w.name}: n={n} r={r}")
+    sim = timestep.AgentSim(w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask, w.pts, r, seed)
+    sim.step()  # eager first step
+    torch.cuda.synchronize()
+    sim.capture()
+    for _ in range(2):
+        sim.replay()
+    torch.cuda.synchronize()
+    steps = args.timestep_steps
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    a.record()
+    for _ in range(steps):
+        sim.replay()
+    b.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    ms = a.elapsed_time(b) / steps
+    code, flags = sim.status()
+    rp = sim.buf.row_ptr.cpu().numpy()
+    pairs = int(rp[-1])
+    total_steps = sim.steps_done
+    log(f"timestep: {ms:.3f} ms/step (wall {wall:.3f}), pairs {pairs}, status {code}/{flags}")
+    exact = None
+    if not args.no_cpu:
+        import oracle
+        L = oracle.Lattice(w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask)
+        cur = w.pts
+        for t in range(total_steps):
+            cur = oracle.move(L, seed, t, cur)
+        got = sim.positions()
+        pos_ok = all(np.array_equal(got[k], cur[k]) for k in range(3))
+        rows = sample_of(n, 32768, 4)
+        srp, sids = sample_rows(rp, sim.buf.ids, rows)
+        g = oracle.Grid(L, cur)
+        ref = g.radius(r, queries=tuple(np.asarray(c)[rows] for c in cur))
+        g.close()
+        exact = bool(pos_ok and same_rows(srp, sids, ref))
+        log(f"timestep after {total_steps} steps: positions equal {pos_ok}, sampled rows bit-exact {exact}")
+    out["timestep"] = {"workload": w.name, "steps": steps, "ms_per_step": round(ms, 4),
+                       "wall_ms_per_step": round(wall, 4), "agent_queries_per_s": round(n / (ms * 1e-3), 1),
+                       "pairs_per_step": pairs, "pairs_per_s": round(pairs / (ms * 1e-3), 1),
+                       "step": "move + rebuild + count + scan + write + checksum, one graph replay",
+                       "status_ok": code == sphidx.OK and flags == 0,
+                       "positions_and_sampled_rows_bit_exact_vs_oracle": exact}
+    del sim
+    torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------------------
+# Serving loop
+
+def leg_serving(args, out):
+    import numpy as np
+    import torch
+
+    from paper_cs_0608108_amd import serving, sphidx, synth
+
+    w = synth.serving_lattice()
+    spec = w.lat
+    seed = w.extra["seed"]
+    log(f"workload {w.name}: n={w.n}")
+    lat = sphidx.Lattice(spec.log2_cells, spec.frac_bits, spec.cyclic_mask, w.n)
+    dev = [sphidx.to_dev_u32(a) for a in w.pts]
+    lat.build(*dev)
+    tab = sphidx.Tables(lat, 2, 16 * spec.edge)
+    nb = args.serving_batches
+    sizes = synth.serving_batch_sizes(seed, nb, 65536)
+    qs = [synth.serving_batch(spec, seed, i, int(s)) for i, s in enumerate(sizes)]
+    pool = 4 << 30
+
+    def make(arrivals):
+        return [serving.Batch(i, float(arrivals[i]), q, r, k) for i, (q, r, k) in enumerate(qs)]
+
+    fast = serving.GpuExecutor(lat, tab, args.serving_slots, int(sizes.max()), pool)
+    plain = serving.GpuExecutor(lat, tab, 1, int(sizes.max()), pool,
+                                launch=sphidx.LaunchConfig(schedule=sphidx.SCHED_PLAIN))
+    # warm-up (first launches, table upload) on a few batches
+    serving.run_admission_model(make(np.zeros(nb))[:4], fast, args.serving_slots, pool)
+    serving.run_admission_model(make(np.zeros(nb))[:4], plain, 1, pool)
+    torch.cuda.synchronize()
+    # capacity: every batch queued at t = 0
+    res = {}
+    for name, ex, slots in (("continuous", fast, args.serving_slots), ("plain_per_batch", plain, 1)):
+        bs = make(np.zeros(nb))
+        serving.run_admission_model(bs, ex, slots, pool)
+        res[name + "_saturated"] = serving.latency_stats(bs)
+    cap_qps = res["plain_per_batch_saturated"]["queries_per_s"]
+    rate = 0.7 * cap_qps / float(sizes.mean())  # batches/s: 70% of the plain path's capacity
+    arr = np.cumsum(synth.serving_interarrivals(seed, nb, rate))
+    for name, ex, slots in (("continuous", fast, args.serving_slots), ("plain_per_batch", plain, 1)):
+        bs = make(arr)
+        adm = serving.run_admission_model(bs, ex, slots, pool)
+        st = serving.latency_stats(bs)
+        st["pool_peak_bytes"] = adm.pool.peak
+        st["rejected"] = sum(b.rejected for b in bs)
+        res[name + "_poisson"] = st
+    pairs = sum(b.pairs for b in bs)
+    exact = None
+    if not args.no_cpu:
+        # the last run's rows of a few batches against the oracle
+        import oracle
+        L = oracle.Lattice(spec.log2_cells, spec.frac_bits, spec.cyclic_mask)
+        g = oracle.Grid(L, w.pts)
+        small = [i for i in np.argsort(sizes)[: max(3, nb // 10)]]
+        chk = make(np.zeros(nb))
+        chk = [chk[i] for i in small]
+        serving.run_admission_model(chk, fast, args.serving_slots, pool, keep=True)
+        exact = True
+        for b in chk:
+            ref = g.mixed(b.k, b.radius, queries=b.centres)
+            rp, ids = b.result
+            exact &= bool(np.array_equal(rp, ref.row_ptr) and np.array_equal(ids, ref.ids))
+        g.close()
+    r = res
+    log(f"serving: continuous p50 {r['continuous_poisson']['p50_ms']:.2f} p99 {r['continuous_poisson']['p99_ms']:.2f} "
+        f"ms; plain p50 {r['plain_per_batch_poisson']['p50_ms']:.2f} p99 {r['plain_per_batch_poisson']['p99_ms']:.2f}"
+        f" ms; capacity {r['continuous_saturated']['queries_per_s']:.0f} vs {cap_qps:.0f} q/s; oracle {exact}")
+    out["serving"] = {"workload": w.name, "batches": nb, "slots": args.serving_slots,
+                      "mean_batch": float(sizes.mean()), "median_batch": float(np.median(sizes)),
+                      "poisson_rate_batches_per_s": round(rate, 2),
+                      "pairs_last_run": int(pairs), **res,
+                      "p99_speedup_vs_plain": round(r["plain_per_batch_poisson"]["p99_ms"]
+                                                    / r["continuous_poisson"]["p99_ms"], 3),
+                      "sampled_batches_bit_exact_vs_oracle": exact}
+    del fast, plain, lat, tab, dev
+    torch.cuda.empty_cache()
+
+
+def copy_calibration(nbytes):
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(5):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / 5
+    print(json.dumps({"copy_bytes": nbytes, "ms": ms, "GBps_read_plus_write": 2 * nbytes / (ms * 1e-3) / 1e9}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--legs", default=",".join(LEGS), help="comma list of " + ",".join(LEGS))
+    ap.add_argument("--no-tune", action="store_true", help="use the cached/default launch configuration")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs (profiling runs)")
+    ap.add_argument("--no-baselines", action="store_true", help="skip the plain-launch and cube-scan legs")
+    ap.add_argument("--timestep-steps", type=int, default=100)
+    ap.add_argument("--serving-batches", type=int, default=120)
+    ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--copy-bytes", type=int, default=0, help="only time a plain device copy of this size")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path; run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    torch.cuda.set_device(0)
+    if args.copy_bytes:
+        copy_calibration(args.copy_bytes)
+        return
+    legs = [x for x in args.legs.split(",") if x]
+    for x in legs:
+        if x not in LEGS:
+            sys.exit(f"unknown leg {x}")
+    out = {"metric": METRIC, "value": None, "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int64", "data": "synthetic"}
+    for x in legs:
+        log(f"== leg {x}")
+        {"c2": leg_c2, "knn": leg_knn, "timestep": leg_timestep, "serving": leg_serving}[x](args, out)
     print(json.dumps(out))
 
 

@@ -244,6 +244,13 @@ sphidx_status sphidx_cube_scan_knn(const sphidx_lattice* lat, const sphidx_queri
 sphidx_status sphidx_move_agents(const sphidx_lattice_desc* desc, uint64_t seed, uint32_t step,
                                  uint32_t* x_dev, uint32_t* y_dev, uint32_t* z_dev, uint32_t n, void* stream);
 
+/* The same with the step read from *step_dev (uint32, device) and the
+ * counter advanced by one after the move, in stream order: a timestep
+ * captured once in a HIP graph draws new displacements on every replay. */
+sphidx_status sphidx_move_agents_counted(const sphidx_lattice_desc* desc, uint64_t seed, uint32_t* step_dev,
+                                         uint32_t* x_dev, uint32_t* y_dev, uint32_t* z_dev, uint32_t n,
+                                         void* stream);
+
 /* out_dev[0] = sum of row sizes, out_dev[1] = sum_i mix64((i << 32) | size_i)
  * (mod 2^64), from row_ptr (Q + 1 entries).  out_dev is uint64[2]. */
 sphidx_status sphidx_count_checksum(const int64_t* row_ptr_dev, uint32_t Q, uint64_t* out_dev, void* stream);

@@ -437,7 +437,15 @@ sphidx_status sphidx_move_agents(const sphidx_lattice_desc* desc, uint64_t seed,
                                  uint32_t* y_dev, uint32_t* z_dev, uint32_t n, void* stream) {
     if (!desc_ok(desc)) return SPHIDX_ERR_INVALID_ARG;
     if (n > 0 && (!x_dev || !y_dev || !z_dev)) return SPHIDX_ERR_INVALID_ARG;
-    return dev_err(launch_move_agents(*desc, seed, step, x_dev, y_dev, z_dev, n, (hipStream_t)stream));
+    return dev_err(launch_move_agents(*desc, seed, step, nullptr, x_dev, y_dev, z_dev, n, (hipStream_t)stream));
+}
+
+sphidx_status sphidx_move_agents_counted(const sphidx_lattice_desc* desc, uint64_t seed, uint32_t* step_dev,
+                                         uint32_t* x_dev, uint32_t* y_dev, uint32_t* z_dev, uint32_t n,
+                                         void* stream) {
+    if (!desc_ok(desc) || !step_dev) return SPHIDX_ERR_INVALID_ARG;
+    if (n > 0 && (!x_dev || !y_dev || !z_dev)) return SPHIDX_ERR_INVALID_ARG;
+    return dev_err(launch_move_agents(*desc, seed, 0, step_dev, x_dev, y_dev, z_dev, n, (hipStream_t)stream));
 }
 
 sphidx_status sphidx_count_checksum(const int64_t* row_ptr_dev, uint32_t Q, uint64_t* out_dev, void* stream) {

@@ -21,6 +21,7 @@ struct MoveArgs {
     uint32_t dmax;
     uint64_t seed;
     uint32_t step;
+    const uint32_t* step_dev;  // when set, the step is read here
     uint32_t n;
     uint32_t* v[3];
 };
@@ -28,10 +29,11 @@ struct MoveArgs {
 __global__ __launch_bounds__(256) void move_kernel(MoveArgs a) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
+    const uint32_t step = a.step_dev ? *a.step_dev : a.step;
     const uint64_t span = 2ull * a.dmax + 1ull;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        uint64_t h = counter_hash(a.seed, 1000ull + 3ull * a.step + (uint64_t)k, i);
+        uint64_t h = counter_hash(a.seed, 1000ull + 3ull * step + (uint64_t)k, i);
         int64_t delta = (int64_t)(((h >> 32) * span) >> 32) - (int64_t)a.dmax;
         int64_t w = (int64_t)1 << a.wbits[k];
         int64_t nv = (int64_t)a.v[k][i] + delta;
@@ -42,6 +44,8 @@ __global__ __launch_bounds__(256) void move_kernel(MoveArgs a) {
         a.v[k][i] = (uint32_t)nv;
     }
 }
+
+__global__ void advance_step_kernel(uint32_t* step) { *step += 1u; }
 
 __global__ __launch_bounds__(256) void checksum_kernel(const int64_t* __restrict__ row_ptr, uint32_t Q,
                                                        unsigned long long* out) {
@@ -64,10 +68,10 @@ __global__ __launch_bounds__(256) void checksum_kernel(const int64_t* __restrict
 
 }  // namespace
 
-hipError_t launch_move_agents(const sphidx_lattice_desc& d, uint64_t seed, uint32_t step, uint32_t* x,
-                              uint32_t* y, uint32_t* z, uint32_t n, hipStream_t st) {
-    if (n == 0) return hipSuccess;
+hipError_t launch_move_agents(const sphidx_lattice_desc& d, uint64_t seed, uint32_t step, uint32_t* step_dev,
+                              uint32_t* x, uint32_t* y, uint32_t* z, uint32_t n, hipStream_t st) {
     MoveArgs a;
+    a.step_dev = step_dev;
     for (int k = 0; k < 3; ++k) a.wbits[k] = d.log2_cells[k] + d.frac_bits;
     a.cyc = d.cyclic_mask;
     a.dmax = (1u << d.frac_bits) / 4u;
@@ -77,7 +81,9 @@ hipError_t launch_move_agents(const sphidx_lattice_desc& d, uint64_t seed, uint3
     a.v[0] = x;
     a.v[1] = y;
     a.v[2] = z;
-    move_kernel<<<(n + 255) / 256, 256, 0, st>>>(a);
+    if (n > 0) move_kernel<<<(n + 255) / 256, 256, 0, st>>>(a);
+    // stream order: the counter advances after every object has moved
+    if (step_dev) advance_step_kernel<<<1, 1, 0, st>>>(step_dev);
     return hipGetLastError();
 }
 

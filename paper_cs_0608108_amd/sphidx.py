@@ -83,6 +83,7 @@ SIGNATURES = {
     "sphidx_cube_scan_radius": (ctypes.c_int, [P, ctypes.POINTER(Queries), ctypes.POINTER(CSRDesc), P]),
     "sphidx_cube_scan_knn": (ctypes.c_int, [P, ctypes.POINTER(Queries), ctypes.POINTER(CSRDesc), P]),
     "sphidx_move_agents": (ctypes.c_int, [ctypes.POINTER(LatticeDesc), U64, U32, P, P, P, U32, P]),
+    "sphidx_move_agents_counted": (ctypes.c_int, [ctypes.POINTER(LatticeDesc), U64, P, P, P, P, U32, P]),
     "sphidx_count_checksum": (ctypes.c_int, [P, U32, P, P]),
     "sphidx_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sphidx_version": (ctypes.c_char_p, []),
@@ -375,6 +376,11 @@ def run(lat, tab, q: Queries, launch: LaunchConfig | None = None, want_dist2=Tru
 def move_agents(desc: LatticeDesc, seed, step, x, y, z, stream=None):
     check(load().sphidx_move_agents(ctypes.byref(desc), int(seed), int(step), _ptr(x), _ptr(y), _ptr(z),
                                     int(x.numel()), _stream(stream)), "move_agents")
+
+
+def move_agents_counted(desc: LatticeDesc, seed, step_dev, x, y, z, stream=None):
+    check(load().sphidx_move_agents_counted(ctypes.byref(desc), int(seed), _ptr(step_dev), _ptr(x), _ptr(y),
+                                            _ptr(z), int(x.numel()), _stream(stream)), "move_agents_counted")
 
 
 def count_checksum(row_ptr, Q, out, stream=None):
