@@ -33,6 +33,7 @@ B bytes (the calibration run for the HBM byte counters).
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -118,38 +119,47 @@ def leg_c2(args, out):
     log(f"launch config: {cfg}")
 
     def timed(ln, steps, warmup):
+        """Wall ms/step, mean phase ms (rebuild, count pass, write pass) and
+        mean ms of the count and write kernels alone (events the library
+        records around them on the launch stream)."""
         for _ in range(warmup):
             step(ln)
         torch.cuda.synchronize()
-        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+        E = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+        ev = [[E() for _ in range(4)] for _ in range(steps)]
+        kev = [[E() for _ in range(4)] for _ in range(steps)]
+        lc = [dataclasses.replace(ln, events=(k[0], k[1])) for k in kev]
+        lw = [dataclasses.replace(ln, events=(k[2], k[3])) for k in kev]
         t0 = time.perf_counter()
         for s in range(steps):
             e = ev[s]
             e[0].record()
             lat.build(*dev)
             e[1].record()
-            sphidx.count(lat, tab, q, buf, ln)
+            sphidx.count(lat, tab, q, buf, lc[s])
             e[2].record()
-            sphidx.write(lat, tab, q, buf, ln)
+            sphidx.write(lat, tab, q, buf, lw[s])
             e[3].record()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         ph = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(3)] for e in ev])
-        return (t1 - t0) * 1e3 / steps, ph.mean(axis=0)
+        kk = np.array([[k[0].elapsed_time(k[1]), k[2].elapsed_time(k[3])] for k in kev])
+        return (t1 - t0) * 1e3 / steps, ph.mean(axis=0), kk.mean(axis=0)
 
-    ms, phases = timed(tuned, args.steps, args.warmup)
+    ms, phases, kern = timed(tuned, args.steps, args.warmup)
     code, flags = lat.status()
     assert code == sphidx.OK, (code, flags)
     rp = buf.row_ptr.cpu().numpy()
     ids = buf.ids[: int(rp[-1])].cpu().numpy().view(np.uint32)
-    log(f"persistent: {ms:.3f} ms/step; build {phases[0]:.3f} count {phases[1]:.3f} write {phases[2]:.3f} ms")
+    log(f"persistent: {ms:.3f} ms/step; build {phases[0]:.3f} count {phases[1]:.3f} write {phases[2]:.3f} ms; "
+        f"count kernel {kern[0]:.3f} write kernel {kern[1]:.3f} ms")
 
     if not args.no_baselines:
         k2 = max(3, args.steps // 2)
         plain = sphidx.LaunchConfig(method=sphidx.METHOD_SPHERE, schedule=sphidx.SCHED_PLAIN)
-        ms_plain, ph_plain = timed(plain, k2, 1)
+        ms_plain, ph_plain, _ = timed(plain, k2, 1)
         cube = sphidx.LaunchConfig(method=sphidx.METHOD_CUBE, schedule=sphidx.SCHED_PERSISTENT, **cfg)
-        ms_cube, ph_cube = timed(cube, k2, 1)
+        ms_cube, ph_cube, _ = timed(cube, k2, 1)
         rp_c = buf.row_ptr.cpu().numpy()
         ids_c = buf.ids[: int(rp_c[-1])].cpu().numpy().view(np.uint32)
         same = bool(np.array_equal(rp_c, rp) and np.array_equal(ids_c, ids))
@@ -163,17 +173,19 @@ def leg_c2(args, out):
         })
         log(f"plain: {ms_plain:.3f} ms/step; cube: {ms_cube:.3f} ms/step; cube result identical: {same}")
 
-    # roofline of the dominant kernel (the write pass): algorithmic bytes =
+    # roofline of the dominant kernel, the write kernel: algorithmic bytes =
     # point records 16 B/pt + cell_start 4 B/cell + row_ptr 8 B/row + radius
-    # 4 B/query + ids 4 B/pair, over the write launch's event-timed duration
+    # 4 B/query + descriptors 64 B/query + ids 4 B/pair, over its own
+    # event-timed duration on the launch stream
     ncells = lat.ncells
-    write_bytes = 16 * n + 4 * (ncells + 2) + 8 * (n + 1) + 4 * n + 4 * total
-    achieved = write_bytes / (phases[2] * 1e-3) / 1e9
+    write_bytes = 16 * n + 4 * (ncells + 2) + 8 * (n + 1) + 4 * n + 64 * n + 4 * total
+    achieved = write_bytes / (kern[1] * 1e-3) / 1e9
     traffic = _stored_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                "kernel": "write pass (write_kernel + its fallback/long-row kernels)",
-                "algorithmic_bytes": write_bytes, "kernel_ms": round(float(phases[2]), 4)}
+                "kernel": "write_kernel (write pass, sphere tables)",
+                "algorithmic_bytes": write_bytes, "kernel_ms": round(float(kern[1]), 4),
+                "count_kernel_ms": round(float(kern[0]), 4)}
 
     cpu = None
     exact = None

@@ -199,6 +199,11 @@ typedef struct {
                                  1 = off, 2 = on: cells wholly inside the sphere are counted whole */
     uint32_t* stats_dev; /* optional uint32[4*Q]: per query walked entries, kept cells,
                             candidate objects tested, cube cells (count pass) */
+    void* event_begin;   /* optional hipEvent_t, recorded on the stream just before the pass's main
+                            kernel (count pass: the count kernel; write pass: the write kernel,
+                            or the top-K kernel when every row is K-NN), for timing it alone */
+    void* event_end;     /* optional hipEvent_t, recorded just after that kernel (neither event is
+                            recorded when Q = 0) */
 } sphidx_launch;
 
 /* Bytes of device scratch a query call on Q queries needs. */

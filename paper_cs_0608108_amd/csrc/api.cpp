@@ -88,6 +88,7 @@ TabArgs tab_args(const sphidx_tables* t) {
 struct Launch {
     uint32_t method, persistent, waves, tile, bpc, cap, tab_lds, interior;
     uint32_t* stats;
+    hipEvent_t ev_begin, ev_end;
 };
 
 sphidx_status resolve_launch(const sphidx_launch* in, const sphidx_tables* tab, Launch& o) {
@@ -101,6 +102,8 @@ sphidx_status resolve_launch(const sphidx_launch* in, const sphidx_tables* tab, 
     o.interior = in ? in->interior : 0u;
     if (o.interior > 2) return SPHIDX_ERR_INVALID_ARG;
     o.stats = in ? in->stats_dev : nullptr;
+    o.ev_begin = in ? (hipEvent_t)in->event_begin : nullptr;
+    o.ev_end = in ? (hipEvent_t)in->event_end : nullptr;
     if (in && in->schedule > SPHIDX_SCHED_PERSISTENT) return SPHIDX_ERR_INVALID_ARG;
     if (o.method > SPHIDX_METHOD_CUBE) return SPHIDX_ERR_INVALID_ARG;
     if (!(o.waves == 1 || o.waves == 2 || o.waves == 4)) return SPHIDX_ERR_INVALID_ARG;
@@ -218,11 +221,11 @@ sphidx_status run_pass(int pass, const sphidx_lattice* lat, const sphidx_tables*
     // second extent per row: worth it once cells hold an object or more
     A.interior = ln.interior == 2 || (ln.interior == 0 && (uint64_t)lat->n >= (uint64_t)lat->ncells);
     if (pass == 0) {
-        s = dev_err(launch_query_pass(0, L, T, A, ln.waves, ln.bpc, st));
+        s = dev_err(launch_query_pass(0, L, T, A, ln.waves, ln.bpc, st, ln.ev_begin, ln.ev_end));
         if (s != SPHIDX_OK) return s;
         return dev_err(launch_scan_i64(csr->row_ptr_dev, q->count, scan_tmp_of(csr, q->count), st));
     }
-    return dev_err(launch_query_pass(1, L, T, A, ln.waves, ln.bpc, st));
+    return dev_err(launch_query_pass(1, L, T, A, ln.waves, ln.bpc, st, ln.ev_begin, ln.ev_end));
 }
 
 }  // namespace

@@ -998,7 +998,10 @@ size_t query_lds_bytes(int pass, uint32_t cap, uint32_t waves, size_t table_byte
 }
 
 hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const QArgs& q,
-                             uint32_t waves_per_block, uint32_t blocks_per_cu, hipStream_t st) {
+                             uint32_t waves_per_block, uint32_t blocks_per_cu, hipStream_t st,
+                             hipEvent_t ev_begin, hipEvent_t ev_end) {
+    // optional timing events around the pass's main kernel
+    auto mark = [st](hipEvent_t ev) { return ev ? hipEventRecord(ev, st) : hipSuccess; };
     const size_t tb = T.lds ? (((size_t)T.total * 4 + 15) & ~(size_t)15) : 0;
     const int variant = !T.has ? 0 : (T.lds ? 2 : 1);
     clear_counters_kernel<<<1, 256, 0, st>>>(q.queues);
@@ -1016,8 +1019,10 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
     ql.persistent = 1;
     ql.tile = 1;
     if (pass == 0) {
+        if ((e = mark(ev_begin)) != hipSuccess) return e;
         e = launch_ptr(SPHIDX_PICK(count_kernel, variant, kSphere, , false), q.Q, q, w, b,
                        query_lds_bytes(0, q.sort_cap, w, tb), st, L, T);
+        if (e == hipSuccess) e = mark(ev_end);
         if (e != hipSuccess || variant == 0) return e;
         return launch_ptr((const void*)count_kernel<kCube, false, true>, 0, ql, w, b,
                           query_lds_bytes(0, q.sort_cap, w, 0), st, L, T);
@@ -1025,7 +1030,9 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
     const size_t sh1 = query_lds_bytes(1, q.sort_cap, w, tb);
     const size_t sh2 = query_lds_bytes(2, q.sort_cap, w, tb);
     if (q.mode != SPHIDX_MODE_KNN) {
+        if ((e = mark(ev_begin)) != hipSuccess) return e;
         e = launch_ptr(SPHIDX_PICK(write_kernel, variant, kSphere, , false), q.Q, q, w, b, sh1, st, L, T);
+        if (e == hipSuccess) e = mark(ev_end);
         if (e != hipSuccess) return e;
         if (variant != 0) {
             e = launch_ptr((const void*)write_kernel<kCube, false, true>, 0, ql, w, b,
@@ -1035,5 +1042,7 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
         // K-NN rows of a mixed batch and long radius rows, from the list
         return launch_ptr(SPHIDX_PICK(topm_kernel, variant, kEither, , true), 0, ql, w, b, sh2, st, L, T);
     }
-    return launch_ptr(SPHIDX_PICK(topm_kernel, variant, kEither, , false), q.Q, q, w, b, sh2, st, L, T);
+    if ((e = mark(ev_begin)) != hipSuccess) return e;
+    e = launch_ptr(SPHIDX_PICK(topm_kernel, variant, kEither, , false), q.Q, q, w, b, sh2, st, L, T);
+    return e == hipSuccess ? mark(ev_end) : e;
 }

@@ -127,7 +127,8 @@ hipError_t launch_build(const sphidx_lattice* lat, const uint32_t* x, const uint
 hipError_t launch_scan_i64(int64_t* data, uint32_t n, void* tmp, hipStream_t st);
 size_t scan_i64_tmp_bytes(uint32_t n);
 hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const QArgs& q,
-                             uint32_t waves_per_block, uint32_t blocks_per_cu, hipStream_t st);
+                             uint32_t waves_per_block, uint32_t blocks_per_cu, hipStream_t st,
+                             hipEvent_t ev_begin, hipEvent_t ev_end);
 hipError_t launch_move_agents(const sphidx_lattice_desc& d, uint64_t seed, uint32_t step, uint32_t* step_dev,
                               uint32_t* x, uint32_t* y, uint32_t* z, uint32_t n, hipStream_t st);
 hipError_t launch_count_checksum(const int64_t* row_ptr, uint32_t Q, uint64_t* out, hipStream_t st);

@@ -54,7 +54,7 @@ class CSRDesc(ctypes.Structure):
 class LaunchDesc(ctypes.Structure):
     _fields_ = [("method", U32), ("schedule", U32), ("waves_per_block", U32), ("tile", U32),
                 ("blocks_per_cu", U32), ("sort_cap", U32), ("table_in_lds", U32), ("interior", U32),
-                ("stats_dev", P)]
+                ("stats_dev", P), ("event_begin", P), ("event_end", P)]
 
 
 # Every symbol include/sphidx.h declares, with its ctypes signature.
@@ -270,6 +270,7 @@ class LaunchConfig:
     table_in_lds: int = 0
     interior: int = 0
     stats: torch.Tensor | None = None
+    events: tuple | None = None  # (begin, end) torch.cuda.Event around the pass's main kernel
 
     def c(self) -> LaunchDesc:
         d = LaunchDesc()
@@ -278,6 +279,11 @@ class LaunchConfig:
         d.sort_cap, d.table_in_lds = self.sort_cap, self.table_in_lds
         d.interior = self.interior
         d.stats_dev = None if self.stats is None else self.stats.data_ptr()
+        if self.events is not None:
+            for ev in self.events:
+                if not ev.cuda_event:  # torch creates the HIP event at its first record
+                    ev.record()
+            d.event_begin, d.event_end = self.events[0].cuda_event, self.events[1].cuda_event
         return d
 
 
