@@ -867,8 +867,27 @@ __global__ __launch_bounds__(256) void topm_kernel(LatArgs L, TabArgs T, QArgs A
         uint64_t ld = 0;
         uint32_t li = 0;
         uint32_t written = 0;
+        // objects per cell around the centre: the home cell's count, with the
+        // lattice mean as a floor (K-NN rows carry no density of their own)
+        float dens = (float)L.n / (float)(L.ncells ? L.ncells : 1u);
+        if (s.flags & F_SPHERE) {
+            const uint32_t home = pack_cell(L, s.c[0], s.c[1], s.c[2]);
+            dens = fmaxf(dens, (float)(L.cs[home + 1] - L.cs[home]));
+        }
+        const float e = (float)(1u << L.F);
         while (written < rowlen) {
             const uint32_t M = min(cap, rowlen - written);
+            const uint32_t target = written + M;
+            // first bound: the radius expected to hold `target` objects (a
+            // radius row: the row's own mean density over its ball); grown
+            // and the window restarted whenever fewer than M lie within it
+            float rho;
+            if (s.flags & F_KNN)
+                rho = 1.25f * e * cbrtf(0.2387f * (float)target / fmaxf(dens, 1e-6f)) + 0.5f * e;
+            else
+                rho = 1.1f * (float)s.r * cbrtf((float)target / (float)rowlen);
+            uint64_t B = rho >= (float)s.r ? s.r2 : min(s.r2, (uint64_t)((double)rho * (double)rho));
+            if (!(s.flags & F_SPHERE)) B = s.r2;  // the bounding cube is scanned whole anyway
             uint32_t m = 0;
             uint64_t bdd = kMaxD2;
             uint32_t bii = kMaxId;
@@ -876,7 +895,7 @@ __global__ __launch_bounds__(256) void topm_kernel(LatArgs L, TabArgs T, QArgs A
             auto visit = [&](bool act, uint32_t p, const uint4& P) -> bool {
                 const uint64_t d2 = obj_dist2(aw, s, P);
                 const uint32_t id = P.w;
-                bool cv = act && d2 <= s.r2 && p != s.self;
+                bool cv = act && d2 <= B && p != s.self;
                 if (cv && has_lower) cv = key_less(ld, li, d2, id);
                 if (cv && m == M) cv = key_less(d2, id, bdd, bii);
                 const uint64_t bm = __ballot(cv);
@@ -935,10 +954,19 @@ __global__ __launch_bounds__(256) void topm_kernel(LatArgs L, TabArgs T, QArgs A
                 }
                 return false;
             };
-            walk<METHOD, TLDS, false, true>(L, T, tab_lds, s, walked, [&]() { return m == M ? bdd : s.r2; },
-                                            [&](const RowRef& r) -> bool {
-                return for_candidates(L, r.st0, r.cnt0, r.st1, r.cnt1, own, cand, visit);
-            });
+            // every object within B is visited and nothing beyond B is kept,
+            // so M kept means they are the M nearest above the lower bound
+            for (;;) {
+                walk<METHOD, TLDS, false, true>(L, T, tab_lds, s, walked, [&]() { return m == M ? bdd : B; },
+                                                [&](const RowRef& r) -> bool {
+                    return for_candidates(L, r.st0, r.cnt0, r.st1, r.cnt1, own, cand, visit);
+                });
+                if (m == M || B >= s.r2) break;
+                B = min(s.r2, B + B + (B >> 2) + 1u);  // radius x1.5
+                m = 0;
+                bdd = kMaxD2;
+                bii = kMaxId;
+            }
             wave_sync();
             const uint32_t got = min(m, M);
             store_sorted(A, td, tix, got, rb + written);
