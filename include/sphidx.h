@@ -176,9 +176,20 @@ typedef struct {
     uint32_t* ids_dev;    /* capacity entries */
     int64_t* dist2_dev;   /* capacity entries, or NULL when not wanted */
     int64_t capacity;     /* entries available in ids (and dist2) */
-    void* workspace_dev;  /* sphidx_query_workspace_bytes(Q) bytes, 256-byte aligned */
-    size_t workspace_bytes;
+    void* workspace_dev;  /* at least sphidx_query_workspace_bytes(Q) bytes, 256-byte aligned; */
+    size_t workspace_bytes; /* bytes beyond that minimum are the stash (below) */
 } sphidx_csr;
+
+/* The stash.  Workspace bytes beyond the minimum let the count pass keep
+ * each radius row of at most sort_cap objects, already sorted, so that the
+ * write pass copies it into place instead of walking the tables again.  A
+ * row needs 4 bytes per object (12 when the count call passes dist2_dev).
+ * Rows that do not fit are walked again by the write pass, so any size is
+ * correct; sphidx_query_stash_bytes gives the size that keeps every row.
+ * The write pass must use the workspace the count pass used, unchanged.
+ * Only the persistent schedule stashes (a plain launch's waves are too
+ * short-lived to fill allocation chunks). */
+size_t sphidx_query_stash_bytes(uint64_t pairs, int want_dist2);
 
 #define SPHIDX_METHOD_SPHERE 0u /* sphere-table walk (falls back to the cube where the tables do not apply) */
 #define SPHIDX_METHOD_CUBE 1u   /* bin-lattice bounding-cube scan: the paper's baseline */
@@ -200,10 +211,11 @@ typedef struct {
     uint32_t* stats_dev; /* optional uint32[4*Q]: per query walked entries, kept cells,
                             candidate objects tested, cube cells (count pass) */
     void* event_begin;   /* optional hipEvent_t, recorded on the stream just before the pass's main
-                            kernel (count pass: the count kernel; write pass: the write kernel,
-                            or the top-K kernel when every row is K-NN), for timing it alone */
+                            kernel (count pass: the count kernel; write pass: the stash copy and
+                            the write kernel, or the top-K kernel when every row is K-NN) */
     void* event_end;     /* optional hipEvent_t, recorded just after that kernel (neither event is
                             recorded when Q = 0) */
+    uint32_t no_stash;   /* 1: never keep rows in the workspace stash (see sphidx_csr) */
 } sphidx_launch;
 
 /* Bytes of device scratch a query call on Q queries needs. */

@@ -1,4 +1,5 @@
 // C ABI of libsphidx: argument validation, workspace layout and dispatch.
+#include <algorithm>
 #include <cstring>
 #include <new>
 
@@ -86,7 +87,7 @@ TabArgs tab_args(const sphidx_tables* t) {
 }
 
 struct Launch {
-    uint32_t method, persistent, waves, tile, bpc, cap, tab_lds, interior;
+    uint32_t method, persistent, waves, tile, bpc, cap, tab_lds, interior, no_stash;
     uint32_t* stats;
     hipEvent_t ev_begin, ev_end;
 };
@@ -101,6 +102,8 @@ sphidx_status resolve_launch(const sphidx_launch* in, const sphidx_tables* tab, 
     o.tab_lds = in ? in->table_in_lds : 0u;
     o.interior = in ? in->interior : 0u;
     if (o.interior > 2) return SPHIDX_ERR_INVALID_ARG;
+    o.no_stash = in ? in->no_stash : 0u;
+    if (o.no_stash > 1) return SPHIDX_ERR_INVALID_ARG;
     o.stats = in ? in->stats_dev : nullptr;
     o.ev_begin = in ? (hipEvent_t)in->event_begin : nullptr;
     o.ev_end = in ? (hipEvent_t)in->event_end : nullptr;
@@ -112,14 +115,17 @@ sphidx_status resolve_launch(const sphidx_launch* in, const sphidx_tables* tab, 
     if (o.method == SPHIDX_METHOD_SPHERE && !tab) return SPHIDX_ERR_INVALID_ARG;
     if (o.method == SPHIDX_METHOD_CUBE) o.tab_lds = 0;
     size_t tab_bytes = (o.tab_lds && tab) ? (tab->h_rows.size() * 4 + 15) / 16 * 16 : 0;
-    if (query_lds_bytes(2, o.cap, o.waves, 0) > kMaxBlockLds) return SPHIDX_ERR_INVALID_ARG;
-    if (o.tab_lds && query_lds_bytes(2, o.cap, o.waves, tab_bytes) > kMaxBlockLds) return SPHIDX_ERR_CAPACITY;
+    for (int pass = 1; pass <= 3; ++pass) {
+        if (query_lds_bytes(pass, o.cap, o.waves, 0) > kMaxBlockLds) return SPHIDX_ERR_INVALID_ARG;
+        if (o.tab_lds && query_lds_bytes(pass, o.cap, o.waves, tab_bytes) > kMaxBlockLds) return SPHIDX_ERR_CAPACITY;
+    }
     return SPHIDX_OK;
 }
 
-// Query workspace: counters | descriptors[Q] | longq[Q] | fbq[Q] | scan partials.
+// Query workspace: counters | descriptors[Q] | longq[Q] | fbq[Q] | walkq[Q] |
+// soff[Q] | scan partials, then the stash: every byte beyond the minimum.
 struct QLayout {
-    size_t counters, desc, longq, fbq, scan, total;
+    size_t counters, desc, longq, fbq, walkq, soff, scan, total;
 };
 
 QLayout query_layout(uint32_t Q) {
@@ -134,6 +140,8 @@ QLayout query_layout(uint32_t Q) {
     l.desc = take((size_t)Q * 64);
     l.longq = take((size_t)Q * 4);
     l.fbq = take((size_t)Q * 4);
+    l.walkq = take((size_t)Q * 4);
+    l.soff = take((size_t)Q * 4);
     l.scan = take(scan_i64_tmp_bytes(Q));
     l.total = off;
     return l;
@@ -174,17 +182,50 @@ QArgs q_args(const sphidx_queries* q, sphidx_csr* csr, const Launch& ln) {
     const QLayout ql = query_layout(q->count);
     char* ws = (char*)csr->workspace_dev;
     A.queues = (uint32_t*)(ws + ql.counters);
-    A.long_count = A.queues + SPHIDX_NQSETS * SPHIDX_NQUEUE * SPHIDX_QSTRIDE;
-    A.fb_count = A.long_count + SPHIDX_QSTRIDE;
+    uint32_t* lists = A.queues + SPHIDX_NQSETS * SPHIDX_NQUEUE * SPHIDX_QSTRIDE;
+    A.long_count = lists;
+    A.fb_count = lists + SPHIDX_QSTRIDE;
+    A.walk_count = lists + 2 * SPHIDX_QSTRIDE;
+    A.stash_hdr = lists + 3 * SPHIDX_QSTRIDE;
+    A.stash_ctr = lists + SPHIDX_NLISTS * SPHIDX_QSTRIDE;
     A.longq = (uint32_t*)(ws + ql.longq);
     A.fbq = (uint32_t*)(ws + ql.fbq);
+    A.walkq = (uint32_t*)(ws + ql.walkq);
+    A.soff = (uint32_t*)(ws + ql.soff);
     A.desc = (uint4*)(ws + ql.desc);
+    A.stash_base = ws + ql.total;
     A.stats = ln.stats;
     A.method = ln.method;
     A.persistent = ln.persistent;
     A.tile = ln.tile;
     A.sort_cap = ln.cap;
     return A;
+}
+
+// Count pass: size the stash from the bytes beyond the minimum workspace.
+// Rows are kept as ids (plus dist^2 when this call asks for them) in
+// NQUEUE regions, one per XCD, handed out to waves in chunks.
+void plan_stash(QArgs& A, const sphidx_csr* csr, const Launch& ln, uint32_t mode, bool interior_forced) {
+    A.stash = 0;
+    // plain launches: a wave lives for `tile` queries only, too short to
+    // fill a chunk of its own
+    if (ln.no_stash || !ln.persistent || interior_forced || mode == SPHIDX_MODE_KNN) return;
+    const size_t base = query_layout(A.Q).total;
+    if (csr->workspace_bytes <= base + 4096) return;
+    const size_t room = csr->workspace_bytes - base - 512;  // alignment slack
+    const bool d2 = csr->dist2_dev != nullptr;
+    uint64_t elems = d2 ? room / 12 : room / 4;
+    elems = std::min<uint64_t>(elems, 0xFFFFFF00ull);
+    const uint64_t region = elems / SPHIDX_NQUEUE;
+    if (region < 4096) return;
+    A.stash = 1;
+    A.stash_region = (uint32_t)region;
+    A.stash_ids = (uint32_t*)A.stash_base;
+    A.stash_d2 = d2 ? (int64_t*)(A.stash_base + align_up(region * SPHIDX_NQUEUE * 4)) : nullptr;
+    // about 8 grabs per resident wave and region: little tail left unused
+    const uint64_t waves = (uint64_t)device_cu_count() * ln.bpc * ln.waves;
+    const uint64_t per = std::max<uint64_t>(1, waves / SPHIDX_NQUEUE);
+    A.stash_chunk = (uint32_t)std::min<uint64_t>(8192, std::max<uint64_t>(ln.cap, region / (per * 8)));
 }
 
 void* scan_tmp_of(sphidx_csr* csr, uint32_t Q) { return (char*)csr->workspace_dev + query_layout(Q).scan; }
@@ -217,9 +258,12 @@ sphidx_status run_pass(int pass, const sphidx_lattice* lat, const sphidx_tables*
     TabArgs T = tab_args(ln.method == SPHIDX_METHOD_SPHERE ? tab : nullptr);
     T.lds = ln.tab_lds;
     QArgs A = q_args(q, csr, ln);
+    if (pass == 0) plan_stash(A, csr, ln, q->mode, ln.interior == 2);
     // counting wholly-inside cells whole saves object reads but costs a
     // second extent per row: worth it once cells hold an object or more
-    A.interior = ln.interior == 2 || (ln.interior == 0 && (uint64_t)lat->n >= (uint64_t)lat->ncells);
+    // (not with the stash, which needs every object of a row)
+    A.interior = !A.stash &&
+                 (ln.interior == 2 || (ln.interior == 0 && (uint64_t)lat->n >= (uint64_t)lat->ncells));
     if (pass == 0) {
         s = dev_err(launch_query_pass(0, L, T, A, ln.waves, ln.bpc, st, ln.ev_begin, ln.ev_end));
         if (s != SPHIDX_OK) return s;
@@ -386,6 +430,15 @@ sphidx_status sphidx_tables_load(const char* path, sphidx_tables** out) {
 }
 
 size_t sphidx_query_workspace_bytes(uint32_t Q) { return query_ws_bytes(Q); }
+
+size_t sphidx_query_stash_bytes(uint64_t pairs, int want_dist2) {
+    // the rows, plus the tails left unused in each wave's last chunk (a
+    // chunk is at most an eighth of a region per resident wave, at least
+    // 256 objects) and the alignment slack
+    const uint64_t waves = (uint64_t)device_cu_count() * 64u;
+    const uint64_t elems = pairs + pairs / 4 + waves * 256u + 4096u * SPHIDX_NQUEUE;
+    return (size_t)(elems * (want_dist2 ? 12u : 4u) + 1024u);
+}
 
 sphidx_status sphidx_count(const sphidx_lattice* lat, const sphidx_tables* tab, const sphidx_queries* q,
                            sphidx_csr* csr, const sphidx_launch* launch, void* stream) {

@@ -401,8 +401,8 @@ __device__ __forceinline__ uint64_t axis_gap2(int o, uint32_t up, uint32_t dn, u
 // x-gap satisfies gx^2 <= bound^2 - gy^2 - gz^2 -- the exact test of Eq. 1
 // solved for x, one contiguous run; the wholly-inside cells solve the same
 // with the far distances (Section III.A, last paragraph).
-template <bool INTERIOR>
-__device__ __forceinline__ RowRef sphere_row(const LatArgs& L, const Query& s, uint32_t w, bool has, uint64_t bound2) {
+__device__ __forceinline__ RowRef sphere_row(const LatArgs& L, const Query& s, uint32_t w, bool has, uint64_t bound2,
+                                             bool interior) {
     const int oy = ((int)(w << 16)) >> 16, oz = ((int)w) >> 16;
     const uint32_t Ly = 1u << L.lg[1], Lz = 1u << L.lg[2];
     uint32_t ty = (uint32_t)((int)s.c[1] + oy), tz = (uint32_t)((int)s.c[2] + oz);
@@ -422,7 +422,7 @@ __device__ __forceinline__ RowRef sphere_row(const LatArgs& L, const Query& s, u
     const int npos = (int)((X + fx) >> L.F);
     const int nneg = X > fx ? (int)((X - fx - 1u) >> L.F) + 1 : 0;
     int ia = 1, ib = 0;
-    if (INTERIOR) {
+    if (interior) {
         const uint32_t hy = axis_far(oy, s.f[1], L.F), hz = axis_far(oz, s.f[2], L.F);
         const uint64_t hyz = sq(hy) + sq(hz);
         const uint32_t Xi = isqrt64(hyz <= s.r2 ? s.r2 - hyz : 0u);
@@ -524,44 +524,49 @@ __device__ __forceinline__ bool for_candidates(const LatArgs& L, uint32_t st0, u
     return false;
 }
 
-// Walk the query's rows: the outside cell first (when objects there may be
-// within r), then sphere-table rows or bounding-cube rows, 64 per step.
-// on_step(row) returns true to stop.  bound2_now() is re-read before every
-// step (top-M shrinks it); KEY_STOP enables the cut-off on sorted row keys.
-template <int METHOD, bool TLDS, bool INTERIOR, bool KEY_STOP, typename B, typename S>
+// Walk the query's rows: sphere-table rows or bounding-cube rows, 64 per
+// step, one per lane.  When objects outside the region may be within r, the
+// outside cell (Section II.B: every such object lives in one cell) is a
+// leading pseudo-row of the first step.  on_step(row) returns true to stop.
+// bound2_now() is re-read before every step (top-M shrinks it); KEY_STOP
+// enables the cut-off on sorted row keys; `interior` marks the cells wholly
+// inside the sphere (count pass).
+template <int METHOD, bool TLDS, bool KEY_STOP, typename B, typename S>
 __device__ __forceinline__ void walk(const LatArgs& L, const TabArgs& T, const uint32_t* tab_lds, const Query& s,
-                                     uint32_t& walked, B&& bound2_now, S&& on_step) {
+                                     bool interior, uint32_t& walked, B&& bound2_now, S&& on_step) {
     const uint32_t lane = lane_id();
-    if (s.flags & F_OUTSIDE) {
-        // every object outside the region lives in one cell (Section II.B)
-        RowRef r = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
-        if (lane == 0) {
-            r.st0 = L.cs[L.ncells];
-            r.cnt0 = L.cs[L.ncells + 1] - r.st0;
-        }
-        if (on_step(r)) return;
-    }
+    const uint32_t pre = (s.flags & F_OUTSIDE) ? 1u : 0u;
     const bool sphere = METHOD == kSphere || (METHOD == kEither && (s.flags & F_SPHERE));
     const uint32_t nent = sphere ? s.tend : s.nn[1] * s.nn[2];
+    const uint32_t total = nent + pre;
     const uint32_t* rows = TLDS ? tab_lds + s.tb : T.rows + s.tb;
+    // entry index of this lane's row in the current step (pseudo-row: ~0)
+    uint32_t ent = lane - pre;
     uint32_t nxt = 0;
-    if (sphere && lane < nent) nxt = rows[lane];
+    if (sphere && ent < nent) nxt = rows[ent];
     const double inv_ny = (!sphere && s.nn[1]) ? 1.0 / (double)s.nn[1] : 0.0;
-    for (uint32_t base = 0; base < nent; base += 64) {
-        const uint32_t idx = base + lane;
+    for (uint32_t base = 0; base < total; base += 64, ent += 64) {
+        const bool is_out = pre && base == 0 && lane == 0;
         RowRef r;
         if (METHOD == kSphere || (METHOD == kEither && sphere)) {
             const uint64_t bound2 = bound2_now();
             // rows are sorted by key: once the key exceeds the bound no
-            // further row can hold anything closer
-            if (KEY_STOP && uni64((uint64_t)T.rkey[s.tb + base]) > bound2) break;
+            // further row can hold anything closer (the first row's key is 0)
+            if (KEY_STOP && base > 0 && uni64((uint64_t)T.rkey[s.tb + base - pre]) > bound2) break;
             const uint32_t w = nxt;
-            if (idx + 64 < nent) nxt = rows[idx + 64];
-            r = sphere_row<INTERIOR>(L, s, w, idx < nent, bound2);
+            if (ent + 64 < nent) nxt = rows[ent + 64];
+            r = sphere_row(L, s, w, ent < nent, bound2, interior);
         } else {
-            r = cube_row(L, s, idx, idx < nent, inv_ny);
+            r = cube_row(L, s, ent, ent < nent, inv_ny);
         }
-        walked += min(64u, nent - base);
+        if (is_out) {
+            r.st0 = L.cs[L.ncells];
+            r.cnt0 = L.cs[L.ncells + 1] - r.st0;
+            r.cnt1 = 0u;
+            r.icnt = 0u;
+            r.kept = 0u;
+        }
+        walked += min(64u, total - base) - (base == 0 ? pre : 0u);
         if (on_step(r)) return;
     }
 }
@@ -575,45 +580,47 @@ __device__ __forceinline__ void for_each_query(uint32_t Q, const QArgs& A, uint3
     if (Q == 0) return;
     const uint32_t lane = lane_id();
     const uint32_t wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if (!A.persistent) {
-        // consecutive block ids go round-robin over the 8 XCDs: give each XCD
-        // a contiguous range of slices so neighbouring queries share its L2
-        const uint32_t G = gridDim.x, b = blockIdx.x;
-        const uint32_t full = G / SPHIDX_NQUEUE, rem = G % SPHIDX_NQUEUE;
-        const uint32_t x = b % SPHIDX_NQUEUE, i = b / SPHIDX_NQUEUE;
-        const uint32_t lb = x * full + min(x, rem) + i;
-        const uint64_t q0 = ((uint64_t)lb * nw + wave) * A.tile;
-        for (uint32_t t = 0; t < A.tile; ++t) {
-            const uint64_t qi = q0 + t;
-            if (qi >= Q) break;
-            f((uint32_t)qi);
-        }
-        return;
-    }
-    // one queue per XCD over a contiguous range of queries: drain the own
-    // queue, then take from the others; a queue found empty stays empty, so
-    // every wave stops after one empty round
+    // plain: consecutive block ids go round-robin over the 8 XCDs; give each
+    // XCD a contiguous range of slices so neighbouring queries share its L2.
+    // persistent: one queue per XCD over a contiguous range of queries; drain
+    // the own queue, then take from the others; a queue found empty stays
+    // empty, so every wave stops after one empty round.
     uint32_t x = blockIdx.x % SPHIDX_NQUEUE;
     uint32_t misses = 0;
-    while (misses < SPHIDX_NQUEUE) {
-        const uint32_t qs = (uint32_t)(((uint64_t)x * Q) / SPHIDX_NQUEUE);
-        const uint32_t qe = (uint32_t)(((uint64_t)(x + 1) * Q) / SPHIDX_NQUEUE);
-        uint32_t* qc = queues + x * SPHIDX_QSTRIDE;
-        uint32_t t = 0;
-        if (lane == 0) {
-            // an exhausted queue is skipped with a plain read, not an atomic
-            t = __hip_atomic_load(qc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if ((uint64_t)qs + t < qe) t = atomicAdd(qc, A.tile);
+    bool first = true;
+    for (;;) {
+        uint32_t b = 0, e = 0;
+        if (!A.persistent) {
+            if (!first) break;
+            const uint32_t G = gridDim.x, bi = blockIdx.x;
+            const uint32_t full = G / SPHIDX_NQUEUE, rem = G % SPHIDX_NQUEUE;
+            const uint32_t lb = x * full + min(x, rem) + bi / SPHIDX_NQUEUE;
+            const uint64_t q0 = ((uint64_t)lb * nw + wave) * A.tile;
+            b = (uint32_t)min(q0, (uint64_t)Q);
+            e = (uint32_t)min(q0 + A.tile, (uint64_t)Q);
+        } else {
+            if (misses >= SPHIDX_NQUEUE) break;
+            const uint32_t qs = (uint32_t)(((uint64_t)x * Q) / SPHIDX_NQUEUE);
+            const uint32_t qe = (uint32_t)(((uint64_t)(x + 1) * Q) / SPHIDX_NQUEUE);
+            uint32_t* qc = queues + x * SPHIDX_QSTRIDE;
+            uint32_t t = 0;
+            if (lane == 0) {
+                // an exhausted queue is skipped with a plain read, not an atomic
+                t = __hip_atomic_load(qc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((uint64_t)qs + t < qe) t = atomicAdd(qc, A.tile);
+            }
+            t = uni(t);
+            if ((uint64_t)qs + t >= qe) {
+                x = (x + 1) % SPHIDX_NQUEUE;
+                ++misses;
+                continue;
+            }
+            misses = 0;
+            b = qs + t;
+            e = (uint32_t)min((uint64_t)qe, (uint64_t)qs + t + A.tile);
         }
-        t = uni(t);
-        if ((uint64_t)qs + t >= qe) {
-            x = (x + 1) % SPHIDX_NQUEUE;
-            ++misses;
-            continue;
-        }
-        misses = 0;
-        const uint32_t end = (uint32_t)min((uint64_t)qe, (uint64_t)qs + t + A.tile);
-        for (uint32_t qi = qs + t; qi < end; ++qi) f(qi);
+        first = false;
+        for (uint32_t qi = b; qi < e; ++qi) f(qi);
     }
 }
 
@@ -633,72 +640,7 @@ __device__ __forceinline__ size_t table_lds_bytes(const TabArgs& T) {
 }
 
 // ---------------------------------------------------------------------------
-// Pass 0: row sizes
-
-// Queue sets of the work counters.
-constexpr int kQCount = 0, kQWrite = 1, kQTopm = 2, kQFbCount = 3, kQFbWrite = 4;
-
-__device__ __forceinline__ uint32_t* queue_set(const QArgs& A, int set) {
-    return A.queues + (size_t)set * SPHIDX_NQUEUE * SPHIDX_QSTRIDE;
-}
-
-// FROM_LIST: the queries of the sphere method that the tables do not cover,
-// scanned with the bounding cube.
-template <int METHOD, bool TLDS, bool FROM_LIST>
-__global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs A) {
-    extern __shared__ __align__(16) char smem[];
-    const uint32_t* tab_lds = stage_table<TLDS>(T, smem);
-    uint32_t* own = (uint32_t*)(smem + table_lds_bytes<TLDS>(T)) + (threadIdx.x >> 6) * 64;
-    const AxisWrap aw = axis_wrap(L);
-    const uint32_t lane = lane_id();
-    const uint32_t nq = FROM_LIST ? uni(*A.fb_count) : A.Q;
-    for_each_query(nq, A, queue_set(A, FROM_LIST ? kQFbCount : kQCount), [&](uint32_t ti_) {
-        const uint32_t qi = FROM_LIST ? uni(A.fbq[ti_]) : ti_;
-        const Query s = load_query(L, A, qi);
-        if (METHOD == kSphere && (s.flags & F_VALID) && !(s.flags & F_SPHERE)) return;  // fallback list
-        const bool knn = s.flags & F_KNN;
-        uint32_t hits = 0, inner = 0, kept = 0, cand = 0, walked = 0;
-        bool self_inner = false;
-        auto visit = [&](bool act, uint32_t p, const uint4& P) -> bool {
-            const bool hit = act && obj_dist2(aw, s, P) <= s.r2 && p != s.self;
-            hits += (uint32_t)__popcll(__ballot(hit));
-            return knn && hits >= s.k;
-        };
-        auto on_row = [&](const RowRef& r) -> bool {
-            kept += r.kept;
-            // cells wholly inside: counted without reading objects; note when
-            // the excluded own object was among them
-            if (r.icnt && s.self - r.ist < r.icnt) self_inner = true;
-            inner += r.icnt;
-            return for_candidates(L, r.st0, r.cnt0, r.st1, r.cnt1, own, cand, visit);
-        };
-        if (s.flags & F_VALID) {
-            if (knn || !A.interior)
-                walk<METHOD, TLDS, false, false>(L, T, tab_lds, s, walked, [&]() { return s.r2; }, on_row);
-            else
-                walk<METHOD, TLDS, true, false>(L, T, tab_lds, s, walked, [&]() { return s.r2; }, on_row);
-            uint32_t total = hits + wave_sum(inner);
-            if (__ballot(self_inner) != 0) total -= 1;
-            if (knn && total > s.k) total = s.k;
-            hits = total;
-        }
-        if (lane == 0) A.row_ptr[s.row] = (int64_t)hits;
-        if (A.stats) {
-            const uint32_t kept_all = wave_sum(kept);
-            const uint32_t ncube = (s.flags & F_VALID) ? cube_cells(L, s) : 0u;
-            if (lane == 0) {
-                uint32_t* stp = A.stats + 4 * (size_t)s.row;
-                stp[0] = walked;
-                stp[1] = kept_all;
-                stp[2] = cand;
-                stp[3] = ncube;
-            }
-        }
-    });
-}
-
-// ---------------------------------------------------------------------------
-// Pass 1, radius rows that fit the LDS buffer: collect, sort, store.
+// Ordering a row by (dist^2, id) in LDS.
 
 __device__ __forceinline__ void store_sorted(const QArgs& A, const uint64_t* td, const uint32_t* ti, uint32_t n,
                                              int64_t dst) {
@@ -709,7 +651,7 @@ __device__ __forceinline__ void store_sorted(const QArgs& A, const uint64_t* td,
 }
 
 // Sort the n <= cap pairs (td, ti) of one row by (dist^2, id) and store them
-// at row offset rb.  Every pair has dist^2 <= r2, so the bucket
+// at dst.  Every pair has dist^2 <= r2, so the bucket
 // floor(n * dist^2 / r2) (float arithmetic: monotone in dist^2) never puts a
 // larger distance in an earlier bucket; a histogram, its prefix sum and a
 // scatter order the buckets, and each pair's place inside its bucket (about
@@ -718,8 +660,8 @@ __device__ __forceinline__ uint32_t sort_bucket(uint64_t d2, float scale, uint32
     return min((uint32_t)((float)d2 * scale), n - 1u);
 }
 
-__device__ void bucket_sort_store(const QArgs& A, const uint64_t* td, const uint32_t* ti, uint64_t* sd,
-                                  uint32_t* si, uint32_t* hist, uint32_t n, uint64_t r2, int64_t rb) {
+__device__ void bucket_sort_store(const uint64_t* td, const uint32_t* ti, uint64_t* sd, uint32_t* si, uint32_t* hist,
+                                  uint32_t n, uint64_t r2, uint32_t* dst_ids, int64_t* dst_d2) {
     const uint32_t lane = lane_id();
     if (n == 0) return;
     const float scale = r2 > 0 ? (float)n / (float)r2 : 0.0f;
@@ -764,10 +706,134 @@ __device__ void bucket_sort_store(const QArgs& A, const uint64_t* td, const uint
         const uint32_t lo = hist[b], hi = b + 1 < n ? hist[b + 1] : n;
         uint32_t rank = lo;
         for (uint32_t j = lo; j < hi; ++j) rank += key_less(sd[j], si[j], d, id) ? 1u : 0u;
-        A.out_ids[rb + rank] = id;
-        if (A.out_d2) A.out_d2[rb + rank] = (int64_t)d;
+        dst_ids[rank] = id;
+        if (dst_d2) dst_d2[rank] = (int64_t)d;
     }
 }
+
+// ---------------------------------------------------------------------------
+// Pass 0: row sizes
+
+// Queue sets of the work counters.
+constexpr int kQCount = 0, kQWrite = 1, kQTopm = 2, kQFbCount = 3, kQFbWrite = 4, kQWalk = 5;
+
+__device__ __forceinline__ uint32_t* queue_set(const QArgs& A, int set) {
+    return A.queues + (size_t)set * SPHIDX_NQUEUE * SPHIDX_QSTRIDE;
+}
+
+// FROM_LIST: a query list (the sphere method's fallback queries, scanned with
+// the bounding cube).  STASH: radius rows of at most sort_cap hits are also
+// collected, sorted and kept in the workspace's stash, so that the write pass
+// only copies them into place; other rows go to the walk list.
+template <int METHOD, bool TLDS, bool FROM_LIST, bool STASH>
+__global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs A) {
+    extern __shared__ __align__(16) char smem[];
+    const uint32_t* tab_lds = stage_table<TLDS>(T, smem);
+    const uint32_t wave = threadIdx.x >> 6;
+    const uint32_t cap = A.sort_cap;
+    char* wb = smem + table_lds_bytes<TLDS>(T) + (size_t)wave * (STASH ? (size_t)cap * 28 + 256 : 256);
+    uint64_t* td = (uint64_t*)wb;
+    uint64_t* sd = td + cap;
+    uint32_t* ti = (uint32_t*)(sd + cap);
+    uint32_t* si = ti + cap;
+    uint32_t* hist = si + cap;
+    uint32_t* own = STASH ? hist + cap : (uint32_t*)wb;
+    const AxisWrap aw = axis_wrap(L);
+    const uint32_t lane = lane_id();
+    const uint32_t nq = FROM_LIST ? uni(*A.list_count) : A.Q;
+    // this wave's stash chunk [cur, lim) in its region; `dry` once the
+    // region is used up
+    const uint32_t region = blockIdx.x % SPHIDX_NQUEUE;
+    uint32_t cur = 0, lim = 0;
+    bool dry = false;
+    for_each_query(nq, A, queue_set(A, FROM_LIST ? (int)A.list_set : kQCount), [&](uint32_t ti_) {
+        const uint32_t qi = FROM_LIST ? uni(A.list[ti_]) : ti_;
+        const Query s = load_query(L, A, qi);
+        if (METHOD == kSphere && (s.flags & F_VALID) && !(s.flags & F_SPHERE)) return;  // fallback list
+        const bool knn = s.flags & F_KNN;
+        uint32_t hits = 0, inner = 0, kept = 0, cand = 0, walked = 0;
+        bool self_inner = false;
+        auto visit = [&](bool act, uint32_t p, const uint4& P) -> bool {
+            const uint64_t d2 = obj_dist2(aw, s, P);
+            const bool hit = act && d2 <= s.r2 && p != s.self;
+            const uint64_t hm = __ballot(hit);
+            if (STASH && hit) {
+                const uint32_t slot = hits + lanes_below(hm);
+                if (slot < cap) {
+                    td[slot] = d2;
+                    ti[slot] = P.w;
+                }
+            }
+            hits += (uint32_t)__popcll(hm);
+            return knn && hits >= s.k;
+        };
+        auto on_row = [&](const RowRef& r) -> bool {
+            kept += r.kept;
+            // cells wholly inside: counted without reading objects; note when
+            // the excluded own object was among them
+            if (r.icnt && s.self - r.ist < r.icnt) self_inner = true;
+            inner += r.icnt;
+            return for_candidates(L, r.st0, r.cnt0, r.st1, r.cnt1, own, cand, visit);
+        };
+        if (s.flags & F_VALID) {
+            walk<METHOD, TLDS, false>(L, T, tab_lds, s, !STASH && !knn && A.interior, walked,
+                                      [&]() { return s.r2; }, on_row);
+            uint32_t total = hits + wave_sum(inner);
+            if (__ballot(self_inner) != 0) total -= 1;
+            if (knn && total > s.k) total = s.k;
+            hits = total;
+        }
+        if (lane == 0) A.row_ptr[s.row] = (int64_t)hits;
+        if (STASH) {
+            uint32_t off = 0u;  // empty rows: nothing to copy
+            if ((s.flags & F_VALID) && hits > 0) {
+                bool ok = !knn && hits <= cap;
+                if (ok && cur + hits > lim) {
+                    ok = false;
+                    if (!dry) {
+                        const uint32_t grab = max(A.stash_chunk, hits);
+                        uint32_t t = 0;
+                        if (lane == 0) t = atomicAdd(A.stash_ctr + region * SPHIDX_QSTRIDE, grab);
+                        t = uni(t);
+                        if ((uint64_t)t + grab <= A.stash_region) {
+                            cur = region * A.stash_region + t;
+                            lim = cur + grab;
+                            ok = true;
+                        } else {
+                            dry = true;
+                        }
+                    }
+                }
+                if (ok) {
+                    wave_sync();
+                    bucket_sort_store(td, ti, sd, si, hist, hits, s.r2, A.stash_ids + cur,
+                                      A.stash_d2 ? A.stash_d2 + cur : nullptr);
+                    wave_sync();
+                    off = cur;
+                    cur += hits;
+                } else {
+                    off = kMaxId;
+                    if (lane == 0) A.walkq[atomicAdd(A.walk_count, 1u)] = qi;
+                }
+            }
+            if (lane == 0) A.soff[qi] = off;
+        }
+        if (A.stats) {
+            const uint32_t kept_all = wave_sum(kept);
+            const uint32_t ncube = (s.flags & F_VALID) ? cube_cells(L, s) : 0u;
+            if (lane == 0) {
+                uint32_t* stp = A.stats + 4 * (size_t)s.row;
+                stp[0] = walked;
+                stp[1] = kept_all;
+                stp[2] = cand;
+                stp[3] = ncube;
+            }
+        }
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Pass 1, radius rows that fit the LDS buffer: collect, sort, store.
 
 template <int METHOD, bool TLDS, bool FROM_LIST>
 __global__ __launch_bounds__(256) void write_kernel(LatArgs L, TabArgs T, QArgs A) {
@@ -788,9 +854,15 @@ __global__ __launch_bounds__(256) void write_kernel(LatArgs L, TabArgs T, QArgs 
     }
     const AxisWrap aw = axis_wrap(L);
     const uint32_t lane = lane_id();
-    const uint32_t nq = FROM_LIST ? uni(*A.fb_count) : A.Q;
-    for_each_query(nq, A, queue_set(A, FROM_LIST ? kQFbWrite : kQWrite), [&](uint32_t ti_) {
-        const uint32_t qi = FROM_LIST ? uni(A.fbq[ti_]) : ti_;
+    // after a stashing count pass only the rows it did not keep are walked:
+    // the main launch takes the walk list, the list launch skips kept rows
+    const bool stashed = A.stash_hdr[kHdrMode] != 0u;
+    const bool from_walk = !FROM_LIST && stashed;
+    const uint32_t nq = FROM_LIST ? uni(*A.list_count) : (from_walk ? uni(*A.walk_count) : A.Q);
+    for_each_query(nq, A, queue_set(A, FROM_LIST ? (int)A.list_set : (from_walk ? kQWalk : kQWrite)),
+                   [&](uint32_t ti_) {
+        const uint32_t qi = FROM_LIST ? uni(A.list[ti_]) : (from_walk ? uni(A.walkq[ti_]) : ti_);
+        if (FROM_LIST && stashed && uni(A.soff[qi]) != kMaxId) return;  // copied by the gather kernel
         const Query s = load_query(L, A, qi);
         if (METHOD == kSphere && (s.flags & F_VALID) && !(s.flags & F_SPHERE)) return;  // fallback list
         const int64_t rb = A.row_ptr[s.row];
@@ -816,12 +888,12 @@ __global__ __launch_bounds__(256) void write_kernel(LatArgs L, TabArgs T, QArgs 
             n += (uint32_t)__popcll(hm);
             return false;
         };
-        walk<METHOD, TLDS, false, false>(L, T, tab_lds, s, walked, [&]() { return s.r2; },
+        walk<METHOD, TLDS, false>(L, T, tab_lds, s, false, walked, [&]() { return s.r2; },
                                          [&](const RowRef& r) -> bool {
             return for_candidates(L, r.st0, r.cnt0, r.st1, r.cnt1, own, cand, visit);
         });
         wave_sync();
-        bucket_sort_store(A, td, ti, sd, si, hist, min(n, rowlen), s.r2, rb);
+        bucket_sort_store(td, ti, sd, si, hist, min(n, rowlen), s.r2, A.out_ids + rb, A.out_d2 ? A.out_d2 + rb : nullptr);
         wave_sync();
     });
 }
@@ -851,9 +923,9 @@ __global__ __launch_bounds__(256) void topm_kernel(LatArgs L, TabArgs T, QArgs A
     }
     const AxisWrap aw = axis_wrap(L);
     const uint32_t lane = lane_id();
-    const uint32_t nq = FROM_LIST ? uni(*A.long_count) : A.Q;
+    const uint32_t nq = FROM_LIST ? uni(*A.list_count) : A.Q;
     for_each_query(nq, A, queue_set(A, kQTopm), [&](uint32_t ti_) {
-        const uint32_t qi = FROM_LIST ? uni(A.longq[ti_]) : ti_;
+        const uint32_t qi = FROM_LIST ? uni(A.list[ti_]) : ti_;
         const Query s = load_query(L, A, qi);
         if (!FROM_LIST && !(s.flags & F_KNN)) return;
         const int64_t rb = A.row_ptr[s.row];
@@ -957,7 +1029,7 @@ __global__ __launch_bounds__(256) void topm_kernel(LatArgs L, TabArgs T, QArgs A
             // every object within B is visited and nothing beyond B is kept,
             // so M kept means they are the M nearest above the lower bound
             for (;;) {
-                walk<METHOD, TLDS, false, true>(L, T, tab_lds, s, walked, [&]() { return m == M ? bdd : B; },
+                walk<METHOD, TLDS, true>(L, T, tab_lds, s, false, walked, [&]() { return m == M ? bdd : B; },
                                                 [&](const RowRef& r) -> bool {
                     return for_candidates(L, r.st0, r.cnt0, r.st1, r.cnt1, own, cand, visit);
                 });
@@ -980,8 +1052,76 @@ __global__ __launch_bounds__(256) void topm_kernel(LatArgs L, TabArgs T, QArgs A
     });
 }
 
-__global__ void clear_counters_kernel(uint32_t* c) {
-    for (uint32_t i = threadIdx.x; i < SPHIDX_COUNTER_WORDS; i += blockDim.x) c[i] = 0u;
+// Zero counter words [begin, end); the count pass also writes the stash
+// header (hdr != NULL: four words) after clearing.
+__global__ void clear_counters_kernel(uint32_t* c, uint32_t begin, uint32_t end, uint32_t* hdr, uint4 hv) {
+    for (uint32_t i = begin + threadIdx.x; i < end; i += blockDim.x) c[i] = 0u;
+    if (hdr && threadIdx.x == 0) {
+        hdr[kHdrMode] = hv.x;
+        hdr[kHdrElems] = hv.y;
+        hdr[kHdrHasD2] = hv.z;
+        hdr[kHdrD2Off] = hv.w;
+    }
+}
+
+// Write pass after a stashing count pass: copy every kept row from the stash
+// to its place in the output.  A wave takes 64 consecutive queries; their
+// rows' elements are spread over the lanes (prefix sum + owner map, as for
+// candidates), 64 per step.  If the caller now asks for dist^2 and the stash
+// holds none, the row is put on the walk list instead.
+__global__ __launch_bounds__(256) void gather_kernel(QArgs A, uint32_t* status) {
+    __shared__ uint32_t own_all[4 * 64];
+    const uint32_t* hdr = A.stash_hdr;
+    if (hdr[kHdrMode] == 0u) return;
+    if (A.row_ptr[A.Q] > A.capacity) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(status, SPHIDX_FLAG_CAPACITY);
+        return;
+    }
+    const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
+    uint32_t* own = own_all + wave * 64;
+    const uint64_t q0 = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + wave) * 64u;
+    if (q0 >= A.Q) return;
+    const uint32_t* s_ids = (const uint32_t*)A.stash_base;
+    const bool has_d2 = hdr[kHdrHasD2] != 0u;
+    const int64_t* s_d2 = (const int64_t*)(A.stash_base + hdr[kHdrD2Off] * (size_t)256);
+    const uint64_t qi = q0 + lane;
+    uint32_t len = 0, src = 0;
+    int64_t dst = 0;
+    if (qi < A.Q) {
+        src = A.soff[qi];
+        if (src != kMaxId) {
+            const uint32_t row = A.desc[4 * qi].w;
+            dst = A.row_ptr[row];
+            len = (uint32_t)(A.row_ptr[row + 1] - dst);
+            if (len > 0 && A.out_d2 && !has_d2) {
+                A.walkq[atomicAdd(A.walk_count, 1u)] = (uint32_t)qi;
+                len = 0;
+            }
+        }
+    }
+    const uint32_t incl = scan_add(len);
+    const uint32_t total = lane_val(incl, 63);
+    const uint32_t excl = incl - len;
+    // per owner: element g of the group maps to src + (g - excl), dst + (g - excl)
+    const uint32_t sbase = src - excl;
+    const int64_t dbase = dst - (int64_t)excl;
+    for (uint32_t cb = 0; cb < total; cb += 64) {
+        own[lane] = 0;
+        wave_sync();
+        if (len > 0 && excl < cb + 64 && incl > cb) own[excl > cb ? excl - cb : 0] = lane + 1;
+        wave_sync();
+        const uint32_t o = scan_max(own[lane]) - 1u;
+        const uint32_t g = cb + lane;
+        const uint32_t sp = bperm(sbase, o) + g;
+        const uint64_t db = ((uint64_t)bperm((uint32_t)((uint64_t)dbase >> 32), o) << 32) |
+                            bperm((uint32_t)(uint64_t)dbase, o);
+        if (g < total) {
+            const int64_t dp = (int64_t)db + (int64_t)g;
+            A.out_ids[dp] = s_ids[sp];
+            if (A.out_d2) A.out_d2[dp] = s_d2[sp];
+        }
+        wave_sync();
+    }
 }
 
 // Kernel choice by variant: cube, sphere, sphere with the row table in LDS.
@@ -1020,20 +1160,37 @@ int device_cu_count() {
     return cus;
 }
 
+// LDS bytes per block: pass 0 count (3 with the stash), 1 write, 2 top-M.
 size_t query_lds_bytes(int pass, uint32_t cap, uint32_t waves, size_t table_bytes) {
-    size_t per = pass == 0 ? 256 : (pass == 1 ? (size_t)cap * 28 + 256 : (size_t)cap * 24 + 64 * 12 + 256);
+    size_t per = 256;
+    if (pass == 1 || pass == 3) per = (size_t)cap * 28 + 256;
+    if (pass == 2) per = (size_t)cap * 24 + 64 * 12 + 256;
     return table_bytes + per * waves;
 }
 
 hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const QArgs& q,
                              uint32_t waves_per_block, uint32_t blocks_per_cu, hipStream_t st,
                              hipEvent_t ev_begin, hipEvent_t ev_end) {
-    // optional timing events around the pass's main kernel
+    // optional timing events around the pass's main kernel(s)
     auto mark = [st](hipEvent_t ev) { return ev ? hipEventRecord(ev, st) : hipSuccess; };
     const size_t tb = T.lds ? (((size_t)T.total * 4 + 15) & ~(size_t)15) : 0;
     const int variant = !T.has ? 0 : (T.lds ? 2 : 1);
-    clear_counters_kernel<<<1, 256, 0, st>>>(q.queues);
-    hipError_t e = hipGetLastError();
+    const uint32_t lists = SPHIDX_NQSETS * SPHIDX_NQUEUE * SPHIDX_QSTRIDE;
+    const uint32_t set_words = SPHIDX_NQUEUE * SPHIDX_QSTRIDE;
+    hipError_t e;
+    if (pass == 0) {
+        // everything, then the stash header for the write pass
+        const uint4 hv = make_uint4(q.stash, q.stash ? q.stash_region * SPHIDX_NQUEUE : 0u, q.stash_d2 ? 1u : 0u,
+                                    q.stash_d2 ? (uint32_t)(((char*)q.stash_d2 - q.stash_base) / 256) : 0u);
+        clear_counters_kernel<<<1, 256, 0, st>>>(q.queues, 0u, SPHIDX_COUNTER_WORDS, q.stash_hdr, hv);
+    } else {
+        // the write-side queue sets and the long / fallback lists; the walk
+        // list, the stash header and the stash counters stay as the count
+        // pass left them
+        clear_counters_kernel<<<1, 256, 0, st>>>(q.queues, set_words, lists + 2 * SPHIDX_QSTRIDE, nullptr,
+                                                 make_uint4(0, 0, 0, 0));
+    }
+    e = hipGetLastError();
     if (e != hipSuccess || q.Q == 0) return e;
     // per-query descriptors (and, for the sphere method, the fallback list)
     if (variant == 0)
@@ -1047,27 +1204,45 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
     ql.persistent = 1;
     ql.tile = 1;
     if (pass == 0) {
+        const int lp = q.stash ? 3 : 0;
         if ((e = mark(ev_begin)) != hipSuccess) return e;
-        e = launch_ptr(SPHIDX_PICK(count_kernel, variant, kSphere, , false), q.Q, q, w, b,
-                       query_lds_bytes(0, q.sort_cap, w, tb), st, L, T);
+        if (q.stash)
+            e = launch_ptr(SPHIDX_PICK(count_kernel, variant, kSphere, , false, true), q.Q, q, w, b,
+                           query_lds_bytes(lp, q.sort_cap, w, tb), st, L, T);
+        else
+            e = launch_ptr(SPHIDX_PICK(count_kernel, variant, kSphere, , false, false), q.Q, q, w, b,
+                           query_lds_bytes(lp, q.sort_cap, w, tb), st, L, T);
         if (e == hipSuccess) e = mark(ev_end);
         if (e != hipSuccess || variant == 0) return e;
-        return launch_ptr((const void*)count_kernel<kCube, false, true>, 0, ql, w, b,
-                          query_lds_bytes(0, q.sort_cap, w, 0), st, L, T);
+        ql.list = q.fbq;
+        ql.list_count = q.fb_count;
+        ql.list_set = kQFbCount;
+        return launch_ptr(q.stash ? (const void*)count_kernel<kCube, false, true, true>
+                                  : (const void*)count_kernel<kCube, false, true, false>,
+                          0, ql, w, b, query_lds_bytes(lp, q.sort_cap, w, 0), st, L, T);
     }
     const size_t sh1 = query_lds_bytes(1, q.sort_cap, w, tb);
     const size_t sh2 = query_lds_bytes(2, q.sort_cap, w, tb);
     if (q.mode != SPHIDX_MODE_KNN) {
         if ((e = mark(ev_begin)) != hipSuccess) return e;
+        // rows kept by a stashing count pass (does nothing otherwise)
+        gather_kernel<<<(q.Q + 255) / 256, 256, 0, st>>>(q, L.status);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
         e = launch_ptr(SPHIDX_PICK(write_kernel, variant, kSphere, , false), q.Q, q, w, b, sh1, st, L, T);
         if (e == hipSuccess) e = mark(ev_end);
         if (e != hipSuccess) return e;
         if (variant != 0) {
+            ql.list = q.fbq;
+            ql.list_count = q.fb_count;
+            ql.list_set = kQFbWrite;
             e = launch_ptr((const void*)write_kernel<kCube, false, true>, 0, ql, w, b,
                            query_lds_bytes(1, q.sort_cap, w, 0), st, L, T);
             if (e != hipSuccess) return e;
         }
         // K-NN rows of a mixed batch and long radius rows, from the list
+        ql.list = q.longq;
+        ql.list_count = q.long_count;
+        ql.list_set = kQTopm;
         return launch_ptr(SPHIDX_PICK(topm_kernel, variant, kEither, , true), 0, ql, w, b, sh2, st, L, T);
     }
     if ((e = mark(ev_begin)) != hipSuccess) return e;

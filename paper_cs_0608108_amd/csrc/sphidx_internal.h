@@ -98,11 +98,25 @@ struct QArgs {
     uint32_t* out_ids;
     int64_t* out_d2;
     int64_t capacity;
-    uint32_t* queues;   // work counters: 5 x NQUEUE, then the list counts
+    uint32_t* queues;   // work counters: NQSETS x NQUEUE, then the list counters
     uint32_t* long_count;
     uint32_t* longq;    // rows handed from the write kernels to the top-M kernel
     uint32_t* fb_count;
     uint32_t* fbq;      // sphere method: queries the tables do not cover (cube scan)
+    uint32_t* walk_count;
+    uint32_t* walkq;    // stash mode: queries the count pass did not stash
+    uint32_t* soff;     // stash mode: per query, first stash element of its sorted row
+    uint32_t* stash_hdr;  // stash header written by the count pass (see StashHdr)
+    uint32_t* stash_ctr;  // NQUEUE per-region allocation counters
+    char* stash_base;     // start of the stash area of the workspace
+    uint32_t* stash_ids;  // count pass: stash arrays (ids, optional dist^2)
+    int64_t* stash_d2;
+    uint32_t stash;       // count pass: 1 = keep sorted rows in the stash
+    uint32_t stash_region;  // elements per region
+    uint32_t stash_chunk;   // elements per allocation grab
+    const uint32_t* list;       // list-driven launches: the query list,
+    const uint32_t* list_count; // its length (device)
+    uint32_t list_set;          // and its work-queue set
     uint4* desc;        // per query (processing order): 4 x uint4 set up by the setup kernel
     uint32_t* stats;
     uint32_t method;
@@ -112,10 +126,16 @@ struct QArgs {
     uint32_t interior;  // count pass: count wholly-inside cells without reading them
 };
 
+// Stash header words (in the counter block): written by the count pass,
+// read by the write pass, which therefore needs no host-side state.
+enum : uint32_t { kHdrMode = 0, kHdrElems = 1, kHdrHasD2 = 2, kHdrD2Off = 3 };
+
 #define SPHIDX_NQUEUE 8         // one work queue per XCD of the MI355X
 #define SPHIDX_QSTRIDE 32       // counters 128 bytes apart: one L2 line each
-#define SPHIDX_NQSETS 5         // count, write, top-M, fallback count, fallback write
-#define SPHIDX_COUNTER_WORDS (SPHIDX_NQSETS * SPHIDX_NQUEUE * SPHIDX_QSTRIDE + 2 * SPHIDX_QSTRIDE)
+#define SPHIDX_NQSETS 6         // count, write, top-M, fallback count, fallback write, walk list
+#define SPHIDX_NLISTS 4         // long_count, fb_count, walk_count, stash header
+#define SPHIDX_COUNTER_WORDS \
+    ((SPHIDX_NQSETS * SPHIDX_NQUEUE + SPHIDX_NLISTS + SPHIDX_NQUEUE) * SPHIDX_QSTRIDE)
 #define SPHIDX_MAX_LOG2_SUM 30
 
 // ---------------------------------------------------------------------------

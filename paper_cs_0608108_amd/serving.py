@@ -181,7 +181,7 @@ def run_admission_model(batches, executor, slots, pool_bytes, keep=False, clock=
 class GpuExecutor:
     """Runs batches on the device: one stream, workspace and input buffers per slot."""
 
-    def __init__(self, lat, tab, slots, max_batch, pool_bytes, launch=None):
+    def __init__(self, lat, tab, slots, max_batch, pool_bytes, launch=None, stash_pairs=1 << 24):
         import torch
 
         from . import sphidx
@@ -194,7 +194,7 @@ class GpuExecutor:
         self.slot = []
         for _ in range(slots):
             s = dict(stream=torch.cuda.Stream(),
-                     buf=sphidx.QueryBuffers(max_batch, 0, want_dist2=False),
+                     buf=sphidx.QueryBuffers(max_batch, 0, want_dist2=False, stash_pairs=stash_pairs),
                      inp=torch.empty((5, max_batch), dtype=torch.int32, device="cuda"),
                      host=torch.empty((5, max_batch), dtype=torch.int32, pin_memory=True),
                      total=torch.empty(1, dtype=torch.int64, pin_memory=True))

@@ -54,7 +54,7 @@ class CSRDesc(ctypes.Structure):
 class LaunchDesc(ctypes.Structure):
     _fields_ = [("method", U32), ("schedule", U32), ("waves_per_block", U32), ("tile", U32),
                 ("blocks_per_cu", U32), ("sort_cap", U32), ("table_in_lds", U32), ("interior", U32),
-                ("stats_dev", P), ("event_begin", P), ("event_end", P)]
+                ("stats_dev", P), ("event_begin", P), ("event_end", P), ("no_stash", U32)]
 
 
 # Every symbol include/sphidx.h declares, with its ctypes signature.
@@ -72,6 +72,7 @@ SIGNATURES = {
     "sphidx_tables_save": (ctypes.c_int, [P, ctypes.c_char_p]),
     "sphidx_tables_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(P)]),
     "sphidx_query_workspace_bytes": (SZ, [U32]),
+    "sphidx_query_stash_bytes": (SZ, [ctypes.c_uint64, ctypes.c_int]),
     "sphidx_count": (ctypes.c_int, [P, P, ctypes.POINTER(Queries), ctypes.POINTER(CSRDesc),
                                     ctypes.POINTER(LaunchDesc), P]),
     "sphidx_write": (ctypes.c_int, [P, P, ctypes.POINTER(Queries), ctypes.POINTER(CSRDesc),
@@ -271,6 +272,7 @@ class LaunchConfig:
     interior: int = 0
     stats: torch.Tensor | None = None
     events: tuple | None = None  # (begin, end) torch.cuda.Event around the pass's main kernel
+    no_stash: int = 0
 
     def c(self) -> LaunchDesc:
         d = LaunchDesc()
@@ -278,6 +280,7 @@ class LaunchConfig:
         d.waves_per_block, d.tile, d.blocks_per_cu = self.waves_per_block, self.tile, self.blocks_per_cu
         d.sort_cap, d.table_in_lds = self.sort_cap, self.table_in_lds
         d.interior = self.interior
+        d.no_stash = self.no_stash
         d.stats_dev = None if self.stats is None else self.stats.data_ptr()
         if self.events is not None:
             for ev in self.events:
@@ -307,27 +310,46 @@ def make_queries(count, centres=None, radius=None, k=None, mode=MODE_RADIUS, fla
 
 
 class QueryBuffers:
-    """Device outputs and workspace of one query call."""
+    """Device outputs and workspace of one query call.
 
-    def __init__(self, Q, capacity, want_dist2=True, device="cuda"):
-        lib = load()
+    The workspace is zero-filled when (re)allocated.  `reserve_stash(pairs)`
+    enlarges it so that a following count pass can keep up to that many
+    sorted pairs for the write pass; it must be called before the count, as
+    the write pass reads what the count pass left in the workspace."""
+
+    def __init__(self, Q, capacity, want_dist2=True, device="cuda", stash_pairs=0):
         self.Q = int(Q)
+        self.device = device
         self.row_ptr = torch.empty(self.Q + 1, dtype=torch.int64, device=device)
         self.capacity = int(capacity)
         self.ids = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=device)
         self.dist2 = torch.empty(max(self.capacity, 1), dtype=torch.int64, device=device) if want_dist2 else None
+        self.stash_pairs = 0
+        self._alloc_workspace(int(stash_pairs))
+
+    def _alloc_workspace(self, stash_pairs):
+        lib = load()
         wsb = lib.sphidx_query_workspace_bytes(self.Q)
-        self.workspace = torch.empty(wsb + 256, dtype=torch.uint8, device=device)
+        if stash_pairs > 0:
+            wsb += lib.sphidx_query_stash_bytes(stash_pairs, int(self.dist2 is not None))
+        self.workspace = None
+        self.workspace = torch.zeros(wsb + 256, dtype=torch.uint8, device=self.device)
         self._ws = self.workspace.data_ptr() + ((-self.workspace.data_ptr()) % 256)
         self._wsb = wsb
+        self.stash_pairs = stash_pairs
 
     def grow(self, capacity):
+        """Larger outputs; the workspace (and what a count left there) is kept."""
         if capacity > self.capacity:
             dev = self.ids.device
             self.capacity = int(capacity)
             self.ids = torch.empty(self.capacity, dtype=torch.int32, device=dev)
             if self.dist2 is not None:
                 self.dist2 = torch.empty(self.capacity, dtype=torch.int64, device=dev)
+
+    def reserve_stash(self, pairs):
+        if pairs > self.stash_pairs:
+            self._alloc_workspace(int(pairs))
 
     def c(self) -> CSRDesc:
         d = CSRDesc()
@@ -368,12 +390,17 @@ def query(lat, tab, q: Queries, buf: QueryBuffers, launch: LaunchConfig | None =
                               ctypes.byref(ln), _stream(stream)), "query")
 
 
-def run(lat, tab, q: Queries, launch: LaunchConfig | None = None, want_dist2=True, stream=None):
-    """Count, size the outputs exactly, write; returns host (row_ptr, ids, dist2)."""
+def run(lat, tab, q: Queries, launch: LaunchConfig | None = None, want_dist2=True, stream=None, stash=False):
+    """Count, size the outputs exactly, write; returns host (row_ptr, ids, dist2).
+    stash=True counts a second time with a workspace that keeps every row, so
+    that the write pass copies rows instead of walking again."""
     buf = QueryBuffers(q.count, 0, want_dist2)
     count(lat, tab, q, buf, launch, stream)
     total = int(buf.row_ptr[-1].item())
     buf.grow(max(total, 1))
+    if stash:
+        buf.reserve_stash(max(total, 1))
+        count(lat, tab, q, buf, launch, stream)
     write(lat, tab, q, buf, launch, stream)
     torch.cuda.synchronize()
     return buf.host()

@@ -36,7 +36,9 @@ class AgentSim:
         probe = sphidx.QueryBuffers(self.n, 0, want_dist2=False)
         sphidx.count(self.lat, self.tab, self.q, probe, self.launch)
         cap = int(int(probe.row_ptr[-1].item()) * headroom) + 1024
-        self.buf = sphidx.QueryBuffers(self.n, cap, want_dist2=False)
+        # the stash lets the count pass keep the sorted rows: the write pass
+        # then copies them instead of walking the tables a second time
+        self.buf = sphidx.QueryBuffers(self.n, cap, want_dist2=False, stash_pairs=cap)
         self.graph = None
         self.steps_done = 0
 

@@ -1,0 +1,146 @@
+"""The count pass's stash (sorted rows kept in the workspace and copied into
+place by the write pass) against the oracle, bit for bit: every row stashed,
+a stash too small for all rows (the rest walked again), a write asking for
+dist^2 after a count that kept none, cube-fallback and K-NN rows in the mix,
+and repeated count/write cycles on one workspace."""
+import numpy as np
+import pytest
+
+from gpu_util import assert_same, say, tiny_points
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_cs_0608108_amd import sphidx
+    sphidx.load()
+    return sphidx
+
+
+def _world(sx, log2, F, mask, pts):
+    lat = sx.Lattice(log2, F, mask, max(len(pts[0]), 1))
+    dev = tuple(sx.to_dev_u32(a) for a in pts)
+    lat.build(*dev)
+    lat._dev = dev
+    return lat
+
+
+def _cycle(sx, lat, tab, q, launch, want_d2_count, want_d2_write, stash_frac):
+    """count (sizing) -> reserve a stash for a fraction of the pairs -> count
+    -> write; returns host rows and the number of pairs."""
+    buf = sx.QueryBuffers(q.count, 0, want_dist2=want_d2_count)
+    sx.count(lat, tab, q, buf, launch)
+    total = int(buf.row_ptr[-1].item())
+    if stash_frac > 0:
+        buf.reserve_stash(max(int(total * stash_frac), 1))
+    buf.grow(max(total, 1))
+    sx.count(lat, tab, q, buf, launch)
+    if want_d2_write and buf.dist2 is None:
+        import torch
+        buf.dist2 = torch.empty(max(buf.capacity, 1), dtype=torch.int64, device="cuda")
+    if not want_d2_write:
+        buf.dist2 = None
+    sx.write(lat, tab, q, buf, launch)
+    import torch
+    torch.cuda.synchronize()
+    code, flags = lat.status()
+    assert code == sx.OK and not (flags & sx.FLAG_CAPACITY), (code, flags)
+    return buf.host(), total
+
+
+@pytest.mark.parametrize("mask", [0, 7])
+@pytest.mark.parametrize("stash_frac", [1.0, 0.3, 0.0])
+def test_stash_radius_rows_match_oracle(sx, orc, mask, stash_frac):
+    rng = np.random.default_rng(100 + mask)
+    log2, F = (5, 4, 5), 10
+    pts = tiny_points(rng, log2, F, mask, 30000, outside=(mask != 7))
+    lat = _world(sx, log2, F, mask, pts)
+    tab = sx.Tables(lat, 2, 3 << F)
+    r = rng.integers(1, 3 << F, size=len(pts[0])).astype(np.uint32)
+    r_dev = sx.to_dev_u32(r)  # queries hold raw pointers: keep the tensor alive
+    q = sx.make_queries(len(pts[0]), None, r_dev, None, sx.MODE_RADIUS, 0)
+    L = orc.Lattice(log2, F, mask)
+    g = orc.Grid(L, pts)
+    ref = g.radius(r)
+    g.close()
+    for launch in (sx.LaunchConfig(), sx.LaunchConfig(schedule=sx.SCHED_PLAIN, sort_cap=64, tile=2)):
+        say(f"stash mask={mask} frac={stash_frac} launch={launch.schedule}/{launch.sort_cap}")
+        got, total = _cycle(sx, lat, tab, q, launch, True, True, stash_frac)
+        assert_same(got, ref, f"stash frac {stash_frac}")
+    del r_dev
+
+
+def test_stash_without_dist2_then_write_with_dist2(sx, orc):
+    rng = np.random.default_rng(7)
+    log2, F = (5, 5, 5), 12
+    pts = tiny_points(rng, log2, F, 7, 20000)
+    lat = _world(sx, log2, F, 7, pts)
+    tab = sx.Tables(lat, 2, 2 << F)
+    q = sx.make_queries(len(pts[0]), None, 2 << F, None, sx.MODE_RADIUS, sx.EXCLUDE_SELF)
+    g = orc.Grid(orc.Lattice(log2, F, 7), pts)
+    ref = g.radius(2 << F, flags=orc.EXCLUDE_SELF)
+    g.close()
+    say("stash ids only, write asks dist2")
+    got, _ = _cycle(sx, lat, tab, q, sx.LaunchConfig(), False, True, 1.0)
+    assert_same(got, ref, "dist2 requested after an ids-only stash")
+    say("stash ids only, write ids only")
+    got, _ = _cycle(sx, lat, tab, q, sx.LaunchConfig(), False, False, 1.0)
+    assert_same((got[0], got[1], None), ref, "ids-only stash")
+
+
+def test_stash_with_fallback_and_knn_rows(sx, orc):
+    rng = np.random.default_rng(11)
+    log2, F = (5, 5, 4), 10
+    mask = 1
+    pts = tiny_points(rng, log2, F, mask, 25000, outside=True)
+    lat = _world(sx, log2, F, mask, pts)
+    tab = sx.Tables(lat, 2, 2 << F)  # radii above 2 cells fall back to the cube scan
+    Qn = 6000
+    W = [(1 << (log2[a] + F)) for a in range(3)]
+    cen = [rng.integers(0, W[a] + (W[a] // 8 if a else 0), size=Qn).astype(np.uint32) for a in range(3)]
+    r = rng.integers(0, 4 << F, size=Qn).astype(np.uint32)
+    k = np.where(rng.random(Qn) < 0.3, rng.integers(1, 40, size=Qn), 0).astype(np.uint32)
+    keep = (tuple(sx.to_dev_u32(c) for c in cen), sx.to_dev_u32(r), sx.to_dev_u32(k))
+    q = sx.make_queries(Qn, keep[0], keep[1], keep[2], sx.MODE_MIXED, 0)
+    g = orc.Grid(orc.Lattice(log2, F, mask), pts)
+    ref = g.mixed(k, r, queries=tuple(cen))
+    g.close()
+    for frac in (1.0, 0.5):
+        say(f"mixed stash frac={frac}")
+        got, _ = _cycle(sx, lat, tab, q, sx.LaunchConfig(), True, True, frac)
+        assert_same(got, ref, f"mixed batch with fallback rows, stash {frac}")
+    del keep
+
+
+def test_stash_repeated_cycles_full_size(sx, orc):
+    """The uneven-radius workload at full size, three count/write cycles on
+    one workspace with the stash sized once."""
+    import torch
+
+    from paper_cs_0608108_amd import synth
+    w = synth.radius_uneven_clipped()
+    lat = _world(sx, w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask, w.pts)
+    tab = sx.Tables(lat, 2, 4 * w.lat.edge)
+    rad = sx.to_dev_u32(w.r_fx)
+    q = sx.make_queries(w.n, None, rad, None, sx.MODE_RADIUS, 0)
+    buf = sx.QueryBuffers(w.n, 0, want_dist2=False)
+    sx.count(lat, tab, q, buf)
+    total = int(buf.row_ptr[-1].item())
+    buf.grow(total)
+    buf.reserve_stash(total)
+    g = orc.Grid(orc.Lattice(w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask), w.pts)
+    ref = g.radius(w.r_fx)
+    g.close()
+    for it in range(3):
+        say(f"full-size stash cycle {it}")
+        lat.build(*lat._dev)
+        sx.count(lat, tab, q, buf)
+        sx.write(lat, tab, q, buf)
+        torch.cuda.synchronize()
+        rp, ids, _ = buf.host()
+        assert_same((rp, ids, None), ref, f"cycle {it}")
+    code, flags = lat.status()
+    assert code == sx.OK and flags == 0
