@@ -216,6 +216,8 @@ typedef struct {
     void* event_end;     /* optional hipEvent_t, recorded just after that kernel (neither event is
                             recorded when Q = 0) */
     uint32_t no_stash;   /* 1: never keep rows in the workspace stash (see sphidx_csr) */
+    uint32_t grouped;    /* 1: the count pass takes radius queries in groups of several per
+                            wavefront (persistent schedule); 0: one query per wavefront */
 } sphidx_launch;
 
 /* Bytes of device scratch a query call on Q queries needs. */

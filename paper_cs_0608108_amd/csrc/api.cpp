@@ -87,7 +87,7 @@ TabArgs tab_args(const sphidx_tables* t) {
 }
 
 struct Launch {
-    uint32_t method, persistent, waves, tile, bpc, cap, tab_lds, interior, no_stash;
+    uint32_t method, persistent, waves, tile, bpc, cap, tab_lds, interior, no_stash, grouped;
     uint32_t* stats;
     hipEvent_t ev_begin, ev_end;
 };
@@ -104,6 +104,8 @@ sphidx_status resolve_launch(const sphidx_launch* in, const sphidx_tables* tab, 
     if (o.interior > 2) return SPHIDX_ERR_INVALID_ARG;
     o.no_stash = in ? in->no_stash : 0u;
     if (o.no_stash > 1) return SPHIDX_ERR_INVALID_ARG;
+    o.grouped = in ? in->grouped : 0u;
+    if (o.grouped > 1) return SPHIDX_ERR_INVALID_ARG;
     o.stats = in ? in->stats_dev : nullptr;
     o.ev_begin = in ? (hipEvent_t)in->event_begin : nullptr;
     o.ev_end = in ? (hipEvent_t)in->event_end : nullptr;
@@ -115,7 +117,7 @@ sphidx_status resolve_launch(const sphidx_launch* in, const sphidx_tables* tab, 
     if (o.method == SPHIDX_METHOD_SPHERE && !tab) return SPHIDX_ERR_INVALID_ARG;
     if (o.method == SPHIDX_METHOD_CUBE) o.tab_lds = 0;
     size_t tab_bytes = (o.tab_lds && tab) ? (tab->h_rows.size() * 4 + 15) / 16 * 16 : 0;
-    for (int pass = 1; pass <= 3; ++pass) {
+    for (int pass = 1; pass <= 5; ++pass) {
         if (query_lds_bytes(pass, o.cap, o.waves, 0) > kMaxBlockLds) return SPHIDX_ERR_INVALID_ARG;
         if (o.tab_lds && query_lds_bytes(pass, o.cap, o.waves, tab_bytes) > kMaxBlockLds) return SPHIDX_ERR_CAPACITY;
     }
@@ -123,9 +125,10 @@ sphidx_status resolve_launch(const sphidx_launch* in, const sphidx_tables* tab, 
 }
 
 // Query workspace: counters | descriptors[Q] | longq[Q] | fbq[Q] | walkq[Q] |
-// soff[Q] | scan partials, then the stash: every byte beyond the minimum.
+// soff[Q] | xq[Q] | scan partials, then the stash: every byte beyond the
+// minimum.
 struct QLayout {
-    size_t counters, desc, longq, fbq, walkq, soff, scan, total;
+    size_t counters, desc, longq, fbq, walkq, soff, xq, scan, total;
 };
 
 QLayout query_layout(uint32_t Q) {
@@ -142,6 +145,7 @@ QLayout query_layout(uint32_t Q) {
     l.fbq = take((size_t)Q * 4);
     l.walkq = take((size_t)Q * 4);
     l.soff = take((size_t)Q * 4);
+    l.xq = take((size_t)Q * 4);
     l.scan = take(scan_i64_tmp_bytes(Q));
     l.total = off;
     return l;
@@ -187,11 +191,13 @@ QArgs q_args(const sphidx_queries* q, sphidx_csr* csr, const Launch& ln) {
     A.fb_count = lists + SPHIDX_QSTRIDE;
     A.walk_count = lists + 2 * SPHIDX_QSTRIDE;
     A.stash_hdr = lists + 3 * SPHIDX_QSTRIDE;
+    A.xq_count = lists + 4 * SPHIDX_QSTRIDE;
     A.stash_ctr = lists + SPHIDX_NLISTS * SPHIDX_QSTRIDE;
     A.longq = (uint32_t*)(ws + ql.longq);
     A.fbq = (uint32_t*)(ws + ql.fbq);
     A.walkq = (uint32_t*)(ws + ql.walkq);
     A.soff = (uint32_t*)(ws + ql.soff);
+    A.xq = (uint32_t*)(ws + ql.xq);
     A.desc = (uint4*)(ws + ql.desc);
     A.stash_base = ws + ql.total;
     A.stats = ln.stats;
@@ -264,6 +270,10 @@ sphidx_status run_pass(int pass, const sphidx_lattice* lat, const sphidx_tables*
     // (not with the stash, which needs every object of a row)
     A.interior = !A.stash &&
                  (ln.interior == 2 || (ln.interior == 0 && (uint64_t)lat->n >= (uint64_t)lat->ncells));
+    // count pass: radius queries in groups of several per wavefront (the
+    // persistent schedule; not with per-query statistics or the interior
+    // shortcut, which the grouped kernel does not implement)
+    A.group = pass == 0 && ln.persistent && ln.grouped && !ln.stats && !A.interior;
     if (pass == 0) {
         s = dev_err(launch_query_pass(0, L, T, A, ln.waves, ln.bpc, st, ln.ev_begin, ln.ev_end));
         if (s != SPHIDX_OK) return s;

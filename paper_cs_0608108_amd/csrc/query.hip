@@ -376,7 +376,14 @@ __device__ __forceinline__ RowRef row_ranges(const LatArgs& L, uint32_t base, in
     }
     if (!live) p0 = p1 = p2 = p3 = 0;
     const uint32_t* row = L.cs + base;
-    const uint32_t v0 = row[p0], v1 = row[p1], v2 = row[p2], v3 = row[p3];
+    // a plain run is one range [p0, p3): its middle bounds are needed only
+    // when it wraps or has a wholly-inside part
+    const uint32_t v0 = row[p0], v3 = row[p3];
+    uint32_t v1 = v0, v2 = v0;
+    if (wrap || has_int) {
+        v1 = row[p1];
+        v2 = row[p2];
+    }
     RowRef r;
     r.st0 = v0;
     r.cnt0 = v1 - v0;
@@ -447,6 +454,11 @@ __device__ __forceinline__ RowRef cube_row(const LatArgs& L, const Query& s, uin
     uint32_t ty = (uint32_t)(s.lo[1] + (int32_t)iy), tz = (uint32_t)(s.lo[2] + (int32_t)iz);
     if (L.cyc & 2u) ty &= (1u << L.lg[1]) - 1u;
     if (L.cyc & 4u) tz &= (1u << L.lg[2]) - 1u;
+    if (!has) {
+        // lanes without a row read the first row (always a valid index)
+        ty = 0u;
+        tz = 0u;
+    }
     const uint32_t base = (tz << (L.lg[0] + L.lg[1])) | (ty << L.lg[0]);
     return row_ranges(L, base, s.lo[0], s.lo[0] + (int)s.nn[0] - 1, 1, 0, has);
 }
@@ -576,7 +588,7 @@ __device__ __forceinline__ void walk(const LatArgs& L, const TabArgs& T, const u
 // XCD-aware block order) or persistent (per-XCD work queues).
 
 template <typename F>
-__device__ __forceinline__ void for_each_query(uint32_t Q, const QArgs& A, uint32_t* queues, F&& f) {
+__device__ __forceinline__ void for_each_range(uint32_t Q, const QArgs& A, uint32_t* queues, F&& f) {
     if (Q == 0) return;
     const uint32_t lane = lane_id();
     const uint32_t wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -620,8 +632,15 @@ __device__ __forceinline__ void for_each_query(uint32_t Q, const QArgs& A, uint3
             e = (uint32_t)min((uint64_t)qe, (uint64_t)qs + t + A.tile);
         }
         first = false;
-        for (uint32_t qi = b; qi < e; ++qi) f(qi);
+        if (b < e) f(b, e);
     }
+}
+
+template <typename F>
+__device__ __forceinline__ void for_each_query(uint32_t Q, const QArgs& A, uint32_t* queues, F&& f) {
+    for_each_range(Q, A, queues, [&](uint32_t b, uint32_t e) {
+        for (uint32_t qi = b; qi < e; ++qi) f(qi);
+    });
 }
 
 // Stage the whole row table in LDS (shared by the block's waves).
@@ -715,10 +734,49 @@ __device__ void bucket_sort_store(const uint64_t* td, const uint32_t* ti, uint64
 // Pass 0: row sizes
 
 // Queue sets of the work counters.
-constexpr int kQCount = 0, kQWrite = 1, kQTopm = 2, kQFbCount = 3, kQFbWrite = 4, kQWalk = 5;
+constexpr int kQCount = 0, kQWrite = 1, kQTopm = 2, kQFbCount = 3, kQFbWrite = 4, kQWalk = 5, kQExtra = 6;
 
 __device__ __forceinline__ uint32_t* queue_set(const QArgs& A, int set) {
     return A.queues + (size_t)set * SPHIDX_NQUEUE * SPHIDX_QSTRIDE;
+}
+
+// Rows of at most 64 pairs whose key fits one 64-bit word: with id < 2^idbits
+// and dist^2 < 2^(64 - idbits), (dist^2 << idbits) | id orders exactly as
+// (dist^2, id) and is unique, so a pair's place is the number of smaller
+// keys.  One pair per lane; the keys are read back as LDS broadcasts.
+__device__ void sort_small_store(const uint64_t* td, const uint32_t* ti, uint64_t* ck, uint32_t n, uint32_t idbits,
+                                 uint32_t* dst_ids, int64_t* dst_d2) {
+    const uint32_t lane = lane_id();
+    uint64_t d = 0, k = ~0ull;
+    uint32_t id = 0;
+    if (lane < n) {
+        d = td[lane];
+        id = ti[lane];
+        k = (d << idbits) | id;
+    }
+    ck[lane] = k;  // lanes past n: the largest key, padding for the paired reads
+    wave_sync();
+    uint32_t rank = 0;
+    for (uint32_t j = 0; j < n; j += 2) {
+        const ulonglong2 p = *(const ulonglong2*)(ck + j);
+        rank += (p.x < k ? 1u : 0u) + (p.y < k ? 1u : 0u);
+    }
+    if (lane < n) {
+        dst_ids[rank] = id;
+        if (dst_d2) dst_d2[rank] = (int64_t)d;
+    }
+    wave_sync();
+}
+
+// Order the n <= cap pairs of one row by (dist^2, id) and store them at dst.
+__device__ __forceinline__ void sort_row_store(const uint64_t* td, const uint32_t* ti, uint64_t* sd, uint32_t* si,
+                                               uint32_t* hist, uint32_t n, uint64_t r2, uint32_t idbits,
+                                               uint32_t* dst_ids, int64_t* dst_d2) {
+    const uint32_t r2bits = r2 ? 64u - (uint32_t)__builtin_clzll(r2) : 0u;
+    if (n <= 64 && r2bits + idbits <= 64)
+        sort_small_store(td, ti, sd, n, idbits, dst_ids, dst_d2);
+    else
+        bucket_sort_store(td, ti, sd, si, hist, n, r2, dst_ids, dst_d2);
 }
 
 // FROM_LIST: a query list (the sphere method's fallback queries, scanned with
@@ -746,6 +804,7 @@ __global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs 
     const uint32_t region = blockIdx.x % SPHIDX_NQUEUE;
     uint32_t cur = 0, lim = 0;
     bool dry = false;
+    const uint32_t idbits = L.n > 1 ? 32u - (uint32_t)__builtin_clz(L.n - 1u) : 0u;  // ids are below n
     for_each_query(nq, A, queue_set(A, FROM_LIST ? (int)A.list_set : kQCount), [&](uint32_t ti_) {
         const uint32_t qi = FROM_LIST ? uni(A.list[ti_]) : ti_;
         const Query s = load_query(L, A, qi);
@@ -806,8 +865,8 @@ __global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs 
                 }
                 if (ok) {
                     wave_sync();
-                    bucket_sort_store(td, ti, sd, si, hist, hits, s.r2, A.stash_ids + cur,
-                                      A.stash_d2 ? A.stash_d2 + cur : nullptr);
+                    sort_row_store(td, ti, sd, si, hist, hits, s.r2, idbits, A.stash_ids + cur,
+                                   A.stash_d2 ? A.stash_d2 + cur : nullptr);
                     wave_sync();
                     off = cur;
                     cur += hits;
@@ -828,6 +887,329 @@ __global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs 
                 stp[2] = cand;
                 stp[3] = ncube;
             }
+        }
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Pass 0, radius queries in groups: a wavefront takes kGroup consecutive
+// queries and spreads all their table rows over its lanes, 64 rows per
+// step, and all their candidate objects, 64 per step, so that short rows
+// and small radii fill whole steps.  Hits of the group are collected as
+// one 64-bit key (query slot, dist^2, id) each, and one bucket sort orders
+// the group's rows together; with the stash they are kept in one chunk.
+// Queries it does not take (K-NN, keys that would not fit 64 bits) go to
+// the extra list for the one-query-per-wave kernel.
+
+constexpr uint32_t kGroup = 8, kGroupBits = 3, kHitCap = 512;
+// a group ends before its rows would exceed two row steps: at about one or
+// two hits per row (objects per cell below about one) its hits fit kHitCap
+constexpr uint32_t kGroupRows = 128;
+
+// Per-wave LDS of the grouped kernel: slot data (kGroup x 64 B), 32 words of
+// per-slot counters, the 64-word owner map, then (stash) the hit keys in
+// arrival order, the same by bucket, and the bucket counts.
+__host__ __device__ constexpr size_t group_lds_per_wave(bool stash) {
+    return 512 + 128 + 256 + (stash ? (size_t)kHitCap * 20 : 0);
+}
+
+// dist^2 field of a group hit key (slot | dist^2 | id)
+__device__ __forceinline__ uint64_t key_d2(uint64_t k, uint32_t idbits, uint32_t d2bits) {
+    return (k >> idbits) & ((1ull << d2bits) - 1ull);
+}
+
+template <int METHOD, bool TLDS, bool STASH>
+__global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, QArgs A) {
+    extern __shared__ __align__(16) char smem[];
+    const uint32_t* tab_lds = stage_table<TLDS>(T, smem);
+    const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
+    char* wb = smem + table_lds_bytes<TLDS>(T) + (size_t)wave * group_lds_per_wave(STASH);
+    uint4* qp = (uint4*)wb;                    // per slot: centre + table start, r^2 + self + rows,
+                                               // cube extent, flags + row
+    uint32_t* cnt = (uint32_t*)(wb + 512);     // [0, 8) hits, [8, 16) row start, [16, 24) hits,
+    uint32_t* qst = cnt + 8;                   // [24, 32) bucket scale (float)
+    uint32_t* qn = cnt + 16;
+    float* qsc = (float*)(cnt + 24);
+    uint32_t* own = cnt + 32;                  // 64: owner map
+    uint64_t* hb = (uint64_t*)(own + 64);      // kHitCap keys in arrival order
+    uint64_t* hs = hb + kHitCap;               // kHitCap keys by bucket
+    uint32_t* hh = (uint32_t*)(hs + kHitCap);  // kHitCap bucket counts, then starts
+    const AxisWrap aw = axis_wrap(L);
+    const uint32_t idbits = L.n > 1 ? 32u - (uint32_t)__builtin_clz(L.n - 1u) : 0u;
+    const uint32_t d2bits = 64u - kGroupBits - idbits;
+    const uint64_t idmask = idbits ? (~0ull >> (64u - idbits)) : 0ull;
+    const uint32_t region = blockIdx.x % SPHIDX_NQUEUE;
+    uint32_t cur = 0, lim = 0;
+    bool dry = false;
+    for_each_range(A.Q, A, queue_set(A, kQCount), [&](uint32_t b, uint32_t e) {
+        for (uint32_t g0 = b, ng = 0; g0 < e; g0 += ng) {
+            const uint32_t cand = min(kGroup, e - g0);
+            // ---- slots: lane l < cand looks at query g0 + l; the group keeps
+            // the leading slots whose rows fit kGroupRows (at least one)
+            const uint32_t qi = g0 + lane;
+            uint32_t rows = 0, row = 0;
+            bool mine = false, extra = false, invalid = false;
+            uint4 d0 = make_uint4(0, 0, 0, 0), d1 = d0, d2 = d0, d3 = d0;
+            if (lane < cand) {
+                d0 = A.desc[4 * (size_t)qi];
+                d1 = A.desc[4 * (size_t)qi + 1];
+                d2 = A.desc[4 * (size_t)qi + 2];
+                d3 = A.desc[4 * (size_t)qi + 3];
+                row = d0.w;
+                const uint32_t flags = d1.z;
+                const uint64_t r2 = (uint64_t)d1.x * d1.x;
+                const uint32_t r2bits = r2 ? 64u - (uint32_t)__builtin_clzll(r2) : 0u;
+                const bool valid = flags & F_VALID, sph = flags & F_SPHERE;
+                if (!valid) {
+                    invalid = true;
+                } else if (METHOD == kSphere && !sph) {
+                    // counted by the fallback list's cube kernel
+                } else if ((flags & F_KNN) || r2bits > d2bits) {
+                    extra = true;
+                } else {
+                    mine = true;
+                    rows = (sph ? d2.x : d2.w * d3.w) + ((flags & F_OUTSIDE) ? 1u : 0u);
+                }
+            }
+            {
+                const uint32_t pre_incl = scan_add(rows);
+                const uint64_t fits = __ballot(lane < cand && pre_incl <= kGroupRows);
+                ng = max(1u, (uint32_t)__popcll(fits));
+            }
+            if (lane >= ng) {
+                rows = 0;
+                mine = extra = invalid = false;
+            }
+            if (invalid) {
+                A.row_ptr[row] = 0;
+                if (STASH) A.soff[qi] = 0u;
+            }
+            if (mine) {
+                const uint64_t r2 = (uint64_t)d1.x * d1.x;
+                const uint32_t self = (A.qx == nullptr && (A.flags & SPHIDX_EXCLUDE_SELF)) ? qi : kMaxId;
+                uint4* p = qp + 4 * lane;
+                p[0] = make_uint4(d0.x, d0.y, d0.z, d1.w);
+                p[1] = make_uint4((uint32_t)r2, (uint32_t)(r2 >> 32), self, rows);
+                p[2] = make_uint4(d3.x, d3.y, d3.z, d2.z);
+                p[3] = make_uint4(d2.w, d3.w, d1.z, row);
+            }
+            if (lane < kGroup) cnt[lane] = 0u;
+            {
+                // the queries left to the one-query-per-wave kernel
+                const uint64_t xm = __ballot(extra);
+                uint32_t xb = 0;
+                if (xm != 0 && lane == 0) xb = atomicAdd(A.xq_count, (uint32_t)__popcll(xm));
+                xb = uni(xb);
+                if (extra) A.xq[xb + lanes_below(xm)] = qi;
+            }
+            wave_sync();
+            const uint32_t incl = scan_add(rows);
+            const uint32_t R = lane_val(incl, 63);
+            const uint32_t excl = incl - rows;
+            uint32_t hcount = 0;
+            for (uint32_t base = 0; base < R; base += 64) {
+                // ---- this lane's row: owner slot and entry
+                own[lane] = 0;
+                wave_sync();
+                if (rows > 0 && excl < base + 64 && incl > base) own[excl > base ? excl - base : 0] = lane + 1;
+                wave_sync();
+                const uint32_t fr = base + lane;
+                const bool act = fr < R;
+                const uint32_t gmax = scan_max(own[lane]);
+                const uint32_t gs = act ? gmax - 1u : 0u;
+                const uint32_t ent = fr - bperm(excl, gs);
+                const uint4* p = qp + 4 * gs;
+                const uint4 pa = p[0], pb = p[1], pc = p[2], pd = p[3];
+                Query sq;
+                sq.q[0] = pa.x;
+                sq.q[1] = pa.y;
+                sq.q[2] = pa.z;
+                sq.tb = pa.w;
+                sq.r2 = (uint64_t)pb.x | ((uint64_t)pb.y << 32);
+                sq.self = pb.z;
+                sq.lo[0] = (int32_t)pc.x;
+                sq.lo[1] = (int32_t)pc.y;
+                sq.lo[2] = (int32_t)pc.z;
+                sq.nn[0] = pc.w;
+                sq.nn[1] = pd.x;
+                sq.nn[2] = pd.y;
+                sq.flags = pd.z;
+                const uint32_t e1 = 1u << L.F;
+                for (int a = 0; a < 3; ++a) {
+                    sq.c[a] = sq.q[a] >> L.F;
+                    sq.f[a] = sq.q[a] & (e1 - 1u);
+                    sq.up[a] = e1 - sq.f[a];
+                    sq.dn[a] = sq.f[a] + 1u;
+                }
+                const bool is_out = act && (sq.flags & F_OUTSIDE) && ent + 1u == pb.w;
+                const bool sph = METHOD == kSphere || (METHOD == kEither && (sq.flags & F_SPHERE));
+                const bool live = act && !is_out;
+                RowRef r;
+                if (sph) {
+                    const uint32_t* rws = TLDS ? tab_lds : T.rows;
+                    const uint32_t w = live ? rws[sq.tb + ent] : 0u;
+                    r = sphere_row(L, sq, w, live, sq.r2, false);
+                } else {
+                    const double inv_ny = sq.nn[1] ? 1.0 / (double)sq.nn[1] : 0.0;
+                    r = cube_row(L, sq, live ? ent : 0u, live, inv_ny);
+                }
+                if (is_out) {
+                    // every object outside the region lives in one cell (Section II.B)
+                    r.st0 = L.cs[L.ncells];
+                    r.cnt0 = L.cs[L.ncells + 1] - r.st0;
+                    r.cnt1 = 0u;
+                }
+                // ---- the candidates of these rows, 64 per step
+                const uint32_t tl = r.cnt0 + r.cnt1;
+                const uint32_t cincl = scan_add(tl);
+                const uint32_t ctot = lane_val(cincl, 63);
+                const uint32_t cexcl = cincl - tl;
+                const uint32_t smx0 = r.st0 - cexcl, bnd = cexcl + r.cnt0, smx1 = r.st1 - bnd;
+                for (uint32_t cb = 0; cb < ctot; cb += 64) {
+                    wave_sync();
+                    own[lane] = 0;
+                    wave_sync();
+                    if (tl > 0 && cexcl < cb + 64 && cincl > cb) own[cexcl > cb ? cexcl - cb : 0] = lane + 1;
+                    wave_sync();
+                    const uint32_t o = scan_max(own[lane]) - 1u;
+                    const uint32_t g = cb + lane;
+                    const bool cact = g < ctot;
+                    // cross-lane reads outside any condition: a permute from
+                    // a lane masked off by a branch would read 0
+                    const uint32_t bo = bperm(bnd, o);
+                    const uint32_t p0 = bperm(smx0, o) + g;
+                    const uint32_t p1 = bperm(smx1, o) + g;
+                    const uint32_t pos = g < bo ? p0 : p1;
+                    const uint32_t sl = bperm(gs, o);
+                    uint4 P = make_uint4(0u, 0u, 0u, kMaxId);
+                    if (cact) P = L.pts[pos];
+                    const uint4 ca = qp[4 * sl], cq = qp[4 * sl + 1];
+                    Query cs;
+                    cs.q[0] = ca.x;
+                    cs.q[1] = ca.y;
+                    cs.q[2] = ca.z;
+                    const uint64_t d2 = obj_dist2(aw, cs, P);
+                    const uint64_t r2 = (uint64_t)cq.x | ((uint64_t)cq.y << 32);
+                    const bool hit = cact && d2 <= r2 && pos != cq.z;
+                    const uint64_t H = __ballot(hit);
+                    // hits per slot: each run of slots of one query adds its
+                    // share of the ballot once (runs are contiguous)
+                    const uint32_t prev = bperm(sl, (lane + 63u) & 63u);
+                    const bool leader = cact && (lane == 0 || sl != prev);
+                    const uint64_t lm = __ballot(leader);
+                    if (leader && H != 0) {
+                        const uint64_t above = lane == 63 ? 0ull : (lm >> (lane + 1)) << (lane + 1);
+                        const uint64_t upto = above ? ((above & (~above + 1ull)) - 1ull) : ~0ull;
+                        const uint64_t seg = upto & ~((1ull << lane) - 1ull);
+                        const uint32_t c = (uint32_t)__popcll(H & seg);
+                        if (c) atomicAdd(&cnt[sl], c);
+                    }
+                    if (STASH) {
+                        const uint32_t hp = hcount + lanes_below(H);
+                        if (hit && hp < kHitCap)
+                            hb[hp] = ((uint64_t)sl << (64u - kGroupBits)) | (d2 << idbits) | (uint64_t)P.w;
+                        hcount += (uint32_t)__popcll(H);
+                    }
+                }
+                wave_sync();
+            }
+            // ---- row sizes
+            uint32_t nq = 0;
+            if (mine) {
+                nq = cnt[lane];
+                A.row_ptr[row] = (int64_t)nq;
+            }
+            if (STASH) {
+                const uint32_t total = hcount;
+                bool ok = total <= kHitCap;
+                if (ok && total > 0 && cur + total > lim) {
+                    ok = false;
+                    if (!dry) {
+                        const uint32_t grab = max(A.stash_chunk, total);
+                        uint32_t t = 0;
+                        if (lane == 0) t = atomicAdd(A.stash_ctr + region * SPHIDX_QSTRIDE, grab);
+                        t = uni(t);
+                        if ((uint64_t)t + grab <= A.stash_region) {
+                            cur = region * A.stash_region + t;
+                            lim = cur + grab;
+                            ok = true;
+                        } else {
+                            dry = true;
+                        }
+                    }
+                }
+                const uint32_t qs0 = scan_add(nq) - nq;
+                if (ok && total > 0) {
+                    if (lane < kGroup) {
+                        qst[lane] = qs0;
+                        qn[lane] = nq;
+                        const uint4 pb = qp[4 * lane + 1];
+                        const uint64_t r2 = (uint64_t)pb.x | ((uint64_t)pb.y << 32);
+                        qsc[lane] = (mine && r2 > 0) ? (float)nq / (float)r2 : 0.0f;
+                    }
+                    for (uint32_t t = lane; t < total; t += 64) hh[t] = 0u;
+                    wave_sync();
+                    // bucket of a key: its slot's rows start + floor(n * d^2 / r^2)
+                    auto bucket = [&](uint64_t k) -> uint32_t {
+                        const uint32_t sl = (uint32_t)(k >> (64u - kGroupBits));
+                        const uint32_t n = qn[sl];
+                        const uint32_t bi = min((uint32_t)((float)key_d2(k, idbits, d2bits) * qsc[sl]), n - 1u);
+                        return qst[sl] + bi;
+                    };
+                    uint32_t slot[kHitCap / 64];
+#pragma unroll
+                    for (uint32_t k = 0; k < kHitCap / 64; ++k) {
+                        const uint32_t t = lane + 64u * k;
+                        if (t < total) slot[k] = atomicAdd(&hh[bucket(hb[t])], 1u);
+                    }
+                    wave_sync();
+                    const uint32_t per = (total + 63u) >> 6;
+                    const uint32_t bb = lane * per;
+                    uint32_t sum = 0;
+                    for (uint32_t k = 0; k < per; ++k)
+                        if (bb + k < total) sum += hh[bb + k];
+                    uint32_t run = scan_add(sum) - sum;
+                    wave_sync();
+                    for (uint32_t k = 0; k < per; ++k)
+                        if (bb + k < total) {
+                            const uint32_t c = hh[bb + k];
+                            hh[bb + k] = run;
+                            run += c;
+                        }
+                    wave_sync();
+#pragma unroll
+                    for (uint32_t k = 0; k < kHitCap / 64; ++k) {
+                        const uint32_t t = lane + 64u * k;
+                        if (t < total) {
+                            const uint64_t key = hb[t];
+                            hs[hh[bucket(key)] + slot[k]] = key;
+                        }
+                    }
+                    wave_sync();
+                    for (uint32_t t = lane; t < total; t += 64) {
+                        const uint64_t key = hs[t];
+                        const uint32_t bi = bucket(key);
+                        const uint32_t lo = hh[bi], hi = bi + 1 < total ? hh[bi + 1] : total;
+                        uint32_t rank = lo;
+                        for (uint32_t j = lo; j < hi; ++j) rank += hs[j] < key ? 1u : 0u;
+                        A.stash_ids[cur + rank] = (uint32_t)(key & idmask);
+                        if (A.stash_d2) A.stash_d2[cur + rank] = (int64_t)key_d2(key, idbits, d2bits);
+                    }
+                    wave_sync();
+                    if (mine) A.soff[qi] = cur + qs0;
+                    cur += total;
+                } else {
+                    // not kept: the write pass walks these rows again
+                    const bool walk_again = mine && nq > 0;
+                    if (mine) A.soff[qi] = walk_again ? kMaxId : 0u;
+                    const uint64_t wm = __ballot(walk_again);
+                    uint32_t wb0 = 0;
+                    if (wm != 0 && lane == 0) wb0 = atomicAdd(A.walk_count, (uint32_t)__popcll(wm));
+                    wb0 = uni(wb0);
+                    if (walk_again) A.walkq[wb0 + lanes_below(wm)] = qi;
+                }
+            }
+            wave_sync();
         }
     });
 }
@@ -858,6 +1240,7 @@ __global__ __launch_bounds__(256) void write_kernel(LatArgs L, TabArgs T, QArgs 
     // the main launch takes the walk list, the list launch skips kept rows
     const bool stashed = A.stash_hdr[kHdrMode] != 0u;
     const bool from_walk = !FROM_LIST && stashed;
+    const uint32_t idbits = L.n > 1 ? 32u - (uint32_t)__builtin_clz(L.n - 1u) : 0u;  // ids are below n
     const uint32_t nq = FROM_LIST ? uni(*A.list_count) : (from_walk ? uni(*A.walk_count) : A.Q);
     for_each_query(nq, A, queue_set(A, FROM_LIST ? (int)A.list_set : (from_walk ? kQWalk : kQWrite)),
                    [&](uint32_t ti_) {
@@ -893,7 +1276,8 @@ __global__ __launch_bounds__(256) void write_kernel(LatArgs L, TabArgs T, QArgs 
             return for_candidates(L, r.st0, r.cnt0, r.st1, r.cnt1, own, cand, visit);
         });
         wave_sync();
-        bucket_sort_store(td, ti, sd, si, hist, min(n, rowlen), s.r2, A.out_ids + rb, A.out_d2 ? A.out_d2 + rb : nullptr);
+        sort_row_store(td, ti, sd, si, hist, min(n, rowlen), s.r2, idbits, A.out_ids + rb,
+                       A.out_d2 ? A.out_d2 + rb : nullptr);
         wave_sync();
     });
 }
@@ -1160,11 +1544,13 @@ int device_cu_count() {
     return cus;
 }
 
-// LDS bytes per block: pass 0 count (3 with the stash), 1 write, 2 top-M.
+// LDS bytes per block: pass 0 count (3 with the stash), 1 write, 2 top-M,
+// 4 grouped count (5 with the stash).
 size_t query_lds_bytes(int pass, uint32_t cap, uint32_t waves, size_t table_bytes) {
     size_t per = 256;
     if (pass == 1 || pass == 3) per = (size_t)cap * 28 + 256;
     if (pass == 2) per = (size_t)cap * 24 + 64 * 12 + 256;
+    if (pass == 4 || pass == 5) per = group_lds_per_wave(pass == 5);
     return table_bytes + per * waves;
 }
 
@@ -1206,13 +1592,34 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
     if (pass == 0) {
         const int lp = q.stash ? 3 : 0;
         if ((e = mark(ev_begin)) != hipSuccess) return e;
-        if (q.stash)
-            e = launch_ptr(SPHIDX_PICK(count_kernel, variant, kSphere, , false, true), q.Q, q, w, b,
-                           query_lds_bytes(lp, q.sort_cap, w, tb), st, L, T);
-        else
-            e = launch_ptr(SPHIDX_PICK(count_kernel, variant, kSphere, , false, false), q.Q, q, w, b,
-                           query_lds_bytes(lp, q.sort_cap, w, tb), st, L, T);
-        if (e == hipSuccess) e = mark(ev_end);
+        if (q.group) {
+            // radius queries in groups; the rest through the extra list
+            if (q.stash)
+                e = launch_ptr(SPHIDX_PICK(group_count_kernel, variant, kSphere, , true), q.Q, q, w, b,
+                               query_lds_bytes(5, q.sort_cap, w, tb), st, L, T);
+            else
+                e = launch_ptr(SPHIDX_PICK(group_count_kernel, variant, kSphere, , false), q.Q, q, w, b,
+                               query_lds_bytes(4, q.sort_cap, w, tb), st, L, T);
+            if (e == hipSuccess) e = mark(ev_end);
+            if (e != hipSuccess) return e;
+            ql.list = q.xq;
+            ql.list_count = q.xq_count;
+            ql.list_set = kQExtra;
+            if (q.stash)
+                e = launch_ptr(SPHIDX_PICK(count_kernel, variant, kEither, , true, true), 0, ql, w, b,
+                               query_lds_bytes(lp, q.sort_cap, w, tb), st, L, T);
+            else
+                e = launch_ptr(SPHIDX_PICK(count_kernel, variant, kEither, , true, false), 0, ql, w, b,
+                               query_lds_bytes(lp, q.sort_cap, w, tb), st, L, T);
+        } else {
+            if (q.stash)
+                e = launch_ptr(SPHIDX_PICK(count_kernel, variant, kSphere, , false, true), q.Q, q, w, b,
+                               query_lds_bytes(lp, q.sort_cap, w, tb), st, L, T);
+            else
+                e = launch_ptr(SPHIDX_PICK(count_kernel, variant, kSphere, , false, false), q.Q, q, w, b,
+                               query_lds_bytes(lp, q.sort_cap, w, tb), st, L, T);
+            if (e == hipSuccess) e = mark(ev_end);
+        }
         if (e != hipSuccess || variant == 0) return e;
         ql.list = q.fbq;
         ql.list_count = q.fb_count;

@@ -105,6 +105,8 @@ struct QArgs {
     uint32_t* fbq;      // sphere method: queries the tables do not cover (cube scan)
     uint32_t* walk_count;
     uint32_t* walkq;    // stash mode: queries the count pass did not stash
+    uint32_t* xq_count;
+    uint32_t* xq;       // grouped count: queries left to the one-query-per-wave kernel
     uint32_t* soff;     // stash mode: per query, first stash element of its sorted row
     uint32_t* stash_hdr;  // stash header written by the count pass (see StashHdr)
     uint32_t* stash_ctr;  // NQUEUE per-region allocation counters
@@ -124,6 +126,7 @@ struct QArgs {
     uint32_t tile;
     uint32_t sort_cap;
     uint32_t interior;  // count pass: count wholly-inside cells without reading them
+    uint32_t group;     // count pass: radius queries in groups per wavefront
 };
 
 // Stash header words (in the counter block): written by the count pass,
@@ -132,8 +135,8 @@ enum : uint32_t { kHdrMode = 0, kHdrElems = 1, kHdrHasD2 = 2, kHdrD2Off = 3 };
 
 #define SPHIDX_NQUEUE 8         // one work queue per XCD of the MI355X
 #define SPHIDX_QSTRIDE 32       // counters 128 bytes apart: one L2 line each
-#define SPHIDX_NQSETS 6         // count, write, top-M, fallback count, fallback write, walk list
-#define SPHIDX_NLISTS 4         // long_count, fb_count, walk_count, stash header
+#define SPHIDX_NQSETS 7         // count, write, top-M, fallback count, fallback write, walk list, extra list
+#define SPHIDX_NLISTS 5         // long_count, fb_count, walk_count, stash header, xq_count
 #define SPHIDX_COUNTER_WORDS \
     ((SPHIDX_NQSETS * SPHIDX_NQUEUE + SPHIDX_NLISTS + SPHIDX_NQUEUE) * SPHIDX_QSTRIDE)
 #define SPHIDX_MAX_LOG2_SUM 30

@@ -54,7 +54,8 @@ class CSRDesc(ctypes.Structure):
 class LaunchDesc(ctypes.Structure):
     _fields_ = [("method", U32), ("schedule", U32), ("waves_per_block", U32), ("tile", U32),
                 ("blocks_per_cu", U32), ("sort_cap", U32), ("table_in_lds", U32), ("interior", U32),
-                ("stats_dev", P), ("event_begin", P), ("event_end", P), ("no_stash", U32)]
+                ("stats_dev", P), ("event_begin", P), ("event_end", P), ("no_stash", U32),
+                ("grouped", U32)]
 
 
 # Every symbol include/sphidx.h declares, with its ctypes signature.
@@ -273,6 +274,7 @@ class LaunchConfig:
     stats: torch.Tensor | None = None
     events: tuple | None = None  # (begin, end) torch.cuda.Event around the pass's main kernel
     no_stash: int = 0
+    grouped: int = 0
 
     def c(self) -> LaunchDesc:
         d = LaunchDesc()
@@ -281,6 +283,7 @@ class LaunchConfig:
         d.sort_cap, d.table_in_lds = self.sort_cap, self.table_in_lds
         d.interior = self.interior
         d.no_stash = self.no_stash
+        d.grouped = self.grouped
         d.stats_dev = None if self.stats is None else self.stats.data_ptr()
         if self.events is not None:
             for ev in self.events:

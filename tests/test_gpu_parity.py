@@ -25,6 +25,8 @@ def _launches(sx):
     L = sx.LaunchConfig
     return {
         "sphere-persistent": L(method=sx.METHOD_SPHERE, schedule=sx.SCHED_PERSISTENT),
+        "sphere-grouped": L(method=sx.METHOD_SPHERE, schedule=sx.SCHED_PERSISTENT, grouped=1),
+        "cube-grouped": L(method=sx.METHOD_CUBE, schedule=sx.SCHED_PERSISTENT, grouped=1),
         "sphere-plain": L(method=sx.METHOD_SPHERE, schedule=sx.SCHED_PLAIN),
         "sphere-small-cap": L(method=sx.METHOD_SPHERE, schedule=sx.SCHED_PERSISTENT, sort_cap=64, tile=1,
                               waves_per_block=2),
@@ -118,7 +120,7 @@ def test_packed_index_and_outside_cell_follow_the_paper_example(sx):
 # Hand fixtures (Section II.A definitions worked by hand)
 
 @pytest.mark.parametrize("name", ["hand_cyclic.txt", "hand_clipped.txt"])
-@pytest.mark.parametrize("launch", ["sphere-persistent", "sphere-plain", "cube"])
+@pytest.mark.parametrize("launch", ["sphere-persistent", "sphere-plain", "cube", "sphere-grouped"])
 def test_hand_fixtures(sx, name, launch):
     latd, pts, rows = read_hand(name)
     lat = lattice(sx, latd["log2_cells"], latd["frac_bits"], latd["cyclic_mask"], pts)

@@ -66,7 +66,8 @@ def test_stash_radius_rows_match_oracle(sx, orc, mask, stash_frac):
     g = orc.Grid(L, pts)
     ref = g.radius(r)
     g.close()
-    for launch in (sx.LaunchConfig(), sx.LaunchConfig(schedule=sx.SCHED_PLAIN, sort_cap=64, tile=2)):
+    for launch in (sx.LaunchConfig(), sx.LaunchConfig(grouped=1),
+                   sx.LaunchConfig(schedule=sx.SCHED_PLAIN, sort_cap=64, tile=2)):
         say(f"stash mask={mask} frac={stash_frac} launch={launch.schedule}/{launch.sort_cap}")
         got, total = _cycle(sx, lat, tab, q, launch, True, True, stash_frac)
         assert_same(got, ref, f"stash frac {stash_frac}")
@@ -108,9 +109,9 @@ def test_stash_with_fallback_and_knn_rows(sx, orc):
     g = orc.Grid(orc.Lattice(log2, F, mask), pts)
     ref = g.mixed(k, r, queries=tuple(cen))
     g.close()
-    for frac in (1.0, 0.5):
-        say(f"mixed stash frac={frac}")
-        got, _ = _cycle(sx, lat, tab, q, sx.LaunchConfig(), True, True, frac)
+    for frac, grouped in ((1.0, 0), (0.5, 0), (1.0, 1), (0.5, 1)):
+        say(f"mixed stash frac={frac} grouped={grouped}")
+        got, _ = _cycle(sx, lat, tab, q, sx.LaunchConfig(grouped=grouped), True, True, frac)
         assert_same(got, ref, f"mixed batch with fallback rows, stash {frac}")
     del keep
 
