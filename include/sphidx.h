@@ -231,9 +231,11 @@ size_t sphidx_query_workspace_bytes(uint32_t Q);
 sphidx_status sphidx_count(const sphidx_lattice* lat, const sphidx_tables* tab, const sphidx_queries* q,
                            sphidx_csr* csr, const sphidx_launch* launch, void* stream);
 
-/* Pass 2: fill ids (and dist2) of every row using row_ptr from sphidx_count
- * on the same inputs.  If row_ptr[Q] > capacity it sets SPHIDX_FLAG_CAPACITY
- * and writes nothing (checked on the device, so it can run under capture). */
+/* Pass 2: fill ids (and dist2) of every row using row_ptr and the query
+ * descriptors and lists that sphidx_count left in the workspace: same
+ * inputs, same launch method, same workspace, unchanged in between.  If
+ * row_ptr[Q] > capacity it sets SPHIDX_FLAG_CAPACITY and writes nothing
+ * (checked on the device, so it can run under capture). */
 sphidx_status sphidx_write(const sphidx_lattice* lat, const sphidx_tables* tab, const sphidx_queries* q,
                            sphidx_csr* csr, const sphidx_launch* launch, void* stream);
 

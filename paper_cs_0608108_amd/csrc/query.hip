@@ -121,6 +121,31 @@ __device__ __forceinline__ void wave_sort64(uint64_t& d, uint32_t& id) {
     }
 }
 
+// Sort a bitonic sequence of one (d2, id) key per lane ascending.
+__device__ __forceinline__ void wave_bitonic_clean64(uint64_t& d, uint32_t& id) {
+    const uint32_t l = lane_id();
+#pragma unroll
+    for (uint32_t j = 32; j > 0; j >>= 1) {
+        uint32_t plo = __shfl_xor((uint32_t)d, j);
+        uint32_t phi = __shfl_xor((uint32_t)(d >> 32), j);
+        uint32_t pid = __shfl_xor(id, j);
+        uint64_t pd = ((uint64_t)phi << 32) | plo;
+        bool take = (l & j) == 0 ? key_less(pd, pid, d, id) : key_less(d, id, pd, pid);
+        if (take) {
+            d = pd;
+            id = pid;
+        }
+    }
+}
+
+__device__ __forceinline__ uint64_t lane_val64(uint64_t v, uint32_t l) {
+    return ((uint64_t)lane_val((uint32_t)(v >> 32), l) << 32) | lane_val((uint32_t)v, l);
+}
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, uint32_t src) {
+    return ((uint64_t)__shfl((uint32_t)(v >> 32), src) << 32) | (uint32_t)__shfl((uint32_t)v, src);
+}
+
 // Exact quotient (a < 2^31, 1 <= b < 2^31) from a double reciprocal and one
 // correction step.
 __device__ __forceinline__ uint32_t exact_div(uint32_t a, uint32_t b, double inv_b) {
@@ -1339,11 +1364,96 @@ __global__ __launch_bounds__(256) void topm_kernel(LatArgs L, TabArgs T, QArgs A
             // and the window restarted whenever fewer than M lie within it
             float rho;
             if (s.flags & F_KNN)
-                rho = 1.25f * e * cbrtf(0.2387f * (float)target / fmaxf(dens, 1e-6f)) + 0.5f * e;
+                rho = 1.25f * e * cbrtf(0.2387f * (float)target / fmaxf(dens, 1e-6f));
             else
                 rho = 1.1f * (float)s.r * cbrtf((float)target / (float)rowlen);
             uint64_t B = rho >= (float)s.r ? s.r2 : min(s.r2, (uint64_t)((double)rho * (double)rho));
             if (!(s.flags & F_SPHERE)) B = s.r2;  // the bounding cube is scanned whole anyway
+            if (M <= 64) {
+                // ---- a window of at most 64 in registers: lane i holds the
+                // i-th best pair.  A few new pairs are inserted one by one
+                // (place = pairs ahead of it, the rest move up one lane); a
+                // large batch is sorted and merged (the 64 smallest of list
+                // and batch, as a bitonic sequence, then sorted).
+                uint64_t rd = kMaxD2, kd = kMaxD2;
+                uint32_t ri = kMaxId, kid = kMaxId, held = 0, cand2 = 0, walked2 = 0;
+                auto visit_r = [&](bool act, uint32_t p, const uint4& P) -> bool {
+                    const uint64_t d2 = obj_dist2(aw, s, P);
+                    const uint32_t id = P.w;
+                    bool cv = act && d2 <= B && p != s.self;
+                    if (cv && has_lower) cv = key_less(ld, li, d2, id);
+                    if (cv && held >= M) cv = key_less(d2, id, kd, kid);
+                    uint64_t qm = __ballot(cv);
+                    if (qm == 0) return false;
+                    const uint32_t nb = (uint32_t)__popcll(qm);
+                    if (nb > 6) {
+                        uint64_t cd = cv ? d2 : kMaxD2;
+                        uint32_t ci = cv ? id : kMaxId;
+                        wave_sort64(cd, ci);
+                        const uint64_t xd = shfl64(cd, 63u - lane);
+                        const uint32_t xi = __shfl(ci, 63u - lane);
+                        if (key_less(xd, xi, rd, ri)) {
+                            rd = xd;
+                            ri = xi;
+                        }
+                        wave_bitonic_clean64(rd, ri);
+                        held = min(held + nb, 64u);
+                    } else {
+                        while (qm) {
+                            const uint32_t j = (uint32_t)__builtin_ctzll(qm);
+                            qm &= qm - 1ull;
+                            const uint64_t nd = lane_val64(d2, j);
+                            const uint32_t ni = lane_val(id, j);
+                            if (held >= M && !key_less(nd, ni, kd, kid)) continue;
+                            const uint32_t pos = (uint32_t)__popcll(__ballot(key_less(rd, ri, nd, ni)));
+                            const uint32_t below = lane ? lane - 1u : 0u;
+                            const uint64_t sd = shfl64(rd, below);
+                            const uint32_t si = __shfl(ri, below);
+                            if (lane > pos) {
+                                rd = sd;
+                                ri = si;
+                            } else if (lane == pos) {
+                                rd = nd;
+                                ri = ni;
+                            }
+                            held = min(held + 1u, 64u);
+                            if (held >= M) {
+                                kd = lane_val64(rd, M - 1u);
+                                kid = lane_val(ri, M - 1u);
+                            }
+                        }
+                    }
+                    if (held >= M) {
+                        kd = lane_val64(rd, M - 1u);
+                        kid = lane_val(ri, M - 1u);
+                    }
+                    return false;
+                };
+                for (;;) {
+                    walk<METHOD, TLDS, true>(L, T, tab_lds, s, false, walked2, [&]() { return held >= M ? kd : B; },
+                                             [&](const RowRef& r) -> bool {
+                        return for_candidates(L, r.st0, r.cnt0, r.st1, r.cnt1, own, cand2, visit_r);
+                    });
+                    if (held >= M || B >= s.r2) break;
+                    B = min(s.r2, B + B + (B >> 2) + 1u);  // radius x1.5
+                    held = 0;
+                    rd = kMaxD2;
+                    ri = kMaxId;
+                    kd = kMaxD2;
+                    kid = kMaxId;
+                }
+                const uint32_t got = min(held, M);
+                if (lane < got) {
+                    A.out_ids[rb + written + lane] = ri;
+                    if (A.out_d2) A.out_d2[rb + written + lane] = (int64_t)rd;
+                }
+                if (got == 0) break;
+                has_lower = true;
+                ld = lane_val64(rd, got - 1u);
+                li = lane_val(ri, got - 1u);
+                written += got;
+                continue;
+            }
             uint32_t m = 0;
             uint64_t bdd = kMaxD2;
             uint32_t bii = kMaxId;
@@ -1570,21 +1680,23 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
                                     q.stash_d2 ? (uint32_t)(((char*)q.stash_d2 - q.stash_base) / 256) : 0u);
         clear_counters_kernel<<<1, 256, 0, st>>>(q.queues, 0u, SPHIDX_COUNTER_WORDS, q.stash_hdr, hv);
     } else {
-        // the write-side queue sets and the long / fallback lists; the walk
-        // list, the stash header and the stash counters stay as the count
-        // pass left them
-        clear_counters_kernel<<<1, 256, 0, st>>>(q.queues, set_words, lists + 2 * SPHIDX_QSTRIDE, nullptr,
+        // the write-side queue sets and the long-row list; the descriptors,
+        // the fallback and walk lists, the stash header and the stash
+        // counters stay as the count pass left them
+        clear_counters_kernel<<<1, 256, 0, st>>>(q.queues, set_words, lists + SPHIDX_QSTRIDE, nullptr,
                                                  make_uint4(0, 0, 0, 0));
     }
     e = hipGetLastError();
     if (e != hipSuccess || q.Q == 0) return e;
-    // per-query descriptors (and, for the sphere method, the fallback list)
-    if (variant == 0)
-        setup_kernel<kCube><<<(q.Q + 255) / 256, 256, 0, st>>>(L, T, q);
-    else
-        setup_kernel<kSphere><<<(q.Q + 255) / 256, 256, 0, st>>>(L, T, q);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (pass == 0) {
+        // per-query descriptors (and, for the sphere method, the fallback list)
+        if (variant == 0)
+            setup_kernel<kCube><<<(q.Q + 255) / 256, 256, 0, st>>>(L, T, q);
+        else
+            setup_kernel<kSphere><<<(q.Q + 255) / 256, 256, 0, st>>>(L, T, q);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     const uint32_t w = waves_per_block, b = blocks_per_cu;
     QArgs ql = q;  // list-driven launches: persistent, one query per grab
     ql.persistent = 1;
