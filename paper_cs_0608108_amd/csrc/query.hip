@@ -1,37 +1,37 @@
-// Neighbourhood query kernels for gfx950 (wave64): one wavefront per query.
+// Neighbourhood query kernels for gfx950 (wave64).
 //
 // Per query:
 //   setup   (one thread per query, setup_kernel) home cell = q >> F, sub-cell
-//           class = the top s bits of q's position inside its cell (Section
-//           III.A: the position inside the cell selects a specialised table),
-//           the method, and the class table's prefix end from the radius
-//           index (Section II.A: one lookup tells where to stop in the sorted
-//           offset array), stored as a 64-byte descriptor.
-//   walk    (one wavefront per query, all values wave-uniform) 64 x EPL
-//           consecutive table entries per step, EPL per lane, sorted by
-//           increasing key: centre to edge.  A lane translates its offset to
-//           an absolute cell (wrap on cyclic axes, region test on clipped
-//           ones, Section II.B), applies the exact run-time test
-//           min-dist^2 <= r^2 (Eq. 1, to every entry) and, when counting,
-//           includes whole the cells that lie wholly inside the sphere
-//           (Section III.A, last paragraph).  The next step's entries are
-//           prefetched while this step's cells are read.
-//   scan    the objects of the kept cells are spread over the lanes: a DPP
-//           prefix sum of per-lane counts, an LDS map of where each lane's
-//           range starts and a DPP max-scan give every slot its owner, so a
-//           wave tests 64 candidates per step whatever the cell loads.  One
+//           class = the top s bits of q's position inside its cell along y
+//           and z (Section III.A: the position inside the cell selects a
+//           specialised table), the method, and the class table's prefix end
+//           from the radius index (Section II.A: one lookup tells where to
+//           stop in the sorted table), stored as a 64-byte descriptor.
+//   walk    the class table lists x-rows of cells (oy, oz) sorted by their
+//           minimum distance, centre to edge; 64 rows per step, one per lane.
+//           A lane solves the exact test of Eq. 1 for its row's contiguous
+//           run of cells, wraps cyclic axes or clips to the region (Section
+//           II.B), and turns the run into one range of objects (two when it
+//           wraps), since objects are sorted by packed ZYX cell.
+//   scan    the objects of the rows are spread over the lanes: a DPP prefix
+//           sum of per-lane counts, an LDS map of where each lane's range
+//           starts and a DPP max-scan give every slot its owner, so a wave
+//           tests 64 candidates per step whatever the cell loads.  One
 //           16-byte load fetches a candidate's coordinates and id.
 //   output  count pass: hits per row (K-NN: min(K, hits within the cap),
-//           stopping once K are found).  Write pass: radius rows are
-//           compacted into LDS with ballot + mbcnt, sorted by (dist^2, id)
-//           and stored; K-NN rows, and radius rows longer than the LDS
-//           buffer, go to the top-M kernel, which keeps the M best in LDS,
-//           shrinks the bound to the M-th distance once M are held and stops
-//           at the first table entry whose key exceeds it (Section II.A,
-//           K nearest).
-// Queries whose radius exceeds the tables' cap or the cyclic limit, or whose
-// centre is outside the region, and every query of the cube method, scan the
-// bin-lattice bounding cube instead (Section I; Section III.C).
+//           stopping once K are found); with workspace to spare it also
+//           sorts each radius row by (dist^2, id) and keeps it (the stash),
+//           and the write pass only copies the kept rows into place.  Rows
+//           not kept are walked again by the write pass.  K-NN rows and
+//           long rows go to the top-M kernel, which keeps the M best (in
+//           registers for M <= 64), shrinks the bound to the M-th distance
+//           once M are held and stops at the first row whose key exceeds it
+//           (Section II.A, K nearest).
+// The count pass can also take radius queries in groups of several per
+// wavefront, so that short rows and small radii fill whole steps.  Queries
+// whose radius exceeds the tables' cap or the cyclic limit, or whose centre
+// is outside the region, and every query of the cube method, scan the
+// bin-lattice bounding cube instead (Section I; Section III.B).
 #include "sphidx_internal.h"
 
 namespace {
