@@ -85,9 +85,9 @@ sphidx_status sphidx_lattice_create(const sphidx_lattice_desc* desc, uint32_t ma
 void sphidx_lattice_destroy(sphidx_lattice* lat);
 
 /* Rebuild the cell lists from n objects (dev x, y, z: uint32[n]) as a
- * counting sort: cell-id histogram, exclusive scan, scatter into per-cell
- * SoA arrays (each object is in exactly one cell, Section I).  Object ids are
- * their input indices.  Objects with a clipped-axis coordinate >= 2^30 set
+ * counting sort: cell-id histogram, exclusive scan, scatter of one 16-byte
+ * record {x, y, z, id} per object in packed-cell order (each object is in
+ * exactly one cell, Section I).  Object ids are their input indices.  Objects with a clipped-axis coordinate >= 2^30 set
  * SPHIDX_FLAG_RANGE and are left out.  n <= max_points.  The lattice must not
  * be read by queries still in flight on other streams. */
 sphidx_status sphidx_build_lattice(sphidx_lattice* lat, const uint32_t* x_dev, const uint32_t* y_dev,

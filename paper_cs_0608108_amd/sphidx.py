@@ -201,7 +201,7 @@ class Lattice:
         return code, int(f.value)
 
     def host_arrays(self):
-        """Copy cell_start and the sorted SoA arrays back to the host (for tests).
+        """Copy cell_start and the sorted object records back to the host (for tests).
         The view's pointers lie inside this object's workspace tensor."""
         v = self.view()
         base = self.workspace.data_ptr()
