@@ -23,8 +23,13 @@ def sx():
     return sphidx
 
 
-@pytest.mark.parametrize("mask,log2,n,seed", [(7, (5, 5, 5), 32768, 11), (5, (5, 4, 6), 20000, 12)])
-def test_timestep_graph_replays_match_oracle(sx, orc, mask, log2, n, seed):
+@pytest.mark.parametrize("mask,log2,n,seed,launch", [
+    (7, (5, 5, 5), 32768, 11, {}),
+    (5, (5, 4, 6), 20000, 12, {}),
+    (7, (5, 5, 5), 32768, 13, {"sort_cap": 128, "table_in_lds": 1}),
+    (5, (5, 4, 6), 20000, 14, {"grouped": 1, "waves_per_block": 2}),
+])
+def test_timestep_graph_replays_match_oracle(sx, orc, mask, log2, n, seed, launch):
     import torch
 
     from paper_cs_0608108_amd import synth, timestep
@@ -32,8 +37,8 @@ def test_timestep_graph_replays_match_oracle(sx, orc, mask, log2, n, seed):
     spec = synth.LatticeSpec(log2, F, mask)
     pts = synth.uniform_points(spec, n, seed)
     r = 3 * (1 << F)
-    say(f"timestep mask={mask} log2={log2} n={n} seed={seed}")
-    sim = timestep.AgentSim(log2, F, mask, pts, r, seed)
+    say(f"timestep mask={mask} log2={log2} n={n} seed={seed} launch={launch}")
+    sim = timestep.AgentSim(log2, F, mask, pts, r, seed, launch=sx.LaunchConfig(**launch))
     L = orc.Lattice(log2, F, mask)
     cur = tuple(np.asarray(a, dtype=np.uint32) for a in pts)
 
