@@ -45,7 +45,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "all-agents neighbor queries/sec and HBM GB/s at 1 GPU; p99 latency vs plain launch"
 HBM_PEAK_GBS = 8000.0
-LEGS = ("c2", "knn", "timestep", "serving")
+LEGS = ("c2", "knn", "timestep", "serving", "sweep")
+DEFAULT_LEGS = ("c2", "knn", "timestep", "serving")
 
 
 def log(*a):
@@ -487,6 +488,83 @@ def leg_serving(args, out):
     torch.cuda.empty_cache()
 
 
+# ---------------------------------------------------------------------------
+# Section IV sweep: sphere tables against the bin-lattice cube scan
+
+def leg_sweep(args, out):
+    """All neighbours and the nearest neighbour for random centres, by world
+    (16^3, 32^3), boundary (wrapping, clipped), load and query distance (cell
+    units, up to 3/4 of the world), the shapes of the paper's Figs. 5-10.
+    Each point times the same queries with both methods (count + write, the
+    write touching every neighbour's id) and checks that their rows agree."""
+    import numpy as np
+    import torch
+
+    from paper_cs_0608108_amd import sphidx, synth
+
+    radii = (0.25, 0.5, 1.0, 1.5, 2.0, 3.0, 4.0, 5.0, 6.0, 7.0, 7.5, 8.0, 10.0, 12.0)
+    rows = []
+    mismatches = 0
+
+    def timed_query(lat, tab, q, ln, reps=3):
+        buf = sphidx.QueryBuffers(q.count, 0, want_dist2=False)
+        sphidx.count(lat, tab, q, buf, ln)
+        total = int(buf.row_ptr[-1].item())
+        buf.grow(max(total, 1))
+        buf.reserve_stash(max(total, 1))
+
+        def run():
+            sphidx.count(lat, tab, q, buf, ln)
+            sphidx.write(lat, tab, q, buf, ln)
+        run()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            run()
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) / reps, buf
+
+    for log2 in (4, 5):
+        for mask in (7, 0):
+            for load in (0.625, 1.0, 5.0, 10.0, 20.0):
+                w = synth.sweep_world(log2, mask, load)
+                L = 1 << log2
+                lat = sphidx.Lattice(w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask, max(w.n, 1))
+                dev = [sphidx.to_dev_u32(a) for a in w.pts]
+                lat.build(*dev)
+                tab = sphidx.Tables(lat, 2, int(0.75 * L * w.lat.edge))
+                for rc in radii:
+                    if rc > 0.75 * L:
+                        continue
+                    r = int(rc * w.lat.edge)
+                    # enough queries to fill the GPU, few enough to bound the output
+                    vol = min(4.19 * rc ** 3, float(L ** 3))
+                    Q = int(min(16384, max(512, 3e7 / max(load * vol, 1.0))))
+                    cen = [sphidx.to_dev_u32(a) for a in synth.sweep_centres(w.lat, 6, Q)]
+                    point = {"world": f"{L}^3", "wrap": mask == 7, "load": load, "r": rc, "queries": Q}
+                    for mode, k, key in ((sphidx.MODE_RADIUS, 0, "all"), (sphidx.MODE_KNN, 1, "nearest")):
+                        q = sphidx.make_queries(Q, tuple(cen), r, k, mode, 0)
+                        t_s, b_s = timed_query(lat, tab, q, sphidx.LaunchConfig())
+                        t_c, b_c = timed_query(lat, tab, q, sphidx.LaunchConfig(method=sphidx.METHOD_CUBE))
+                        n_s = int(b_s.row_ptr[-1].item())
+                        same = bool(torch.equal(b_s.row_ptr, b_c.row_ptr) and torch.equal(b_s.ids[:n_s], b_c.ids[:n_s]))
+                        mismatches += 0 if same else 1
+                        point[key] = {"sphere_ms": round(t_s, 4), "cube_ms": round(t_c, 4),
+                                      "ratio": round(t_c / t_s, 3), "pairs": n_s, "same": same}
+                        del b_s, b_c
+                    rows.append(point)
+                    log(f"sweep {point['world']} wrap={point['wrap']} load={load} r={rc}: all x{point['all']['ratio']}"
+                        f" nearest x{point['nearest']['ratio']}")
+                del lat, tab, dev
+                torch.cuda.empty_cache()
+    out["section_iv_sweep"] = {
+        "ratio": "cube ms / sphere ms (above 1: the sphere tables are faster)",
+        "step": "count + write on random centres; rows compared between the methods",
+        "all_points_identical": mismatches == 0, "points": rows}
+
+
 def copy_calibration(nbytes):
     import torch
     src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
@@ -508,7 +586,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--legs", default=",".join(LEGS), help="comma list of " + ",".join(LEGS))
+    ap.add_argument("--legs", default=",".join(DEFAULT_LEGS), help="comma list of " + ",".join(LEGS))
     ap.add_argument("--no-tune", action="store_true", help="use the cached/default launch configuration")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs (profiling runs)")
     ap.add_argument("--no-baselines", action="store_true", help="skip the plain-launch and cube-scan legs")
@@ -536,7 +614,8 @@ def main():
            "vs_baseline": None, "dtype": "int64", "data": "synthetic"}
     for x in legs:
         log(f"== leg {x}")
-        {"c2": leg_c2, "knn": leg_knn, "timestep": leg_timestep, "serving": leg_serving}[x](args, out)
+        {"c2": leg_c2, "knn": leg_knn, "timestep": leg_timestep, "serving": leg_serving,
+         "sweep": leg_sweep}[x](args, out)
     print(json.dumps(out))
 
 

@@ -179,6 +179,23 @@ def agents_timestep(n=1 << 23, log2=8, seed=4):
                     r_fx=np.full(n, 3 * lat.edge, dtype=np.uint32), extra={"seed": seed})
 
 
+def sweep_world(log2, cyclic_mask, load, seed=6):
+    """Section IV worlds: L^3 cells (L = 16 or 32), objects uniform at `load`
+    objects per cell on average."""
+    lat = LatticeSpec((log2,) * 3, 16, cyclic_mask)
+    n = int(round(load * lat.ncells))
+    pts = uniform_points(lat, n, seed)
+    kind = "wrapping" if cyclic_mask == 7 else "clipped"
+    return Workload(f"sweep_{1 << log2}^3_{kind}_load{load}", lat, pts, extra={"seed": seed})
+
+
+def sweep_centres(lat: LatticeSpec, seed: int, count: int):
+    """Random query centres uniform over the region (tags 7..9)."""
+    i = np.arange(count, dtype=np.uint64)
+    return tuple(uniform_bits(seed, 7 + a, i, lat.frac_bits + lat.log2_cells[a]).astype(np.uint32)
+                 for a in range(3))
+
+
 def serving_lattice(n=1 << 24, log2=9, seed=5):
     """Device-resident lattice for the serving loop: uniform, cyclic L^3."""
     lat = LatticeSpec((log2,) * 3, 16, 7)
