@@ -926,16 +926,17 @@ __global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs 
 // Queries it does not take (K-NN, keys that would not fit 64 bits) go to
 // the extra list for the one-query-per-wave kernel.
 
-constexpr uint32_t kGroup = 8, kGroupBits = 3, kHitCap = 512;
-// a group ends before its rows would exceed two row steps: at about one or
-// two hits per row (objects per cell below about one) its hits fit kHitCap
-constexpr uint32_t kGroupRows = 128;
+constexpr uint32_t kGroup = 8, kGroupBits = 3, kMaxHitCap = 512;
+// The group's hit buffer holds 2 x sort_cap keys, and a group ends before
+// its rows would exceed sort_cap / 2: at about one or two hits per row
+// (objects per cell below about one) its hits fit the buffer.  A smaller
+// sort_cap trades packing for LDS, hence occupancy.
 
 // Per-wave LDS of the grouped kernel: slot data (kGroup x 64 B), 32 words of
 // per-slot counters, the 64-word owner map, then (stash) the hit keys in
 // arrival order, the same by bucket, and the bucket counts.
-__host__ __device__ constexpr size_t group_lds_per_wave(bool stash) {
-    return 512 + 128 + 256 + (stash ? (size_t)kHitCap * 20 : 0);
+__host__ __device__ constexpr size_t group_lds_per_wave(bool stash, uint32_t cap) {
+    return 512 + 128 + 256 + (stash ? (size_t)cap * 2 * 20 : 0);
 }
 
 // dist^2 field of a group hit key (slot | dist^2 | id)
@@ -948,7 +949,8 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
     extern __shared__ __align__(16) char smem[];
     const uint32_t* tab_lds = stage_table<TLDS>(T, smem);
     const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
-    char* wb = smem + table_lds_bytes<TLDS>(T) + (size_t)wave * group_lds_per_wave(STASH);
+    const uint32_t hitcap = 2 * A.sort_cap, group_rows = A.sort_cap / 2;  // hitcap <= kMaxHitCap
+    char* wb = smem + table_lds_bytes<TLDS>(T) + (size_t)wave * group_lds_per_wave(STASH, A.sort_cap);
     uint4* qp = (uint4*)wb;                    // per slot: centre + table start, r^2 + self + rows,
                                                // cube extent, flags + row
     uint32_t* cnt = (uint32_t*)(wb + 512);     // [0, 8) hits, [8, 16) row start, [16, 24) hits,
@@ -956,9 +958,9 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
     uint32_t* qn = cnt + 16;
     float* qsc = (float*)(cnt + 24);
     uint32_t* own = cnt + 32;                  // 64: owner map
-    uint64_t* hb = (uint64_t*)(own + 64);      // kHitCap keys in arrival order
-    uint64_t* hs = hb + kHitCap;               // kHitCap keys by bucket
-    uint32_t* hh = (uint32_t*)(hs + kHitCap);  // kHitCap bucket counts, then starts
+    uint64_t* hb = (uint64_t*)(own + 64);      // hitcap keys in arrival order
+    uint64_t* hs = hb + hitcap;                // hitcap keys by bucket
+    uint32_t* hh = (uint32_t*)(hs + hitcap);   // hitcap bucket counts, then starts
     const AxisWrap aw = axis_wrap(L);
     const uint32_t idbits = L.n > 1 ? 32u - (uint32_t)__builtin_clz(L.n - 1u) : 0u;
     const uint32_t d2bits = 64u - kGroupBits - idbits;
@@ -970,7 +972,7 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
         for (uint32_t g0 = b, ng = 0; g0 < e; g0 += ng) {
             const uint32_t cand = min(kGroup, e - g0);
             // ---- slots: lane l < cand looks at query g0 + l; the group keeps
-            // the leading slots whose rows fit kGroupRows (at least one)
+            // the leading slots whose rows fit group_rows (at least one)
             const uint32_t qi = g0 + lane;
             uint32_t rows = 0, row = 0;
             bool mine = false, extra = false, invalid = false;
@@ -998,7 +1000,7 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
             }
             {
                 const uint32_t pre_incl = scan_add(rows);
-                const uint64_t fits = __ballot(lane < cand && pre_incl <= kGroupRows);
+                const uint64_t fits = __ballot(lane < cand && pre_incl <= group_rows);
                 ng = max(1u, (uint32_t)__popcll(fits));
             }
             if (lane >= ng) {
@@ -1131,7 +1133,7 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
                     }
                     if (STASH) {
                         const uint32_t hp = hcount + lanes_below(H);
-                        if (hit && hp < kHitCap)
+                        if (hit && hp < hitcap)
                             hb[hp] = ((uint64_t)sl << (64u - kGroupBits)) | (d2 << idbits) | (uint64_t)P.w;
                         hcount += (uint32_t)__popcll(H);
                     }
@@ -1146,7 +1148,7 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
             }
             if (STASH) {
                 const uint32_t total = hcount;
-                bool ok = total <= kHitCap;
+                bool ok = total <= hitcap;
                 if (ok && total > 0 && cur + total > lim) {
                     ok = false;
                     if (!dry) {
@@ -1181,9 +1183,9 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
                         const uint32_t bi = min((uint32_t)((float)key_d2(k, idbits, d2bits) * qsc[sl]), n - 1u);
                         return qst[sl] + bi;
                     };
-                    uint32_t slot[kHitCap / 64];
+                    uint32_t slot[kMaxHitCap / 64];
 #pragma unroll
-                    for (uint32_t k = 0; k < kHitCap / 64; ++k) {
+                    for (uint32_t k = 0; k < kMaxHitCap / 64; ++k) {
                         const uint32_t t = lane + 64u * k;
                         if (t < total) slot[k] = atomicAdd(&hh[bucket(hb[t])], 1u);
                     }
@@ -1203,7 +1205,7 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
                         }
                     wave_sync();
 #pragma unroll
-                    for (uint32_t k = 0; k < kHitCap / 64; ++k) {
+                    for (uint32_t k = 0; k < kMaxHitCap / 64; ++k) {
                         const uint32_t t = lane + 64u * k;
                         if (t < total) {
                             const uint64_t key = hb[t];
@@ -1660,7 +1662,7 @@ size_t query_lds_bytes(int pass, uint32_t cap, uint32_t waves, size_t table_byte
     size_t per = 256;
     if (pass == 1 || pass == 3) per = (size_t)cap * 28 + 256;
     if (pass == 2) per = (size_t)cap * 24 + 64 * 12 + 256;
-    if (pass == 4 || pass == 5) per = group_lds_per_wave(pass == 5);
+    if (pass == 4 || pass == 5) per = group_lds_per_wave(pass == 5, cap);
     return table_bytes + per * waves;
 }
 
