@@ -25,7 +25,7 @@ ARCH = "gfx950"
 CFLAGS = [
     "-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+    "-Wall", "-Wextra",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 

@@ -339,13 +339,8 @@ struct RowRef {
     uint32_t kept;
 };
 
-// Per-axis distances from a position f inside the home cell to the nearest
-// and to the farthest position of the cell at offset o along that axis.
-__device__ __forceinline__ uint32_t axis_gap(int o, uint32_t f, uint32_t F) {
-    if (o > 0) return ((uint32_t)o << F) - f;
-    if (o < 0) return f + (((uint32_t)(-o) - 1u) << F) + 1u;
-    return 0u;
-}
+// Per-axis distance from a position f inside the home cell to the farthest
+// position of the cell at offset o along that axis.
 __device__ __forceinline__ uint32_t axis_far(int o, uint32_t f, uint32_t F) {
     const uint32_t e = 1u << F;
     if (o > 0) return (((uint32_t)o + 1u) << F) - 1u - f;
