@@ -106,6 +106,21 @@ typedef struct {
 } sphidx_lattice_view;
 sphidx_status sphidx_lattice_get_view(const sphidx_lattice* lat, sphidx_lattice_view* out);
 
+/* The non-empty cell list (Section III.B): the region cells that hold at
+ * least one object, in increasing packed-cell order.  A caller-owned buffer
+ * of at least sphidx_cell_list_bytes(lat) bytes (256-byte aligned) holds
+ *   bytes [0, 4):   uint32 count
+ *   bytes [16, ..): count + 1 entries {uint32 cell, uint32 first}: the packed
+ *                   cell index and the sorted position of its first object;
+ *                   the last entry is {0xFFFFFFFF, cell_start[ncells]}, so
+ *                   entry j's objects are [first_j, first_{j+1}).
+ * Attaching enqueues the list of the current contents on `stream`; from then
+ * on every sphidx_build_lattice rebuilds it after the cell lists, in stream
+ * order.  list_dev = NULL detaches (no list kept; METHOD_AUTO stops choosing
+ * it).  The buffer must outlive the attachment. */
+size_t sphidx_cell_list_bytes(const sphidx_lattice* lat);
+sphidx_status sphidx_lattice_attach_cell_list(sphidx_lattice* lat, void* list_dev, size_t bytes, void* stream);
+
 /* Synchronise `stream`, return the device status word in *flags_out (may be
  * NULL) and clear it.  Returns RANGE or CAPACITY when those bits were set. */
 sphidx_status sphidx_lattice_status(sphidx_lattice* lat, void* stream, uint32_t* flags_out);
@@ -193,6 +208,13 @@ size_t sphidx_query_stash_bytes(uint64_t pairs, int want_dist2);
 
 #define SPHIDX_METHOD_SPHERE 0u /* sphere-table walk (falls back to the cube where the tables do not apply) */
 #define SPHIDX_METHOD_CUBE 1u   /* bin-lattice bounding-cube scan: the paper's baseline */
+#define SPHIDX_METHOD_AUTO 2u   /* per query, the walk with the fewest cells (Section III.B, III.C):
+                                   the sphere table (cells of its prefix for the query's sub-cell class
+                                   and radius), the bounding cube clipped to the region, or the lattice's
+                                   non-empty cell list when one is attached; see select_weight and the
+                                   reversal distances below.  Needs tables. */
+#define SPHIDX_METHOD_LIST 3u   /* every query walks the non-empty cell list (needs an attached list;
+                                   tables unused) */
 
 #define SPHIDX_SCHED_PLAIN 0u      /* one launch, each wave owns a fixed slice of queries */
 #define SPHIDX_SCHED_PERSISTENT 1u /* resident waves pull query tiles from per-XCD work queues */
@@ -200,7 +222,7 @@ size_t sphidx_query_stash_bytes(uint64_t pairs, int want_dist2);
 typedef struct {
     uint32_t method;          /* SPHIDX_METHOD_* */
     uint32_t schedule;        /* SPHIDX_SCHED_* */
-    uint32_t waves_per_block; /* 1, 2, 4, 8 or 16; 0 = default */
+    uint32_t waves_per_block; /* 1, 2 or 4; 0 = default (4) */
     uint32_t tile;            /* queries per wave slice / per queue grab; 0 = default */
     uint32_t blocks_per_cu;   /* persistent residency; 0 = default */
     uint32_t sort_cap;        /* per-wave LDS row buffer (64, 128 or 256); longer rows take the
@@ -218,6 +240,21 @@ typedef struct {
     uint32_t no_stash;   /* 1: never keep rows in the workspace stash (see sphidx_csr) */
     uint32_t grouped;    /* 1: the count pass takes radius queries in groups of several per
                             wavefront (persistent schedule); 0: one query per wavefront */
+    /* METHOD_AUTO (Appendix: weighting factor and reversal distances).  A radius query takes
+     * the sphere when select_weight/256 * (sphere cells) <= (cube cells), else the cube; then
+     * the non-empty list instead if it holds fewer cells than the one chosen (plain counts).
+     * Sphere cells: the entries of the query's sub-cell class with key <= (j * 2^b)^2,
+     * j = ceil(r / 2^b), b = max(F - 6, 0) -- the one lookup of the radius index.  Cube
+     * cells: the bounding cube's cells inside the region (the whole axis once it spans it).
+     * K-NN queries take the sphere or, below knn_reversal_fx, the cube (their final radius is
+     * not known in advance, Section IV.B).  Queries the tables cannot serve choose between the
+     * cube and the list. */
+    uint32_t select_weight;   /* Q8 fixed point; 0 = 256 (the plain volume comparison) */
+    uint32_t reversal_fx;     /* radius queries with r < reversal_fx never take the sphere; 0 = off */
+    uint32_t knn_reversal_fx; /* K-NN queries with cap < knn_reversal_fx take the cube; 0 = off */
+    uint32_t* method_dev;     /* optional uint32[Q], written by the count pass: the walk each query
+                                 used (SPHIDX_METHOD_SPHERE, _CUBE or _LIST), or 0xFFFFFFFF for a
+                                 query with an empty row by definition (invalid centre, K = 0) */
 } sphidx_launch;
 
 /* Bytes of device scratch a query call on Q queries needs. */

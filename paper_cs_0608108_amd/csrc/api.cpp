@@ -49,8 +49,10 @@ Layout lattice_layout(const sphidx_lattice_desc* d, uint32_t max_points) {
     };
     L.cell_start = take((nc + 4) * 4);
     L.pts = take((size_t)max_points * 16);
-    L.rank = take((size_t)max_points * 4);
-    L.scan_tmp = take(scan_u32_tmp_words(nc + 2) * 4);
+    // per-object build scratch; also the flags of the non-empty cell list and
+    // their scan (one word more for the total)
+    L.rank = take(((size_t)max_points + 1) * 4);
+    L.scan_tmp = take(scan_u32_tmp_words(std::max(nc + 2, (size_t)max_points)) * 4);
     L.status = take(64 * 4);
     L.total = off;
     return L;
@@ -66,6 +68,8 @@ LatArgs lat_args(const sphidx_lattice* lat) {
     L.cs = lat->cell_start;
     L.pts = lat->pts;
     L.status = lat->status;
+    L.cells = lat->cell_list ? (const uint2*)(lat->cell_list + 16) : nullptr;
+    L.ncl = lat->cell_list ? (const uint32_t*)lat->cell_list : nullptr;
     return L;
 }
 
@@ -77,6 +81,7 @@ TabArgs tab_args(const sphidx_tables* t) {
     T.rkey = t->d_rkey;
     T.cstart = t->d_rclass_start;
     T.rindex = t->d_rrindex;
+    T.vcount = t->d_vcount;
     T.s = t->s;
     T.rshift = t->rshift;
     T.nr = t->nr;
@@ -88,7 +93,9 @@ TabArgs tab_args(const sphidx_tables* t) {
 
 struct Launch {
     uint32_t method, persistent, waves, tile, bpc, cap, tab_lds, interior, no_stash, grouped;
+    uint32_t weight, rev, knn_rev;
     uint32_t* stats;
+    uint32_t* method_out;
     hipEvent_t ev_begin, ev_end;
 };
 
@@ -107,15 +114,21 @@ sphidx_status resolve_launch(const sphidx_launch* in, const sphidx_tables* tab, 
     o.grouped = in ? in->grouped : 0u;
     if (o.grouped > 1) return SPHIDX_ERR_INVALID_ARG;
     o.stats = in ? in->stats_dev : nullptr;
+    o.method_out = in ? in->method_dev : nullptr;
+    o.weight = (in && in->select_weight) ? in->select_weight : 256u;
+    o.rev = in ? in->reversal_fx : 0u;
+    o.knn_rev = in ? in->knn_reversal_fx : 0u;
+    if (o.weight > (1u << 16)) return SPHIDX_ERR_INVALID_ARG;
     o.ev_begin = in ? (hipEvent_t)in->event_begin : nullptr;
     o.ev_end = in ? (hipEvent_t)in->event_end : nullptr;
     if (in && in->schedule > SPHIDX_SCHED_PERSISTENT) return SPHIDX_ERR_INVALID_ARG;
-    if (o.method > SPHIDX_METHOD_CUBE) return SPHIDX_ERR_INVALID_ARG;
+    if (o.method > SPHIDX_METHOD_LIST) return SPHIDX_ERR_INVALID_ARG;
     if (!(o.waves == 1 || o.waves == 2 || o.waves == 4)) return SPHIDX_ERR_INVALID_ARG;
     if (o.cap < 64 || o.cap > 256 || (o.cap & (o.cap - 1))) return SPHIDX_ERR_INVALID_ARG;
     if (o.tile > 4096 || o.bpc > 64) return SPHIDX_ERR_INVALID_ARG;
-    if (o.method == SPHIDX_METHOD_SPHERE && !tab) return SPHIDX_ERR_INVALID_ARG;
-    if (o.method == SPHIDX_METHOD_CUBE) o.tab_lds = 0;
+    const bool tables = o.method == SPHIDX_METHOD_SPHERE || o.method == SPHIDX_METHOD_AUTO;
+    if (tables && !tab) return SPHIDX_ERR_INVALID_ARG;
+    if (!tables) o.tab_lds = 0;
     size_t tab_bytes = (o.tab_lds && tab) ? (tab->h_rows.size() * 4 + 15) / 16 * 16 : 0;
     for (int pass = 1; pass <= 5; ++pass) {
         if (query_lds_bytes(pass, o.cap, o.waves, 0) > kMaxBlockLds) return SPHIDX_ERR_INVALID_ARG;
@@ -205,6 +218,11 @@ QArgs q_args(const sphidx_queries* q, sphidx_csr* csr, const Launch& ln) {
     A.persistent = ln.persistent;
     A.tile = ln.tile;
     A.sort_cap = ln.cap;
+    A.select = ln.method == SPHIDX_METHOD_AUTO ? 1u : ln.method == SPHIDX_METHOD_LIST ? 2u : 0u;
+    A.weight = ln.weight;
+    A.rev = ln.rev;
+    A.knn_rev = ln.knn_rev;
+    A.method_out = ln.method_out;
     return A;
 }
 
@@ -256,12 +274,14 @@ sphidx_status run_pass(int pass, const sphidx_lattice* lat, const sphidx_tables*
     if (s != SPHIDX_OK) return s;
     if (pass == 1 && csr->capacity > 0 && !csr->ids_dev) return SPHIDX_ERR_INVALID_ARG;
     if (tab && tab->F != lat->desc.frac_bits) return SPHIDX_ERR_INVALID_ARG;
-    if (tab && ln.method == SPHIDX_METHOD_SPHERE && !tab->d_rows) {
+    const bool tables = ln.method == SPHIDX_METHOD_SPHERE || ln.method == SPHIDX_METHOD_AUTO;
+    if (ln.method == SPHIDX_METHOD_LIST && !lat->cell_list) return SPHIDX_ERR_INVALID_ARG;
+    if (tab && tables && !tab->d_rows) {
         s = tables_upload(const_cast<sphidx_tables*>(tab));
         if (s != SPHIDX_OK) return s;
     }
     LatArgs L = lat_args(lat);
-    TabArgs T = tab_args(ln.method == SPHIDX_METHOD_SPHERE ? tab : nullptr);
+    TabArgs T = tab_args(tables ? tab : nullptr);
     T.lds = ln.tab_lds;
     QArgs A = q_args(q, csr, ln);
     if (pass == 0) plan_stash(A, csr, ln, q->mode, ln.interior == 2);
@@ -334,6 +354,26 @@ sphidx_status sphidx_build_lattice(sphidx_lattice* lat, const uint32_t* x_dev, c
     if (n > 0 && (!x_dev || !y_dev || !z_dev)) return SPHIDX_ERR_INVALID_ARG;
     lat->n = n;
     return dev_err(launch_build(lat, x_dev, y_dev, z_dev, n, (hipStream_t)stream));
+}
+
+size_t sphidx_cell_list_bytes(const sphidx_lattice* lat) {
+    if (!lat) return 0;
+    const size_t entries = (size_t)std::min(lat->max_points, lat->ncells) + 1;
+    return 16 + entries * 8;
+}
+
+sphidx_status sphidx_lattice_attach_cell_list(sphidx_lattice* lat, void* list_dev, size_t bytes, void* stream) {
+    if (!lat) return SPHIDX_ERR_INVALID_ARG;
+    if (!list_dev) {
+        lat->cell_list = nullptr;
+        return SPHIDX_OK;
+    }
+    if ((uintptr_t)list_dev % kAlign) return SPHIDX_ERR_INVALID_ARG;
+    if (bytes < sphidx_cell_list_bytes(lat)) return SPHIDX_ERR_CAPACITY;
+    lat->cell_list = (char*)list_dev;
+    const sphidx_status s = dev_err(launch_cell_list(lat, (hipStream_t)stream));
+    if (s != SPHIDX_OK) lat->cell_list = nullptr;
+    return s;
 }
 
 sphidx_status sphidx_lattice_get_view(const sphidx_lattice* lat, sphidx_lattice_view* out) {

@@ -5,6 +5,9 @@
 //   scan    exclusive prefix over ncells + 2 counts -> cell_start (+ total)
 //   scatter per object: position = cell_start[cell] + slot; one 16-byte
 //           record {x, y, z, id} per object, so a candidate is one load
+//   list    (when a list is attached) the non-empty cells in cell order,
+//           Section III.B: flag the first object of each region cell, scan
+//           the flags, write {cell, first position} at the flag's rank
 // plus the reduce-then-scan used for cell_start and for query row pointers.
 #include "sphidx_internal.h"
 
@@ -81,6 +84,33 @@ __global__ __launch_bounds__(256) void scatter_kernel(BuildArgs a) {
     uint32_t cell = object_cell(a, vx, vy, vz, bad);
     uint32_t pos = a.count[cell] + a.rank[i];
     a.pts[pos] = make_uint4(vx, vy, vz, i);
+}
+
+// Packed region cell of a sorted record (normalised, inside the region).
+__device__ __forceinline__ uint32_t record_cell(const BuildArgs& a, const uint4& P) {
+    return ((P.z >> a.F) << (a.lg[0] + a.lg[1])) | ((P.y >> a.F) << a.lg[0]) | (P.x >> a.F);
+}
+
+// flag[i] = 1 when sorted position i holds the first object of a region cell.
+__global__ __launch_bounds__(256) void cell_flag_kernel(BuildArgs a, uint32_t* __restrict__ flag) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    uint32_t f = 0;
+    if (i < a.count[a.ncells]) f = a.count[record_cell(a, a.pts[i])] == i ? 1u : 0u;
+    flag[i] = f;
+}
+
+// After the exclusive scan of the flags (pos[n] = their total): entry
+// pos[i] = {cell, i} for each flagged i, then the count and the closing entry.
+__global__ __launch_bounds__(256) void cell_list_kernel(BuildArgs a, const uint32_t* __restrict__ pos,
+                                                        uint32_t* __restrict__ hdr, uint2* __restrict__ list) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < a.n && pos[i + 1] != pos[i]) list[pos[i]] = make_uint2(record_cell(a, a.pts[i]), i);
+    if (i == 0) {
+        const uint32_t cnt = pos[a.n];
+        hdr[0] = cnt;
+        list[cnt] = make_uint2(0xFFFFFFFFu, a.count[a.ncells]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -194,8 +224,9 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t st
     return hipGetLastError();
 }
 
-hipError_t launch_build(const sphidx_lattice* lat, const uint32_t* x, const uint32_t* y, const uint32_t* z,
-                        uint32_t n, hipStream_t st) {
+namespace {
+
+BuildArgs build_args(const sphidx_lattice* lat, const uint32_t* x, const uint32_t* y, const uint32_t* z, uint32_t n) {
     BuildArgs a;
     for (int k = 0; k < 3; ++k) a.lg[k] = lat->desc.log2_cells[k];
     a.F = lat->desc.frac_bits;
@@ -209,6 +240,28 @@ hipError_t launch_build(const sphidx_lattice* lat, const uint32_t* x, const uint
     a.rank = lat->rank;
     a.pts = lat->pts;
     a.status = lat->status;
+    return a;
+}
+
+}  // namespace
+
+// The attached non-empty cell list of the lattice's current contents (the
+// rank array, build scratch, holds the flags and their scan).
+hipError_t launch_cell_list(const sphidx_lattice* lat, hipStream_t st) {
+    if (!lat->cell_list) return hipSuccess;
+    const BuildArgs a = build_args(lat, nullptr, nullptr, nullptr, lat->n);
+    const uint32_t blocks = (a.n + 255) / 256;
+    if (a.n > 0) cell_flag_kernel<<<blocks, 256, 0, st>>>(a, lat->rank);
+    hipError_t e = scan_exclusive<uint32_t>(lat->rank, a.n, lat->scan_tmp, st);
+    if (e != hipSuccess) return e;
+    cell_list_kernel<<<blocks ? blocks : 1u, 256, 0, st>>>(a, lat->rank, (uint32_t*)lat->cell_list,
+                                                          (uint2*)(lat->cell_list + 16));
+    return hipGetLastError();
+}
+
+hipError_t launch_build(const sphidx_lattice* lat, const uint32_t* x, const uint32_t* y, const uint32_t* z,
+                        uint32_t n, hipStream_t st) {
+    const BuildArgs a = build_args(lat, x, y, z, n);
     size_t ncount = (size_t)lat->ncells + 2;
     hipError_t e = launch_fill_u32(lat->cell_start, 0u, ncount + 1, st);
     if (e != hipSuccess) return e;
@@ -217,7 +270,8 @@ hipError_t launch_build(const sphidx_lattice* lat, const uint32_t* x, const uint
     e = scan_exclusive<uint32_t>(lat->cell_start, ncount, lat->scan_tmp, st);
     if (e != hipSuccess) return e;
     if (n > 0) scatter_kernel<<<blocks, 256, 0, st>>>(a);
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_cell_list(lat, st);
 }
 
 size_t scan_i64_tmp_bytes(uint32_t n) {

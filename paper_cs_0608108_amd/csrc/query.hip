@@ -161,7 +161,9 @@ __device__ __forceinline__ uint64_t sq(uint32_t g) { return (uint64_t)g * (uint6
 // ---------------------------------------------------------------------------
 // Query descriptors
 
-enum : uint32_t { F_VALID = 1u, F_KNN = 2u, F_SPHERE = 4u, F_OUTSIDE = 8u };
+// F_LIST: the query walks the non-empty cell list (neither F_SPHERE nor
+// F_LIST: the bounding cube).
+enum : uint32_t { F_VALID = 1u, F_KNN = 2u, F_SPHERE = 4u, F_OUTSIDE = 8u, F_LIST = 16u };
 
 struct Query {
     uint32_t q[3];  // normalised centre
@@ -172,7 +174,7 @@ struct Query {
     uint32_t tb;    // sphere: first entry of the class table
     uint32_t tend;  // sphere: prefix length
     uint32_t ncube; // cube: cells of the bounding cube
-    uint32_t nn[3]; // cube: cells per axis
+    uint32_t nn[3]; // cube: cells per axis (cell list: 0, its length, 1)
     int32_t lo[3];  // cube: first cell per axis
     uint32_t self;  // sorted position excluded (EXCLUDE_SELF, all agents) or ~0
     uint32_t c[3];  // home cell
@@ -245,19 +247,61 @@ __global__ __launch_bounds__(256) void setup_kernel(LatArgs L, TabArgs T, QArgs 
             nn[a] = hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
             ncube *= nn[a];
         }
-        const bool sphere = METHOD == kSphere && inside && cyc_ok && r <= T.rmax;
-        fallback = valid && METHOD == kSphere && !sphere;
-        if (fallback) A.fbq[atomicAdd(A.fb_count, 1u)] = i;
+        // the tables serve centres inside the region, radii up to their cap
+        // and, on cyclic axes, up to the limit where no offset repeats a cell
+        const bool usable = METHOD == kSphere && inside && cyc_ok && r <= T.rmax;
+        bool sphere = usable, list = false;
+        const uint32_t j = (uint32_t)(((uint64_t)r + (1u << T.rshift) - 1u) >> T.rshift);
+        if (A.select == 2u) {
+            sphere = false;
+            list = true;
+        } else if (A.select == 1u && valid) {
+            // Section III.B/C: the walk with the fewest cells among the sphere
+            // table's prefix, the bounding cube clipped to the region and the
+            // non-empty cell list; the weight scales the sphere's count against
+            // the cube's, and below the reversal distances the sphere is left
+            // out (Appendix).  K-NN queries choose only between the sphere and
+            // the cube (Section IV.B).
+            if (knn) {
+                sphere = sphere && r >= A.knn_rev;
+            } else {
+                sphere = sphere && r >= A.rev;
+                uint64_t chosen = ncube;
+                if (sphere) {
+                    const uint32_t cls3 = ((q[0] & (e - 1u)) >> (L.F - T.s)) |
+                                          (((q[1] & (e - 1u)) >> (L.F - T.s)) << T.s) |
+                                          (((q[2] & (e - 1u)) >> (L.F - T.s)) << (2u * T.s));
+                    const uint64_t vs = T.vcount[(size_t)cls3 * T.nr + j];
+                    sphere = vs * A.weight <= (uint64_t)ncube * 256u;
+                    if (sphere) chosen = vs;
+                }
+                if (L.ncl && (uint64_t)*L.ncl < chosen) {
+                    sphere = false;
+                    list = true;
+                }
+            }
+        }
+        fallback = valid && METHOD == kSphere && !usable;
+        if (valid && METHOD == kSphere && !sphere) A.fbq[atomicAdd(A.fb_count, 1u)] = i;
         uint32_t tb = 0, tend = 0;
         if (sphere && valid) {
             // row tables are specialised on the (y, z) sub-cell position
             const uint32_t cls = ((q[1] & (e - 1u)) >> (L.F - T.s)) | (((q[2] & (e - 1u)) >> (L.F - T.s)) << T.s);
-            const uint32_t j = (uint32_t)(((uint64_t)r + (1u << T.rshift) - 1u) >> T.rshift);
             tb = T.cstart[cls];
             tend = T.rindex[(size_t)cls * T.nr + j];
         }
+        if (list) {
+            // the walk takes nn[1] * nn[2] entries: the whole list
+            nn[0] = 0u;
+            nn[1] = *L.ncl;
+            nn[2] = 1u;
+            lo3[0] = lo3[1] = lo3[2] = 0;
+        }
+        if (A.method_out)
+            A.method_out[row] = !valid ? 0xFFFFFFFFu
+                                       : sphere ? SPHIDX_METHOD_SPHERE : list ? SPHIDX_METHOD_LIST : SPHIDX_METHOD_CUBE;
         const uint32_t flags = (valid ? F_VALID : 0u) | (knn ? F_KNN : 0u) | (sphere ? F_SPHERE : 0u) |
-                               (outside ? F_OUTSIDE : 0u);
+                               (outside ? F_OUTSIDE : 0u) | (list ? F_LIST : 0u);
         uint4* d = A.desc + 4 * (size_t)i;
         d[0] = make_uint4(q[0], q[1], q[2], row);
         d[1] = make_uint4(r, k, flags, tb);
@@ -483,6 +527,43 @@ __device__ __forceinline__ RowRef cube_row(const LatArgs& L, const Query& s, uin
     return row_ranges(L, base, s.lo[0], s.lo[0] + (int)s.nn[0] - 1, 1, 0, has);
 }
 
+// Entry `ent` of the non-empty cell list (Section III.B): the cell's objects
+// are one range, kept when the cell's nearest position is within the radius
+// -- the rejection of cells that are too far, instead of the sphere's
+// rejection of empty cells.  On a cyclic axis the cell's offset is taken to
+// the nearest image, o in [-L/2, L/2); at o = -L/2 the image at +L/2 is as
+// many cells away, and the nearer face of the two counts.
+__device__ __forceinline__ RowRef list_row(const LatArgs& L, const Query& s, uint32_t ent, bool has, uint64_t bound2) {
+    // lanes without an entry read entry 0 (the closing entry of an empty
+    // list), always present
+    const uint2 c = L.cells[has ? ent : 0u];
+    const uint32_t end = L.cells[has ? ent + 1u : 0u].y;
+    const uint32_t cc[3] = {c.x & ((1u << L.lg[0]) - 1u), (c.x >> L.lg[0]) & ((1u << L.lg[1]) - 1u),
+                            c.x >> (L.lg[0] + L.lg[1])};
+    uint64_t g2 = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int o = (int)cc[a] - (int)s.c[a];
+        uint32_t up = s.up[a], dn = s.dn[a];
+        if ((L.cyc >> a) & 1u) {
+            const int La = 1 << L.lg[a];
+            o = ((o + La / 2) & (La - 1)) - La / 2;
+            if (La >= 2 && o == -(La / 2)) dn = min(up, dn);
+        }
+        g2 += axis_gap2(o, up, dn, L.F);
+    }
+    const bool keep = has && g2 <= bound2;
+    RowRef r;
+    r.st0 = c.y;
+    r.cnt0 = keep ? end - c.y : 0u;
+    r.st1 = c.y;
+    r.cnt1 = 0u;
+    r.ist = c.y;
+    r.icnt = 0u;
+    r.kept = keep ? 1u : 0u;
+    return r;
+}
+
 // Minimum-image squared distance of an object to the centre: on a cyclic
 // axis ((p - q + W/2) mod W) - W/2; on a clipped axis plain p - q (both below
 // 2^30, so the difference fits an int).
@@ -588,6 +669,8 @@ __device__ __forceinline__ void walk(const LatArgs& L, const TabArgs& T, const u
             const uint32_t w = nxt;
             if (ent + 64 < nent) nxt = rows[ent + 64];
             r = sphere_row(L, s, w, ent < nent, bound2, interior);
+        } else if (s.flags & F_LIST) {
+            r = list_row(L, s, ent, ent < nent, bound2_now());
         } else {
             r = cube_row(L, s, ent, ent < nent, inv_ny);
         }
@@ -985,8 +1068,8 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
                 if (!valid) {
                     invalid = true;
                 } else if (METHOD == kSphere && !sph) {
-                    // counted by the fallback list's cube kernel
-                } else if ((flags & F_KNN) || r2bits > d2bits) {
+                    // counted by the fallback list's kernel
+                } else if ((flags & (F_KNN | F_LIST)) || r2bits > d2bits) {
                     extra = true;
                 } else {
                     mine = true;

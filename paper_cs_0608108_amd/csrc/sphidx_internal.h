@@ -23,6 +23,9 @@ struct sphidx_lattice {
     uint32_t* status;   // device status word
     size_t bytes;
     int device;
+    // attached non-empty cell list (caller-owned): count word, then entries
+    // {cell, first sorted position} from byte 16; NULL when none
+    char* cell_list;
 };
 
 struct sphidx_tables {
@@ -52,6 +55,7 @@ struct sphidx_tables {
     int64_t* d_rkey = nullptr;
     uint32_t* d_rclass_start = nullptr;
     uint32_t* d_rrindex = nullptr;
+    uint32_t* d_vcount = nullptr;  // copy of h_rindex: cells per class and radius bucket
     size_t device_bytes = 0;
 };
 
@@ -67,6 +71,8 @@ struct LatArgs {
     const uint32_t* cs;   // cell_start
     const uint4* pts;     // sorted objects {x, y, z, id}
     uint32_t* status;
+    const uint2* cells;   // non-empty cell list {cell, first} (NULL: none kept)
+    const uint32_t* ncl;  // its length (device)
 };
 
 struct TabArgs {
@@ -74,6 +80,7 @@ struct TabArgs {
     const int64_t* rkey;    // row keys, same order
     const uint32_t* cstart; // first row of each class
     const uint32_t* rindex; // per class and radius bucket: rows with key <= bucket^2
+    const uint32_t* vcount; // per 3-D sub-cell class and radius bucket: cells with key <= bucket^2
     uint32_t s;
     uint32_t rshift;
     uint32_t nr;
@@ -127,6 +134,11 @@ struct QArgs {
     uint32_t sort_cap;
     uint32_t interior;  // count pass: count wholly-inside cells without reading them
     uint32_t group;     // count pass: radius queries in groups per wavefront
+    uint32_t select;    // setup: 0 = the kernel's method, 1 = choose by volume, 2 = cell list
+    uint32_t weight;    // volume choice: sphere cells x weight / 256 against cube cells
+    uint32_t rev;       // volume choice: radius queries below this skip the sphere
+    uint32_t knn_rev;   // volume choice: K-NN queries below this take the cube
+    uint32_t* method_out;  // optional per query row: the walk used
 };
 
 // Stash header words (in the counter block): written by the count pass,
@@ -147,6 +159,7 @@ enum : uint32_t { kHdrMode = 0, kHdrElems = 1, kHdrHasD2 = 2, kHdrD2Off = 3 };
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t st);
 hipError_t launch_build(const sphidx_lattice* lat, const uint32_t* x, const uint32_t* y, const uint32_t* z,
                         uint32_t n, hipStream_t st);
+hipError_t launch_cell_list(const sphidx_lattice* lat, hipStream_t st);
 hipError_t launch_scan_i64(int64_t* data, uint32_t n, void* tmp, hipStream_t st);
 size_t scan_i64_tmp_bytes(uint32_t n);
 hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const QArgs& q,

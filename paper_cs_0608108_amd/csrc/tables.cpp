@@ -45,7 +45,8 @@ uint64_t fnv1a(const void* data, size_t n, uint64_t h) {
 
 }  // namespace
 
-// Copy the row table to device memory (once).
+// Copy the row table, and the full table's radius index (the cell counts
+// the method choice compares), to device memory (once).
 sphidx_status tables_upload(sphidx_tables* t) {
     if (t->d_rows) return SPHIDX_OK;
     t->device_bytes = 0;
@@ -59,7 +60,8 @@ sphidx_status tables_upload(sphidx_tables* t) {
     bool ok = put((void**)&t->d_rows, t->h_rows.data(), t->h_rows.size() * 4) &&
               put((void**)&t->d_rkey, t->h_rkey.data(), t->h_rkey.size() * 8) &&
               put((void**)&t->d_rclass_start, t->h_rclass_start.data(), t->h_rclass_start.size() * 4) &&
-              put((void**)&t->d_rrindex, t->h_rrindex.data(), t->h_rrindex.size() * 4);
+              put((void**)&t->d_rrindex, t->h_rrindex.data(), t->h_rrindex.size() * 4) &&
+              put((void**)&t->d_vcount, t->h_rindex.data(), t->h_rindex.size() * 4);
     return ok ? SPHIDX_OK : SPHIDX_ERR_OUT_OF_MEMORY;
 }
 
@@ -70,6 +72,8 @@ void free_device(sphidx_tables* t) {
     if (t->d_rkey) (void)hipFree(t->d_rkey);
     if (t->d_rclass_start) (void)hipFree(t->d_rclass_start);
     if (t->d_rrindex) (void)hipFree(t->d_rrindex);
+    if (t->d_vcount) (void)hipFree(t->d_vcount);
+    t->d_vcount = nullptr;
     t->d_rows = nullptr;
     t->d_rkey = nullptr;
     t->d_rclass_start = nullptr;

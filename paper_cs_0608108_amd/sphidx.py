@@ -21,7 +21,7 @@ OK, ERR_INVALID_ARG, ERR_RANGE, ERR_RADIUS, ERR_CAPACITY, ERR_OOM, ERR_DEVICE, E
 FLAG_RANGE, FLAG_CAPACITY, FLAG_FALLBACK = 1, 2, 4
 MODE_RADIUS, MODE_KNN, MODE_MIXED = 0, 1, 2
 EXCLUDE_SELF = 1
-METHOD_SPHERE, METHOD_CUBE = 0, 1
+METHOD_SPHERE, METHOD_CUBE, METHOD_AUTO, METHOD_LIST = 0, 1, 2, 3
 SCHED_PLAIN, SCHED_PERSISTENT = 0, 1
 
 U32, I32, U64, I64, SZ, P = (ctypes.c_uint32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64,
@@ -55,7 +55,8 @@ class LaunchDesc(ctypes.Structure):
     _fields_ = [("method", U32), ("schedule", U32), ("waves_per_block", U32), ("tile", U32),
                 ("blocks_per_cu", U32), ("sort_cap", U32), ("table_in_lds", U32), ("interior", U32),
                 ("stats_dev", P), ("event_begin", P), ("event_end", P), ("no_stash", U32),
-                ("grouped", U32)]
+                ("grouped", U32), ("select_weight", U32), ("reversal_fx", U32), ("knn_reversal_fx", U32),
+                ("method_dev", P)]
 
 
 # Every symbol include/sphidx.h declares, with its ctypes signature.
@@ -66,6 +67,8 @@ SIGNATURES = {
     "sphidx_build_lattice": (ctypes.c_int, [P, P, P, P, U32, P]),
     "sphidx_lattice_get_view": (ctypes.c_int, [P, ctypes.POINTER(LatticeView)]),
     "sphidx_lattice_status": (ctypes.c_int, [P, P, ctypes.POINTER(U32)]),
+    "sphidx_cell_list_bytes": (SZ, [P]),
+    "sphidx_lattice_attach_cell_list": (ctypes.c_int, [P, P, SZ, P]),
     "sphidx_build_sphere_tables": (ctypes.c_int, [ctypes.POINTER(LatticeDesc), U32, U32, ctypes.POINTER(P)]),
     "sphidx_tables_destroy": (None, [P]),
     "sphidx_tables_get_info": (ctypes.c_int, [P, ctypes.POINTER(TablesInfo)]),
@@ -171,6 +174,7 @@ class Lattice:
         self.log2_cells = tuple(int(v) for v in log2_cells)
         self.frac_bits = int(frac_bits)
         self.cyclic_mask = int(cyclic_mask)
+        self.cell_list = None
 
     def __del__(self):
         try:
@@ -193,6 +197,28 @@ class Lattice:
         v = LatticeView()
         check(load().sphidx_lattice_get_view(self.handle, ctypes.byref(v)))
         return v
+
+    def attach_cell_list(self, on=True, stream=None):
+        """Keep the non-empty cell list (rebuilt with every build) in a buffer
+        owned by this object, or detach it."""
+        lib = load()
+        if not on:
+            check(lib.sphidx_lattice_attach_cell_list(self.handle, None, 0, _stream(stream)), "detach_cell_list")
+            self.cell_list = None
+            return
+        nbytes = lib.sphidx_cell_list_bytes(self.handle)
+        buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.workspace.device)
+        off = (-buf.data_ptr()) % 256
+        check(lib.sphidx_lattice_attach_cell_list(self.handle, ctypes.c_void_p(buf.data_ptr() + off), nbytes,
+                                                  _stream(stream)), "attach_cell_list")
+        self.cell_list = buf[off:off + nbytes]
+
+    def cell_list_host(self):
+        """(count, entries uint32[count + 1, 2]) of the attached list (synchronises)."""
+        torch.cuda.synchronize()
+        raw = self.cell_list.view(torch.int32).cpu().numpy().view(np.uint32)
+        cnt = int(raw[0])
+        return cnt, raw[4:4 + 2 * (cnt + 1)].reshape(cnt + 1, 2).copy()
 
     def status(self, stream=None):
         """(status code, flags); synchronises the stream and clears the word."""
@@ -275,6 +301,10 @@ class LaunchConfig:
     events: tuple | None = None  # (begin, end) torch.cuda.Event around the pass's main kernel
     no_stash: int = 0
     grouped: int = 0
+    select_weight: int = 0  # METHOD_AUTO: Q8 weight of the sphere's cell count (0 = 256)
+    reversal_fx: int = 0
+    knn_reversal_fx: int = 0
+    method_out: torch.Tensor | None = None  # int32[Q]: the walk each query used
 
     def c(self) -> LaunchDesc:
         d = LaunchDesc()
@@ -284,6 +314,8 @@ class LaunchConfig:
         d.interior = self.interior
         d.no_stash = self.no_stash
         d.grouped = self.grouped
+        d.select_weight, d.reversal_fx, d.knn_reversal_fx = self.select_weight, self.reversal_fx, self.knn_reversal_fx
+        d.method_dev = None if self.method_out is None else self.method_out.data_ptr()
         d.stats_dev = None if self.stats is None else self.stats.data_ptr()
         if self.events is not None:
             for ev in self.events:

@@ -19,7 +19,7 @@ from . import sphidx
 
 class AgentSim:
     def __init__(self, log2_cells, frac_bits, cyclic_mask, pts, r_fx, seed, subcell_bits=2, headroom=1.25,
-                 launch: sphidx.LaunchConfig | None = None, flags=0):
+                 launch: sphidx.LaunchConfig | None = None, flags=0, cell_list=False):
         self.n = len(pts[0])
         self.desc = sphidx.desc_of(log2_cells, frac_bits, cyclic_mask)
         self.lat = sphidx.Lattice(log2_cells, frac_bits, cyclic_mask, self.n)
@@ -31,6 +31,8 @@ class AgentSim:
         self.q = sphidx.make_queries(self.n, None, self.r_fx, None, sphidx.MODE_RADIUS, flags)
         self.step_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
         self.chk = torch.zeros(2, dtype=torch.int64, device="cuda")
+        if cell_list:  # rebuilt with the lattice, inside the captured step too
+            self.lat.attach_cell_list()
         # size the outputs from the pairs at the starting positions
         self.lat.build(*self.pos)
         probe = sphidx.QueryBuffers(self.n, 0, want_dist2=False)

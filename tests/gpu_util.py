@@ -10,9 +10,13 @@ def say(*a):
     sys.stdout.flush()
 
 
-def lattice(sx, log2, F, mask, pts):
+def lattice(sx, log2, F, mask, pts, cell_list=True):
+    """A built lattice; with cell_list, its non-empty cell list is kept too
+    (which only METHOD_AUTO and METHOD_LIST read)."""
     n = len(pts[0])
     lat = sx.Lattice(log2, F, mask, max(n, 1))
+    if cell_list:
+        lat.attach_cell_list()
     dev = tuple(sx.to_dev_u32(a) for a in pts)
     lat.build(*dev)
     lat._pts_dev = dev  # keep alive

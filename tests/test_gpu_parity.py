@@ -34,6 +34,10 @@ def _launches(sx):
                               waves_per_block=1, sort_cap=128),
         "cube": L(method=sx.METHOD_CUBE, schedule=sx.SCHED_PERSISTENT),
         "cube-plain": L(method=sx.METHOD_CUBE, schedule=sx.SCHED_PLAIN, tile=3),
+        "auto": L(method=sx.METHOD_AUTO, schedule=sx.SCHED_PERSISTENT),
+        "auto-grouped-weighted": L(method=sx.METHOD_AUTO, schedule=sx.SCHED_PERSISTENT, grouped=1,
+                                   select_weight=384, reversal_fx=40),
+        "list-plain": L(method=sx.METHOD_LIST, schedule=sx.SCHED_PLAIN, tile=2),
     }
 
 
@@ -242,7 +246,7 @@ def test_knn_random_worlds_and_mixed_batches(sx, orc, mask):
     rmax = rng.integers(0, 4 * e, n).astype(np.uint32)
     for flags in (0, 1):
         ref = grid.knn(k, rmax, flags=flags)
-        for name in ("sphere-persistent", "sphere-small-cap", "cube-plain"):
+        for name in ("sphere-persistent", "sphere-small-cap", "cube-plain", "auto", "list-plain"):
             assert_same(run(sx, lat, tab, rmax, k=k, mode=sx.MODE_KNN, flags=flags, launch=_launches(sx)[name]),
                         ref, f"knn {name} flags={flags}")
     # mixed: K-NN where k > 0, radius otherwise; explicit centres
@@ -250,7 +254,7 @@ def test_knn_random_worlds_and_mixed_batches(sx, orc, mask):
     kk = np.where(rng.random(500) < 0.5, rng.integers(1, 30, 500), 0).astype(np.uint32)
     rr = rng.integers(0, 4 * e, 500).astype(np.uint32)
     ref = grid.mixed(kk, rr, queries=qs)
-    for name in ("sphere-persistent", "sphere-plain", "cube"):
+    for name in ("sphere-persistent", "sphere-plain", "cube", "auto-grouped-weighted", "list-plain"):
         assert_same(run(sx, lat, tab, rr, k=kk, mode=sx.MODE_MIXED, queries=qs, launch=_launches(sx)[name]),
                     ref, f"mixed {name}")
 

@@ -28,6 +28,10 @@ def sx():
     (5, (5, 4, 6), 20000, 12, {}),
     (7, (5, 5, 5), 32768, 13, {"sort_cap": 128, "table_in_lds": 1}),
     (5, (5, 4, 6), 20000, 14, {"grouped": 1, "waves_per_block": 2}),
+    # the non-empty cell list, rebuilt inside the captured step: chosen by
+    # volume at 150 agents in 32^3 cells, or forced for every query
+    (7, (5, 5, 5), 150, 15, {"method": 2, "cell_list": True}),
+    (5, (5, 4, 6), 3000, 16, {"method": 3, "cell_list": True}),
 ])
 def test_timestep_graph_replays_match_oracle(sx, orc, mask, log2, n, seed, launch):
     import torch
@@ -38,7 +42,9 @@ def test_timestep_graph_replays_match_oracle(sx, orc, mask, log2, n, seed, launc
     pts = synth.uniform_points(spec, n, seed)
     r = 3 * (1 << F)
     say(f"timestep mask={mask} log2={log2} n={n} seed={seed} launch={launch}")
-    sim = timestep.AgentSim(log2, F, mask, pts, r, seed, launch=sx.LaunchConfig(**launch))
+    launch = dict(launch)
+    cell_list = launch.pop("cell_list", False)
+    sim = timestep.AgentSim(log2, F, mask, pts, r, seed, launch=sx.LaunchConfig(**launch), cell_list=cell_list)
     L = orc.Lattice(log2, F, mask)
     cur = tuple(np.asarray(a, dtype=np.uint32) for a in pts)
 
