@@ -189,6 +189,25 @@ def leg_c2(args, out):
             "speedup_vs_cube": round(ms_cube / ms, 3),
         })
         log(f"plain: {ms_plain:.3f} ms/step; cube: {ms_cube:.3f} ms/step; cube result identical: {same}")
+        # the per-query choice (Section III.B/C) with the tuned launch, by
+        # cells (the paper's volumes) and by estimated lane work; the
+        # non-empty cell list is kept (and rebuilt) only here
+        lat.attach_cell_list()
+        for model, tag in ((0, "auto_choice"), (1, "auto_work")):
+            mo = torch.empty(n, dtype=torch.int32, device="cuda")
+            auto = dataclasses.replace(tuned, method=sphidx.METHOD_AUTO, method_out=mo, select_model=model)
+            ms_auto, ph_auto, k_auto = timed(auto, k2, 1)
+            rp_a = buf.row_ptr.cpu().numpy()
+            ids_a = buf.ids[: int(rp_a[-1])].cpu().numpy().view(np.uint32)
+            used = torch.bincount(mo.long(), minlength=4).cpu().tolist()
+            out[tag] = {"ms_per_step": round(ms_auto, 4), "query_ms": round(float(ph_auto[1] + ph_auto[2]), 4),
+                        "rebuild_ms": round(float(ph_auto[0]), 4), "count_kernel_ms": round(float(k_auto[0]), 4),
+                        "chose": {"sphere": used[sphidx.METHOD_SPHERE], "cube": used[sphidx.METHOD_CUBE],
+                                  "list": used[sphidx.METHOD_LIST]},
+                        "same_result": bool(np.array_equal(rp_a, rp) and np.array_equal(ids_a, ids))}
+            log(f"{tag}: {ms_auto:.3f} ms/step (query {ph_auto[1] + ph_auto[2]:.3f} ms, count kernel "
+                f"{k_auto[0]:.3f}), chose {out[tag]['chose']}")
+        lat.attach_cell_list(False)
 
     # roofline of the dominant kernel, the count kernel (it walks the tables,
     # tests candidates, sorts each row and keeps it in the stash):
@@ -504,7 +523,9 @@ def leg_sweep(args, out):
     (16^3, 32^3), boundary (wrapping, clipped), load and query distance (cell
     units, up to 3/4 of the world), the shapes of the paper's Figs. 5-10.
     Each point times the same queries with both methods (count + write, the
-    write touching every neighbour's id) and checks that their rows agree."""
+    write touching every neighbour's id) and checks that their rows agree.
+    All-neighbour points also time the per-query choice by volume (sphere,
+    cube or non-empty cell list, Section III.B/C) and count what it chose."""
     import numpy as np
     import torch
 
@@ -540,8 +561,10 @@ def leg_sweep(args, out):
                 w = synth.sweep_world(log2, mask, load)
                 L = 1 << log2
                 lat = sphidx.Lattice(w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask, max(w.n, 1))
+                lat.attach_cell_list()
                 dev = [sphidx.to_dev_u32(a) for a in w.pts]
                 lat.build(*dev)
+                n_list = lat.cell_list_host()[0]
                 tab = sphidx.Tables(lat, 2, int(0.75 * L * w.lat.edge))
                 for rc in radii:
                     if rc > 0.75 * L:
@@ -551,7 +574,8 @@ def leg_sweep(args, out):
                     vol = min(4.19 * rc ** 3, float(L ** 3))
                     Q = int(min(16384, max(512, 3e7 / max(load * vol, 1.0))))
                     cen = [sphidx.to_dev_u32(a) for a in synth.sweep_centres(w.lat, 6, Q)]
-                    point = {"world": f"{L}^3", "wrap": mask == 7, "load": load, "r": rc, "queries": Q}
+                    point = {"world": f"{L}^3", "wrap": mask == 7, "load": load, "r": rc, "queries": Q,
+                             "nonempty_cells": n_list}
                     for mode, k, key in ((sphidx.MODE_RADIUS, 0, "all"), (sphidx.MODE_KNN, 1, "nearest")):
                         q = sphidx.make_queries(Q, tuple(cen), r, k, mode, 0)
                         t_s, b_s = timed_query(lat, tab, q, sphidx.LaunchConfig())
@@ -561,14 +585,35 @@ def leg_sweep(args, out):
                         mismatches += 0 if same else 1
                         point[key] = {"sphere_ms": round(t_s, 4), "cube_ms": round(t_c, 4),
                                       "ratio": round(t_c / t_s, 3), "pairs": n_s, "same": same}
+                        if mode == sphidx.MODE_RADIUS:
+                            # the choice by cells (model 0, the paper's) and by
+                            # estimated lane work (model 1)
+                            for model, tag in ((0, "auto"), (1, "work")):
+                                mo = torch.empty(Q, dtype=torch.int32, device="cuda")
+                                ln_a = sphidx.LaunchConfig(method=sphidx.METHOD_AUTO, method_out=mo,
+                                                           select_model=model)
+                                t_a, b_a = timed_query(lat, tab, q, ln_a)
+                                same_a = bool(torch.equal(b_s.row_ptr, b_a.row_ptr) and
+                                              torch.equal(b_s.ids[:n_s], b_a.ids[:n_s]))
+                                mismatches += 0 if same_a else 1
+                                used = torch.bincount(mo.long(), minlength=4).cpu().tolist()
+                                point[key].update({f"{tag}_ms": round(t_a, 4), f"ratio_{tag}": round(t_c / t_a, 3),
+                                                   f"{tag}_chose": {"sphere": used[sphidx.METHOD_SPHERE],
+                                                                    "cube": used[sphidx.METHOD_CUBE],
+                                                                    "list": used[sphidx.METHOD_LIST]},
+                                                   f"same_{tag}": same_a})
+                                del b_a
                         del b_s, b_c
                     rows.append(point)
                     log(f"sweep {point['world']} wrap={point['wrap']} load={load} r={rc}: all x{point['all']['ratio']}"
+                        f" auto x{point['all']['ratio_auto']} {point['all']['auto_chose']}"
+                        f" work x{point['all']['ratio_work']} {point['all']['work_chose']}"
                         f" nearest x{point['nearest']['ratio']}")
                 del lat, tab, dev
                 torch.cuda.empty_cache()
     out["section_iv_sweep"] = {
-        "ratio": "cube ms / sphere ms (above 1: the sphere tables are faster)",
+        "ratio": "cube ms / sphere ms (above 1: the sphere tables are faster); ratio_auto, ratio_work: "
+                 "cube ms / ms of the per-query choice by cells (the paper's volumes) and by estimated work",
         "step": "count + write on random centres; rows compared between the methods",
         "all_points_identical": mismatches == 0, "points": rows}
 

@@ -243,6 +243,7 @@ typedef struct {
     /* METHOD_AUTO (Appendix: weighting factor and reversal distances).  A radius query takes
      * the sphere when select_weight/256 * (sphere cells) <= (cube cells), else the cube; then
      * the non-empty list instead if it holds fewer cells than the one chosen (plain counts).
+     * (Model 0 below; model 1 compares estimated work instead of cells.)
      * Sphere cells: the entries of the query's sub-cell class with key <= (j * 2^b)^2,
      * j = ceil(r / 2^b), b = max(F - 6, 0) -- the one lookup of the radius index.  Cube
      * cells: the bounding cube's cells inside the region (the whole axis once it spans it).
@@ -252,6 +253,17 @@ typedef struct {
     uint32_t select_weight;   /* Q8 fixed point; 0 = 256 (the plain volume comparison) */
     uint32_t reversal_fx;     /* radius queries with r < reversal_fx never take the sphere; 0 = off */
     uint32_t knn_reversal_fx; /* K-NN queries with cap < knn_reversal_fx take the cube; 0 = off */
+    uint32_t select_model;    /* what the comparisons count: 0 = cells (the paper's volumes);
+                                 1 = estimated lane work of each walk: the rows it visits (sphere:
+                                 table rows with key <= (j * 2^b)^2, i.e. cells of that prefix with
+                                 ox = 0; cube: its y-z rows; list: its entries) plus the mean objects
+                                 per region cell times the cells whose objects it tests (sphere and
+                                 list: floor(sphere cells * cube cells / unclipped cube cells), or
+                                 the cube cells when the sphere is left out; cube: the cube cells),
+                                 in 1/256 units with the mean taken as
+                                 min(floor(256 * n / region cells), 2^24); the unclipped cube spans
+                                 floor((q - r) / 2^F) .. floor((q + r) / 2^F) per axis, at most the
+                                 axis on a cyclic one */
     uint32_t* method_dev;     /* optional uint32[Q], written by the count pass: the walk each query
                                  used (SPHIDX_METHOD_SPHERE, _CUBE or _LIST), or 0xFFFFFFFF for a
                                  query with an empty row by definition (invalid centre, K = 0) */

@@ -93,7 +93,7 @@ TabArgs tab_args(const sphidx_tables* t) {
 
 struct Launch {
     uint32_t method, persistent, waves, tile, bpc, cap, tab_lds, interior, no_stash, grouped;
-    uint32_t weight, rev, knn_rev;
+    uint32_t weight, rev, knn_rev, model;
     uint32_t* stats;
     uint32_t* method_out;
     hipEvent_t ev_begin, ev_end;
@@ -118,6 +118,8 @@ sphidx_status resolve_launch(const sphidx_launch* in, const sphidx_tables* tab, 
     o.weight = (in && in->select_weight) ? in->select_weight : 256u;
     o.rev = in ? in->reversal_fx : 0u;
     o.knn_rev = in ? in->knn_reversal_fx : 0u;
+    o.model = in ? in->select_model : 0u;
+    if (o.model > 1) return SPHIDX_ERR_INVALID_ARG;
     if (o.weight > (1u << 16)) return SPHIDX_ERR_INVALID_ARG;
     o.ev_begin = in ? (hipEvent_t)in->event_begin : nullptr;
     o.ev_end = in ? (hipEvent_t)in->event_end : nullptr;
@@ -222,6 +224,7 @@ QArgs q_args(const sphidx_queries* q, sphidx_csr* csr, const Launch& ln) {
     A.weight = ln.weight;
     A.rev = ln.rev;
     A.knn_rev = ln.knn_rev;
+    A.model = ln.model;
     A.method_out = ln.method_out;
     return A;
 }

@@ -192,7 +192,7 @@ __device__ __forceinline__ uint32_t pack_cell(const LatArgs& L, uint32_t x, uint
 template <int METHOD>
 __global__ __launch_bounds__(256) void setup_kernel(LatArgs L, TabArgs T, QArgs A) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    bool range_bad = false, fallback = false;
+    bool range_bad = false, fallback = false, to_list = false;
     if (i < A.Q) {
         uint32_t q[3], row, r, k;
         bool valid = true;
@@ -225,11 +225,13 @@ __global__ __launch_bounds__(256) void setup_kernel(LatArgs L, TabArgs T, QArgs 
         const uint32_t e = 1u << L.F;
         bool inside = true, cyc_ok = true, outside = false;
         uint32_t ncube = 1, nn[3] = {0, 0, 0};
+        uint64_t nfull = 1;  // the cube's cells before clipping to the region
         int32_t lo3[3] = {0, 0, 0};
         for (int a = 0; a < 3; ++a) {
             const uint32_t La = 1u << L.lg[a];
             int64_t lo = ((int64_t)q[a] - (int64_t)r) >> L.F;
             int64_t hi = ((int64_t)q[a] + (int64_t)r) >> L.F;
+            nfull *= (uint64_t)min(hi - lo + 1, ((L.cyc >> a) & 1u) ? (int64_t)La : hi - lo + 1);
             if ((L.cyc >> a) & 1u) {
                 // the sphere walk needs ceil(r/e) <= L/2 - 1 (no offset repeats a cell)
                 if (La < 4 || (uint64_t)r > (uint64_t)(La / 2 - 1) * e) cyc_ok = false;
@@ -262,27 +264,50 @@ __global__ __launch_bounds__(256) void setup_kernel(LatArgs L, TabArgs T, QArgs 
             // the cube's, and below the reversal distances the sphere is left
             // out (Appendix).  K-NN queries choose only between the sphere and
             // the cube (Section IV.B).
+            // Model 1 (this design's reading of the weighting, for a row
+            // walk): each walk's lane work, rows visited plus objects tested,
+            // the latter as the mean objects per cell times the cells read.
             if (knn) {
                 sphere = sphere && r >= A.knn_rev;
             } else {
                 sphere = sphere && r >= A.rev;
-                uint64_t chosen = ncube;
+                const uint64_t load = A.model ? min(((uint64_t)L.n << 8) / L.ncells, (uint64_t)1 << 24) : 0u;
+                uint64_t ws = 0, tested = ncube;
+                const uint64_t wc = A.model ? (uint64_t)nn[1] * nn[2] * 256u + load * ncube : ncube;
+                uint64_t chosen = wc;
                 if (sphere) {
                     const uint32_t cls3 = ((q[0] & (e - 1u)) >> (L.F - T.s)) |
                                           (((q[1] & (e - 1u)) >> (L.F - T.s)) << T.s) |
                                           (((q[2] & (e - 1u)) >> (L.F - T.s)) << (2u * T.s));
                     const uint64_t vs = T.vcount[(size_t)cls3 * T.nr + j];
-                    sphere = vs * A.weight <= (uint64_t)ncube * 256u;
-                    if (sphere) chosen = vs;
+                    if (A.model) {
+                        // every table row takes a lane; objects are read only
+                        // in the region: the sphere's cells scaled by the
+                        // part of its bounding cube inside the region
+                        const uint32_t rcls = cls3 >> T.s;
+                        tested = vs * ncube / nfull;
+                        ws = (uint64_t)T.rindex[(size_t)rcls * T.nr + j] * 256u + load * tested;
+                    } else {
+                        ws = vs;
+                    }
+                    sphere = (unsigned __int128)ws * A.weight <= (unsigned __int128)wc * 256u;
+                    if (sphere) chosen = ws;
                 }
-                if (L.ncl && (uint64_t)*L.ncl < chosen) {
-                    sphere = false;
-                    list = true;
+                if (L.ncl) {
+                    const uint64_t nl = *L.ncl;
+                    // the list tests the objects of the cells the sphere meets
+                    // (with the sphere left out: the cube's)
+                    const uint64_t wl = A.model ? nl * 256u + load * tested : nl;
+                    if (wl < chosen) {
+                        sphere = false;
+                        list = true;
+                    }
                 }
             }
         }
         fallback = valid && METHOD == kSphere && !usable;
-        if (valid && METHOD == kSphere && !sphere) A.fbq[atomicAdd(A.fb_count, 1u)] = i;
+        // (chosen per query: the main kernels take every walk themselves)
+        to_list = valid && METHOD == kSphere && !sphere && A.select != 1u;
         uint32_t tb = 0, tend = 0;
         if (sphere && valid) {
             // row tables are specialised on the (y, z) sub-cell position
@@ -307,6 +332,15 @@ __global__ __launch_bounds__(256) void setup_kernel(LatArgs L, TabArgs T, QArgs 
         d[1] = make_uint4(r, k, flags, tb);
         d[2] = make_uint4(tend, ncube, nn[0], nn[1]);
         d[3] = make_uint4((uint32_t)lo3[0], (uint32_t)lo3[1], (uint32_t)lo3[2], nn[2]);
+    }
+    // queries for the fallback list's kernels (bounding cube or cell list):
+    // one atomic per wavefront, the wavefront's queries in order
+    const uint64_t lm = __ballot(to_list);
+    if (lm) {
+        uint32_t base = 0;
+        if (lane_id() == 0) base = atomicAdd(A.fb_count, (uint32_t)__popcll(lm));
+        base = uni(base);
+        if (to_list) A.fbq[base + lanes_below(lm)] = i;
     }
     if (__ballot(range_bad) && lane_id() == 0) atomicOr(L.status, SPHIDX_FLAG_RANGE);
     if (__ballot(fallback) && lane_id() == 0) atomicOr(L.status, SPHIDX_FLAG_FALLBACK);
@@ -690,11 +724,19 @@ __device__ __forceinline__ void walk(const LatArgs& L, const TabArgs& T, const u
 // Query scheduling: plain (each wave owns a fixed slice of `tile` queries,
 // XCD-aware block order) or persistent (per-XCD work queues).
 
+// Persistent grabs shrink with the work: about two per resident wave, at
+// least `tmin` and at most A.tile (64 for the lists), so that a short batch
+// or list of heavy queries is shared out instead of landing on a few waves,
+// and a long one does not pay an atomic per query.
 template <typename F>
-__device__ __forceinline__ void for_each_range(uint32_t Q, const QArgs& A, uint32_t* queues, F&& f) {
+__device__ __forceinline__ void for_each_range(uint32_t Q, const QArgs& A, uint32_t* queues, F&& f,
+                                               uint32_t tmin = 1u) {
     if (Q == 0) return;
     const uint32_t lane = lane_id();
     const uint32_t wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint32_t tmax = A.list ? 64u : A.tile;
+    const uint32_t tile =
+        A.persistent ? max(tmin, min(tmax, (uint32_t)((uint64_t)Q / ((uint64_t)gridDim.x * nw * 2u)))) : A.tile;
     // plain: consecutive block ids go round-robin over the 8 XCDs; give each
     // XCD a contiguous range of slices so neighbouring queries share its L2.
     // persistent: one queue per XCD over a contiguous range of queries; drain
@@ -710,9 +752,9 @@ __device__ __forceinline__ void for_each_range(uint32_t Q, const QArgs& A, uint3
             const uint32_t G = gridDim.x, bi = blockIdx.x;
             const uint32_t full = G / SPHIDX_NQUEUE, rem = G % SPHIDX_NQUEUE;
             const uint32_t lb = x * full + min(x, rem) + bi / SPHIDX_NQUEUE;
-            const uint64_t q0 = ((uint64_t)lb * nw + wave) * A.tile;
+            const uint64_t q0 = ((uint64_t)lb * nw + wave) * tile;
             b = (uint32_t)min(q0, (uint64_t)Q);
-            e = (uint32_t)min(q0 + A.tile, (uint64_t)Q);
+            e = (uint32_t)min(q0 + tile, (uint64_t)Q);
         } else {
             if (misses >= SPHIDX_NQUEUE) break;
             const uint32_t qs = (uint32_t)(((uint64_t)x * Q) / SPHIDX_NQUEUE);
@@ -722,7 +764,7 @@ __device__ __forceinline__ void for_each_range(uint32_t Q, const QArgs& A, uint3
             if (lane == 0) {
                 // an exhausted queue is skipped with a plain read, not an atomic
                 t = __hip_atomic_load(qc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if ((uint64_t)qs + t < qe) t = atomicAdd(qc, A.tile);
+                if ((uint64_t)qs + t < qe) t = atomicAdd(qc, tile);
             }
             t = uni(t);
             if ((uint64_t)qs + t >= qe) {
@@ -732,7 +774,7 @@ __device__ __forceinline__ void for_each_range(uint32_t Q, const QArgs& A, uint3
             }
             misses = 0;
             b = qs + t;
-            e = (uint32_t)min((uint64_t)qe, (uint64_t)qs + t + A.tile);
+            e = (uint32_t)min((uint64_t)qe, (uint64_t)qs + t + tile);
         }
         first = false;
         if (b < e) f(b, e);
@@ -1022,7 +1064,7 @@ __device__ __forceinline__ uint64_t key_d2(uint64_t k, uint32_t idbits, uint32_t
     return (k >> idbits) & ((1ull << d2bits) - 1ull);
 }
 
-template <int METHOD, bool TLDS, bool STASH>
+template <int METHOD, bool TLDS, bool STASH, bool FROM_LIST>
 __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, QArgs A) {
     extern __shared__ __align__(16) char smem[];
     const uint32_t* tab_lds = stage_table<TLDS>(T, smem);
@@ -1046,12 +1088,14 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
     const uint32_t region = blockIdx.x % SPHIDX_NQUEUE;
     uint32_t cur = 0, lim = 0;
     bool dry = false;
-    for_each_range(A.Q, A, queue_set(A, kQCount), [&](uint32_t b, uint32_t e) {
+    const uint32_t nq = FROM_LIST ? uni(*A.list_count) : A.Q;
+    for_each_range(nq, A, queue_set(A, FROM_LIST ? (int)A.list_set : kQCount), [&](uint32_t b, uint32_t e) {
         for (uint32_t g0 = b, ng = 0; g0 < e; g0 += ng) {
             const uint32_t cand = min(kGroup, e - g0);
-            // ---- slots: lane l < cand looks at query g0 + l; the group keeps
-            // the leading slots whose rows fit group_rows (at least one)
-            const uint32_t qi = g0 + lane;
+            // ---- slots: lane l < cand looks at query g0 + l (of the list);
+            // the group keeps the leading slots whose rows fit group_rows (at
+            // least one)
+            const uint32_t qi = FROM_LIST ? (lane < cand ? A.list[g0 + lane] : 0u) : g0 + lane;
             uint32_t rows = 0, row = 0;
             bool mine = false, extra = false, invalid = false;
             uint4 d0 = make_uint4(0, 0, 0, 0), d1 = d0, d2 = d0, d3 = d0;
@@ -1316,7 +1360,7 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
             }
             wave_sync();
         }
-    });
+    }, kGroup);
 }
 
 // ---------------------------------------------------------------------------
@@ -1778,41 +1822,59 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
         if (e != hipSuccess) return e;
     }
     const uint32_t w = waves_per_block, b = blocks_per_cu;
-    QArgs ql = q;  // list-driven launches: persistent, one query per grab
+    // per-query choice: the main kernels walk the sphere, the cube or the
+    // cell list per query (grouping them apart would split the groups)
+    const bool either = variant != 0 && q.select == 1u;
+    QArgs ql = q;  // list-driven launches: persistent, grabs sized from the list
     ql.persistent = 1;
-    ql.tile = 1;
     if (pass == 0) {
         const int lp = q.stash ? 3 : 0;
         if ((e = mark(ev_begin)) != hipSuccess) return e;
         if (q.group) {
-            // radius queries in groups; the rest through the extra list
+            // radius queries in groups: all queries (those of the tables),
+            // then the fallback list's (bounding cube); the rest through the
+            // extra list, one query per wavefront
+            const size_t gl = query_lds_bytes(q.stash ? 5 : 4, q.sort_cap, w, tb);
             if (q.stash)
-                e = launch_ptr(SPHIDX_PICK(group_count_kernel, variant, kSphere, , true), q.Q, q, w, b,
-                               query_lds_bytes(5, q.sort_cap, w, tb), st, L, T);
+                e = launch_ptr(either ? SPHIDX_PICK(group_count_kernel, variant, kEither, , true, false)
+                                      : SPHIDX_PICK(group_count_kernel, variant, kSphere, , true, false),
+                               q.Q, q, w, b, gl, st, L, T);
             else
-                e = launch_ptr(SPHIDX_PICK(group_count_kernel, variant, kSphere, , false), q.Q, q, w, b,
-                               query_lds_bytes(4, q.sort_cap, w, tb), st, L, T);
+                e = launch_ptr(either ? SPHIDX_PICK(group_count_kernel, variant, kEither, , false, false)
+                                      : SPHIDX_PICK(group_count_kernel, variant, kSphere, , false, false),
+                               q.Q, q, w, b, gl, st, L, T);
             if (e == hipSuccess) e = mark(ev_end);
             if (e != hipSuccess) return e;
+            if (variant != 0 && !either) {
+                QArgs qg = ql;
+                qg.list = q.fbq;
+                qg.list_count = q.fb_count;
+                qg.list_set = kQFbCount;
+                const size_t gl0 = query_lds_bytes(q.stash ? 5 : 4, q.sort_cap, w, 0);
+                e = launch_ptr(q.stash ? (const void*)group_count_kernel<kCube, false, true, true>
+                                       : (const void*)group_count_kernel<kCube, false, false, true>,
+                               0, qg, w, b, gl0, st, L, T);
+                if (e != hipSuccess) return e;
+            }
             ql.list = q.xq;
             ql.list_count = q.xq_count;
             ql.list_set = kQExtra;
             if (q.stash)
-                e = launch_ptr(SPHIDX_PICK(count_kernel, variant, kEither, , true, true), 0, ql, w, b,
-                               query_lds_bytes(lp, q.sort_cap, w, tb), st, L, T);
-            else
-                e = launch_ptr(SPHIDX_PICK(count_kernel, variant, kEither, , true, false), 0, ql, w, b,
-                               query_lds_bytes(lp, q.sort_cap, w, tb), st, L, T);
-        } else {
-            if (q.stash)
-                e = launch_ptr(SPHIDX_PICK(count_kernel, variant, kSphere, , false, true), q.Q, q, w, b,
-                               query_lds_bytes(lp, q.sort_cap, w, tb), st, L, T);
-            else
-                e = launch_ptr(SPHIDX_PICK(count_kernel, variant, kSphere, , false, false), q.Q, q, w, b,
-                               query_lds_bytes(lp, q.sort_cap, w, tb), st, L, T);
-            if (e == hipSuccess) e = mark(ev_end);
+                return launch_ptr(SPHIDX_PICK(count_kernel, variant, kEither, , true, true), 0, ql, w, b,
+                                  query_lds_bytes(lp, q.sort_cap, w, tb), st, L, T);
+            return launch_ptr(SPHIDX_PICK(count_kernel, variant, kEither, , true, false), 0, ql, w, b,
+                              query_lds_bytes(lp, q.sort_cap, w, tb), st, L, T);
         }
-        if (e != hipSuccess || variant == 0) return e;
+        if (q.stash)
+            e = launch_ptr(either ? SPHIDX_PICK(count_kernel, variant, kEither, , false, true)
+                                  : SPHIDX_PICK(count_kernel, variant, kSphere, , false, true),
+                           q.Q, q, w, b, query_lds_bytes(lp, q.sort_cap, w, tb), st, L, T);
+        else
+            e = launch_ptr(either ? SPHIDX_PICK(count_kernel, variant, kEither, , false, false)
+                                  : SPHIDX_PICK(count_kernel, variant, kSphere, , false, false),
+                           q.Q, q, w, b, query_lds_bytes(lp, q.sort_cap, w, tb), st, L, T);
+        if (e == hipSuccess) e = mark(ev_end);
+        if (e != hipSuccess || variant == 0 || either) return e;
         ql.list = q.fbq;
         ql.list_count = q.fb_count;
         ql.list_set = kQFbCount;
@@ -1827,10 +1889,12 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
         // rows kept by a stashing count pass (does nothing otherwise)
         gather_kernel<<<(q.Q + 255) / 256, 256, 0, st>>>(q, L.status);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        e = launch_ptr(SPHIDX_PICK(write_kernel, variant, kSphere, , false), q.Q, q, w, b, sh1, st, L, T);
+        e = launch_ptr(either ? SPHIDX_PICK(write_kernel, variant, kEither, , false)
+                              : SPHIDX_PICK(write_kernel, variant, kSphere, , false),
+                       q.Q, q, w, b, sh1, st, L, T);
         if (e == hipSuccess) e = mark(ev_end);
         if (e != hipSuccess) return e;
-        if (variant != 0) {
+        if (variant != 0 && !either) {
             ql.list = q.fbq;
             ql.list_count = q.fb_count;
             ql.list_set = kQFbWrite;

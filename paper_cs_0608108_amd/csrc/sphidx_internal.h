@@ -138,6 +138,7 @@ struct QArgs {
     uint32_t weight;    // volume choice: sphere cells x weight / 256 against cube cells
     uint32_t rev;       // volume choice: radius queries below this skip the sphere
     uint32_t knn_rev;   // volume choice: K-NN queries below this take the cube
+    uint32_t model;     // volume choice: 0 = cells, 1 = estimated lane work
     uint32_t* method_out;  // optional per query row: the walk used
 };
 

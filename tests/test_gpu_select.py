@@ -149,23 +149,30 @@ def test_list_method_matches_oracle(sx, orc, mask):
         assert_same(run(sx, lat, None, 3 << F, 12, sx.MODE_KNN, queries=cen, launch=ln), ref_knn, "knn, list")
 
 
-def _choice_model(sx, tab, log2, F, mask, cen, r, k, knn_mode, n_list, weight=256, rev=0, knn_rev=0):
+def _choice_model(sx, tab, log2, F, mask, cen, r, k, knn_mode, n_list, weight=256, rev=0, knn_rev=0, model=0,
+                  n_obj=0):
     """The walk each query should take (Section III.B/C as the header states
-    it), from the exported tables, the centre, the radius and the list."""
+    it), from the exported tables, the centre, the radius and the list.
+    Model 1 counts rows (the table's cells with ox = 0 are its rows) plus the
+    mean load times the cells tested."""
     info = tab.info()
     s, rmax = info.subcell_bits, info.rmax_fx
     b = max(F - 6, 0)
     e = 1 << F
-    keys = [tab.export(c)[1] for c in range(info.nclasses)]
+    exported = [tab.export(c) for c in range(info.nclasses)]
+    keys = [kk for _, kk in exported]
+    row_keys = [kk[o[:, 0] == 0] for o, kk in exported]  # sorted: a subsequence of sorted keys
+    load = min((n_obj << 8) // (1 << sum(log2)), 1 << 24) if model else 0
     out = np.empty(len(cen[0]), dtype=np.int64)
     for i in range(len(cen[0])):
         q = [int(cen[a][i]) for a in range(3)]
         ri = int(r[i])
         knn = knn_mode or int(k[i]) > 0
-        inside, cyc_ok, ncube = True, True, 1
+        inside, cyc_ok, ncube, nn, full = True, True, 1, [], 1
         for a in range(3):
             La = 1 << log2[a]
             lo, hi = (q[a] - ri) >> F, (q[a] + ri) >> F
+            full *= min(hi - lo + 1, La) if (mask >> a) & 1 else hi - lo + 1
             if (mask >> a) & 1:
                 if La < 4 or ri > (La // 2 - 1) * e:
                     cyc_ok = False
@@ -174,21 +181,27 @@ def _choice_model(sx, tab, log2, F, mask, cen, r, k, knn_mode, n_list, weight=25
             else:
                 inside &= q[a] < (La << F)
                 lo, hi = max(lo, 0), min(hi, La - 1)
-            ncube *= max(hi - lo + 1, 0)
+            nn.append(max(hi - lo + 1, 0))
+            ncube *= nn[-1]
         sphere = inside and cyc_ok and ri <= rmax
         if knn:
             out[i] = sx.METHOD_SPHERE if sphere and ri >= knn_rev else sx.METHOD_CUBE
             continue
         sphere = sphere and ri >= rev
-        chosen = ncube
+        wc = nn[1] * nn[2] * 256 + load * ncube if model else ncube
+        chosen, tested = wc, ncube
         if sphere:
             cls = sum((((q[a] & (e - 1)) >> (F - s)) << (a * s)) for a in range(3))
             j = -(-ri // (1 << b))
             vs = int(np.searchsorted(keys[cls], (j << b) ** 2, side="right"))
-            sphere = vs * weight <= ncube * 256
+            rows = int(np.searchsorted(row_keys[cls], (j << b) ** 2, side="right"))
+            tested = vs * ncube // full
+            ws = rows * 256 + load * tested if model else vs
+            sphere = ws * weight <= wc * 256
             if sphere:
-                chosen = vs
-        if n_list < chosen:
+                chosen = ws
+        wl = n_list * 256 + load * tested if model else n_list
+        if wl < chosen:
             out[i] = sx.METHOD_LIST
         else:
             out[i] = sx.METHOD_SPHERE if sphere else sx.METHOD_CUBE
@@ -215,15 +228,18 @@ def test_auto_choice_matches_model_and_oracle(sx, orc, mask, load):
     ref = g.mixed(k, r, queries=cen)
     g.close()
     seen = set()
-    for weight, rev, knn_rev in ((0, 0, 0), (512, e, 2 * e), (64, 0, 0)):
+    for weight, rev, knn_rev, model in ((0, 0, 0, 0), (512, e, 2 * e, 0), (64, 0, 0, 0), (0, 0, 0, 1),
+                                        (320, e // 2, 0, 1)):
         mo = torch.full((Q,), -7, dtype=torch.int32, device="cuda")
         for grouped in (0, 1):
             ln = sx.LaunchConfig(method=sx.METHOD_AUTO, select_weight=weight, reversal_fx=rev,
-                                 knn_reversal_fx=knn_rev, method_out=mo, grouped=grouped)
-            say(f"auto mask={mask} load={load} weight={weight} rev={rev} knn_rev={knn_rev} grouped={grouped}")
+                                 knn_reversal_fx=knn_rev, method_out=mo, grouped=grouped, select_model=model)
+            say(f"auto mask={mask} load={load} weight={weight} rev={rev} knn_rev={knn_rev} model={model} "
+                f"grouped={grouped}")
             got = run(sx, lat, tab, r, k, sx.MODE_MIXED, queries=cen, launch=ln)
             assert_same(got, ref, "auto choice, mixed")
-            want = _choice_model(sx, tab, log2, F, mask, cen, r, k, False, n_list, weight or 256, rev, knn_rev)
+            want = _choice_model(sx, tab, log2, F, mask, cen, r, k, False, n_list, weight or 256, rev, knn_rev,
+                                 model, n)
             used = mo.cpu().numpy().astype(np.int64)
             bad = np.nonzero(used != want)[0]
             assert len(bad) == 0, (f"choice differs at {bad[:5]}: used {used[bad[:5]]} model {want[bad[:5]]} "

@@ -194,6 +194,43 @@ def test_query_validation_paths(sx):
     lib.sphidx_lattice_destroy(lat)
 
 
+def test_method_choice_and_cell_list_validation(sx):
+    """METHOD_AUTO needs tables, METHOD_LIST an attached cell list; the list
+    buffer is checked for size and alignment before anything is enqueued."""
+    lib = sx.load()
+    lat = _fake_lattice(sx, maxp=1000)
+    assert lib.sphidx_cell_list_bytes(lat) == 16 + (1000 + 1) * 8
+    assert lib.sphidx_cell_list_bytes(None) == 0
+    small = _fake_lattice(sx, log2=(2, 2, 2), maxp=1000)  # 64 cells: the list holds at most 64
+    assert lib.sphidx_cell_list_bytes(small) == 16 + (64 + 1) * 8
+    need = lib.sphidx_cell_list_bytes(lat)
+    st = ctypes.c_void_p()
+    assert lib.sphidx_lattice_attach_cell_list(None, ctypes.c_void_p(1 << 24), need, st) == sx.ERR_INVALID_ARG
+    assert lib.sphidx_lattice_attach_cell_list(lat, ctypes.c_void_p((1 << 24) + 8), need, st) == sx.ERR_INVALID_ARG
+    assert lib.sphidx_lattice_attach_cell_list(lat, ctypes.c_void_p(1 << 24), need - 1, st) == sx.ERR_CAPACITY
+    assert lib.sphidx_lattice_attach_cell_list(lat, None, 0, st) == sx.OK  # detach: nothing kept
+    q = sx.Queries()
+    q.count = 10
+    q.x_dev = q.y_dev = q.z_dev = 1 << 20
+    cs = sx.CSRDesc()
+    cs.row_ptr_dev = 1 << 21
+    cs.workspace_dev = 1 << 22
+    cs.workspace_bytes = lib.sphidx_query_workspace_bytes(10)
+    ln = sx.LaunchDesc()
+    args = lambda tab: (lat, tab, ctypes.byref(q), ctypes.byref(cs), ctypes.byref(ln), st)  # noqa: E731
+    ln.method = sx.METHOD_LIST  # no list attached
+    assert lib.sphidx_count(*args(None)) == sx.ERR_INVALID_ARG
+    ln.method = sx.METHOD_AUTO  # no tables
+    assert lib.sphidx_count(*args(None)) == sx.ERR_INVALID_ARG
+    ln.method = 4
+    assert lib.sphidx_count(*args(None)) == sx.ERR_INVALID_ARG
+    ln.method = sx.METHOD_CUBE
+    ln.select_weight = (1 << 16) + 1
+    assert lib.sphidx_count(*args(None)) == sx.ERR_INVALID_ARG
+    lib.sphidx_lattice_destroy(lat)
+    lib.sphidx_lattice_destroy(small)
+
+
 def test_build_validation(sx):
     lib = sx.load()
     lat = _fake_lattice(sx, maxp=100)
