@@ -31,7 +31,11 @@
 // wavefront, so that short rows and small radii fill whole steps.  Queries
 // whose radius exceeds the tables' cap or the cyclic limit, or whose centre
 // is outside the region, and every query of the cube method, scan the
-// bin-lattice bounding cube instead (Section I; Section III.B).
+// bin-lattice bounding cube instead (Section I; Section III.B).  With the
+// per-query choice each query takes the sphere, the cube or the lattice's
+// non-empty cell list, whichever the comparison of their cells (Section
+// III.B, III.C) or of their estimated work finds smallest; a list entry is
+// one more kind of row.
 #include "sphidx_internal.h"
 
 namespace {
