@@ -45,7 +45,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "all-agents neighbor queries/sec and HBM GB/s at 1 GPU; p99 latency vs plain launch"
 HBM_PEAK_GBS = 8000.0
-LEGS = ("c2", "knn", "timestep", "serving", "sweep")
+LEGS = ("c2", "knn", "timestep", "serving", "sweep", "tables")
 DEFAULT_LEGS = ("c2", "knn", "timestep", "serving")
 
 
@@ -618,6 +618,44 @@ def leg_sweep(args, out):
         "all_points_identical": mismatches == 0, "points": rows}
 
 
+# ---------------------------------------------------------------------------
+# Table designs compared (host only, no GPU)
+
+def leg_tables(args, out):
+    """Cells walked per query under each table design (Section II.A, III.A)
+    for random positions in the home cell, by radius, and the ball/cube ratio
+    of the sub-cell tables in 2, 3 and 4 dimensions (Sections I and V)."""
+    import numpy as np
+
+    from paper_cs_0608108_amd import sphidx
+
+    F = 16
+    e = 1 << F
+    tab = sphidx.Tables(sphidx.desc_of((8, 8, 8), F, 7), 2, 16 * e)
+    rng = np.random.default_rng(31)
+    rows = []
+    for rc in (0.5, 1.0, 2.0, 4.0, 8.0, 16.0):
+        n = 4000
+        f = [rng.integers(0, e, n).astype(np.uint32) for _ in range(3)]
+        r = np.full(n, int(rc * e), dtype=np.uint32)
+        c = sphidx.table_census(tab, f, r)
+        row = {"r_cells": rc, "queries": n}
+        row.update({k: round(float(v.mean()), 1) for k, v in c.items()})
+        rows.append(row)
+        log(f"tables r={rc}: " + " ".join(f"{k} {row[k]}" for k in sphidx.CENSUS_FIELDS))
+    nd = []
+    for dims in (2, 3, 4):
+        for rc in (4, 8, 16):
+            sph, cube, _ = sphidx.table_census_nd(dims, 8, 1, rc << 8)
+            nd.append({"dims": dims, "r_cells": rc, "sphere_cells": round(sph, 1), "cube_cells": round(cube, 1),
+                       "ratio": round(sph / cube, 4)})
+    out["table_census"] = {
+        "designs": "cells walked per query: bin-lattice cube, unshaved table, the paper's 64 specialised tables, "
+                   "those after the Eq. 1 run-time test, this library's sub-cell class tables (s = 2), exact; "
+                   "dropped = exact cells a design leaves out (must be 0)",
+        "by_radius": rows, "ball_to_cube": nd}
+
+
 def copy_calibration(nbytes):
     import torch
     src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
@@ -654,11 +692,12 @@ def main():
         sys.exit(2)
 
     import torch
-    torch.cuda.set_device(0)
+    legs = [x for x in args.legs.split(",") if x]
+    if legs != ["tables"] or args.copy_bytes:
+        torch.cuda.set_device(0)
     if args.copy_bytes:
         copy_calibration(args.copy_bytes)
         return
-    legs = [x for x in args.legs.split(",") if x]
     for x in legs:
         if x not in LEGS:
             sys.exit(f"unknown leg {x}")
@@ -668,7 +707,7 @@ def main():
     for x in legs:
         log(f"== leg {x}")
         {"c2": leg_c2, "knn": leg_knn, "timestep": leg_timestep, "serving": leg_serving,
-         "sweep": leg_sweep}[x](args, out)
+         "sweep": leg_sweep, "tables": leg_tables}[x](args, out)
     print(json.dumps(out))
 
 

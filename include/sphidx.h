@@ -164,6 +164,42 @@ sphidx_status sphidx_tables_export(const sphidx_tables* tab, uint32_t cls, int32
 sphidx_status sphidx_tables_save(const sphidx_tables* tab, const char* path);
 sphidx_status sphidx_tables_load(const char* path, sphidx_tables** out);
 
+/* Table designs compared (host only; Section II.A, III.A).  For nq query
+ * positions inside the home cell (fx, fy, fz < 2^F, host arrays) and radii
+ * r <= the tables' cap (and <= 31 cells), out_host[7*i + k] (uint64) counts
+ * the cells query i walks under each design:
+ *   0 the bin-lattice bounding cube (exact to the sub-cell);
+ *   1 the unshaved table: entries b^2 = sum max(|o|-1, 0)^2 <= floor(d^2),
+ *     d = r / 2^F;
+ *   2 the paper's 64 specialised tables: the unshaved entries below floor(d)^2,
+ *     then, up to floor(d^2), the table chosen by the six bits
+ *     [frac(d) < zeta] (zeta = 2^F - f up, f down), which leaves out each cell
+ *     with an axis at b_o = floor(b) in a flagged direction (the one-direction
+ *     rule) or moving along some axis with all its directions flagged (Eq. 2);
+ *   3 those left after the run-time test of Eq. 1 on the cells at or above
+ *     d - 1;
+ *   4 the prefix key <= r^2 of `tab`'s sub-cell class (this library's tables);
+ *   5 the exact set: cells holding an integer position within r;
+ *   6 exact cells that design 3 leaves out (always 0: the paper's tests are
+ *     conservative for integer positions).
+ * RADIUS when a radius exceeds those limits. */
+sphidx_status sphidx_table_census(const sphidx_tables* tab, uint32_t nq, const uint32_t* fx_host,
+                                  const uint32_t* fy_host, const uint32_t* fz_host, const uint32_t* r_host,
+                                  uint64_t* out_host);
+
+/* The sub-cell class tables in `dims` = 2, 3 or 4 dimensions (Section I: the
+ * method generalises; Section V: more dimensions): over the 2^(dims*s) classes
+ * of s sub-cell bits per axis, the mean number of cells whose key (the
+ * smallest squared distance from the class box, integer positions) is <= r^2
+ * (*sphere_cells) and of the bounding box exact to the class (*cube_cells).
+ * Their ratio tends to the ball/cube volume ratio (pi/4, pi/6, pi^2/32).
+ * With hist_len > 0, unshaved_hist[k] (k < hist_len) receives the number of
+ * cells of the unshaved table (Section II.A) with entry b^2 = k.  RADIUS when
+ * the enumeration would exceed 2^34 cell visits. */
+sphidx_status sphidx_table_census_nd(uint32_t dims, uint32_t frac_bits, uint32_t subcell_bits, uint32_t r_fx,
+                                     double* sphere_cells, double* cube_cells, uint64_t* unshaved_hist,
+                                     uint32_t hist_len);
+
 /* ---------------------------------------------------------------------- */
 /* Queries.                                                                */
 

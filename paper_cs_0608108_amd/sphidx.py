@@ -75,6 +75,9 @@ SIGNATURES = {
     "sphidx_tables_export": (ctypes.c_int, [P, U32, P, P, ctypes.POINTER(U64)]),
     "sphidx_tables_save": (ctypes.c_int, [P, ctypes.c_char_p]),
     "sphidx_tables_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(P)]),
+    "sphidx_table_census": (ctypes.c_int, [P, U32, P, P, P, P, P]),
+    "sphidx_table_census_nd": (ctypes.c_int, [U32, U32, U32, U32, ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_double), P, U32]),
     "sphidx_query_workspace_bytes": (SZ, [U32]),
     "sphidx_query_stash_bytes": (SZ, [ctypes.c_uint64, ctypes.c_int]),
     "sphidx_count": (ctypes.c_int, [P, P, ctypes.POINTER(Queries), ctypes.POINTER(CSRDesc),
@@ -285,6 +288,31 @@ class Tables:
         check(load().sphidx_tables_export(self.handle, int(cls), ctypes.c_void_p(offs.ctypes.data),
                                           ctypes.c_void_p(keys.ctypes.data), ctypes.byref(n)))
         return offs, keys
+
+
+CENSUS_FIELDS = ("cube", "unshaved", "paper64", "paper64_eq1", "subcell", "exact", "dropped")
+
+
+def table_census(tab, f, r):
+    """Cells walked per table design (host only): f = (fx, fy, fz) positions
+    inside the home cell, r radii; returns {design: uint64[n]}."""
+    f = [np.ascontiguousarray(a, dtype=np.uint32) for a in f]
+    r = np.ascontiguousarray(r, dtype=np.uint32)
+    out = np.zeros((len(r), 7), dtype=np.uint64)
+    check(load().sphidx_table_census(tab.handle, len(r), *(ctypes.c_void_p(a.ctypes.data) for a in f),
+                                     ctypes.c_void_p(r.ctypes.data), ctypes.c_void_p(out.ctypes.data)),
+          "table_census")
+    return {k: out[:, i] for i, k in enumerate(CENSUS_FIELDS)}
+
+
+def table_census_nd(dims, frac_bits, subcell_bits, r_fx, hist_len=0):
+    """(mean sphere cells, mean bounding-box cells, unshaved b^2 histogram)."""
+    s, c = ctypes.c_double(), ctypes.c_double()
+    hist = np.zeros(max(hist_len, 1), dtype=np.uint64)
+    check(load().sphidx_table_census_nd(int(dims), int(frac_bits), int(subcell_bits), int(r_fx), ctypes.byref(s),
+                                        ctypes.byref(c), ctypes.c_void_p(hist.ctypes.data), int(hist_len)),
+          "table_census_nd")
+    return s.value, c.value, hist[:hist_len]
 
 
 @dataclass
