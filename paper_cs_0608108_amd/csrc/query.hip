@@ -1686,13 +1686,17 @@ __global__ void clear_counters_kernel(uint32_t* c, uint32_t begin, uint32_t end,
     }
 }
 
-// Write pass after a stashing count pass: copy every kept row from the stash
-// to its place in the output.  A wave takes 64 consecutive queries; their
-// rows' elements are spread over the lanes (prefix sum + owner map, as for
-// candidates), 64 per step.  If the caller now asks for dist^2 and the stash
-// holds none, the row is put on the walk list instead.
-__global__ __launch_bounds__(256) void gather_kernel(QArgs A, uint32_t* status) {
-    __shared__ uint32_t own_all[4 * 64];
+// Pass 1 with the stash: copy each kept row into place.  A wavefront takes 64
+// queries; one lane reads each query's stash offset, output row and length.
+// Their objects are numbered in query order (a prefix sum), and each lane
+// copies every 64th of them: its query is the last whose first number is at
+// most the object's, found by a binary search over the starts kept in LDS
+// (read-only, so steps need no barrier and four are in flight).  Consecutive
+// queries' stash rows are mostly adjacent, so the loads are one stream.  Rows
+// the count pass could not keep are left to the write kernel (offset ~0), as
+// are rows whose dist^2 the stash lacks.
+__global__ __launch_bounds__(256) void gather_kernel(QArgs A, const uint4* pts, uint32_t* status) {
+    __shared__ uint32_t starts_all[4 * 64];
     const uint32_t* hdr = A.stash_hdr;
     if (hdr[kHdrMode] == 0u) return;
     if (A.row_ptr[A.Q] > A.capacity) {
@@ -1700,7 +1704,7 @@ __global__ __launch_bounds__(256) void gather_kernel(QArgs A, uint32_t* status) 
         return;
     }
     const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
-    uint32_t* own = own_all + wave * 64;
+    uint32_t* starts = starts_all + wave * 64;
     const uint64_t q0 = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + wave) * 64u;
     if (q0 >= A.Q) return;
     const uint32_t* s_ids = (const uint32_t*)A.stash_base;
@@ -1712,7 +1716,9 @@ __global__ __launch_bounds__(256) void gather_kernel(QArgs A, uint32_t* status) 
     if (qi < A.Q) {
         src = A.soff[qi];
         if (src != kMaxId) {
-            const uint32_t row = A.desc[4 * qi].w;
+            // the output row: the object's id for all-agents queries (their
+            // processing order is the sorted order), else the query index
+            const uint32_t row = A.qx == nullptr ? pts[qi].w : (uint32_t)qi;
             dst = A.row_ptr[row];
             len = (uint32_t)(A.row_ptr[row + 1] - dst);
             if (len > 0 && A.out_d2 && !has_d2) {
@@ -1724,25 +1730,41 @@ __global__ __launch_bounds__(256) void gather_kernel(QArgs A, uint32_t* status) 
     const uint32_t incl = scan_add(len);
     const uint32_t total = lane_val(incl, 63);
     const uint32_t excl = incl - len;
-    // per owner: element g of the group maps to src + (g - excl), dst + (g - excl)
+    starts[lane] = excl;
+    wave_sync();
+    // object g of query o is at stash sbase[o] + g and output dbase[o] + g
     const uint32_t sbase = src - excl;
-    const int64_t dbase = dst - (int64_t)excl;
-    for (uint32_t cb = 0; cb < total; cb += 64) {
-        own[lane] = 0;
-        wave_sync();
-        if (len > 0 && excl < cb + 64 && incl > cb) own[excl > cb ? excl - cb : 0] = lane + 1;
-        wave_sync();
-        const uint32_t o = scan_max(own[lane]) - 1u;
-        const uint32_t g = cb + lane;
-        const uint32_t sp = bperm(sbase, o) + g;
-        const uint64_t db = ((uint64_t)bperm((uint32_t)((uint64_t)dbase >> 32), o) << 32) |
-                            bperm((uint32_t)(uint64_t)dbase, o);
-        if (g < total) {
-            const int64_t dp = (int64_t)db + (int64_t)g;
-            A.out_ids[dp] = s_ids[sp];
-            if (A.out_d2) A.out_d2[dp] = s_d2[sp];
+    const uint64_t dbase = (uint64_t)(dst - (int64_t)excl);
+    const bool want_d2 = A.out_d2 != nullptr;
+    constexpr uint32_t kSteps = 4;
+    for (uint32_t cb = 0; cb < total; cb += 64u * kSteps) {
+        uint32_t v[kSteps];
+        int64_t w[kSteps], dp[kSteps];
+#pragma unroll
+        for (uint32_t k = 0; k < kSteps; ++k) {
+            const uint32_t g = cb + 64u * k + lane;
+            // the last query whose first object number is <= g (a query with
+            // an empty row shares its start with the next, which wins)
+            uint32_t o = 0;
+#pragma unroll
+            for (uint32_t step = 32; step; step >>= 1)
+                if (starts[o + step] <= g) o += step;
+            const uint32_t sp = bperm(sbase, o) + g;
+            dp[k] = (int64_t)(((uint64_t)bperm((uint32_t)(dbase >> 32), o) << 32) | bperm((uint32_t)dbase, o)) + g;
+            v[k] = 0u;
+            w[k] = 0;
+            if (g < total) {
+                v[k] = s_ids[sp];
+                if (want_d2) w[k] = s_d2[sp];
+            }
         }
-        wave_sync();
+#pragma unroll
+        for (uint32_t k = 0; k < kSteps; ++k) {
+            if (cb + 64u * k + lane < total) {
+                A.out_ids[dp[k]] = v[k];
+                if (want_d2) A.out_d2[dp[k]] = w[k];
+            }
+        }
     }
 }
 
@@ -1891,7 +1913,7 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
     if (q.mode != SPHIDX_MODE_KNN) {
         if ((e = mark(ev_begin)) != hipSuccess) return e;
         // rows kept by a stashing count pass (does nothing otherwise)
-        gather_kernel<<<(q.Q + 255) / 256, 256, 0, st>>>(q, L.status);
+        gather_kernel<<<(q.Q + 255) / 256, 256, 0, st>>>(q, L.pts, L.status);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         e = launch_ptr(either ? SPHIDX_PICK(write_kernel, variant, kEither, , false)
                               : SPHIDX_PICK(write_kernel, variant, kSphere, , false),
