@@ -269,3 +269,29 @@ def test_auto_all_agents_with_stash(sx, orc):
         say(f"auto all agents grouped={ln.grouped} rev={ln.reversal_fx}")
         assert_same(sx.run(lat, tab, q, ln, stash=True), ref, "auto, all agents, stash")
     del rd
+
+
+@pytest.mark.parametrize("log2,mask", [((1, 1, 2), 7), ((1, 2, 3), 5), ((2, 1, 1), 3)])
+def test_list_walk_on_tiny_wrapping_axes(sx, orc, log2, mask):
+    """Axes of two and four cells, radii past the whole world: the list walk's
+    nearest image (both images equally far at half the axis) and the choice
+    between cube and list where no table applies, against brute force."""
+    rng = np.random.default_rng(90 + sum(log2) + mask)
+    F = 8
+    pts = tiny_points(rng, log2, F, mask, 600, outside=(mask != 7))
+    lat = lattice(sx, log2, F, mask, pts)
+    tab = sx.Tables(lat, 2, 3 << F)
+    L = orc.Lattice(log2, F, mask)
+    r = rng.integers(0, 6 << F, len(pts[0])).astype(np.uint32)
+    ref = orc.radius_brute(L, pts, r)
+    for name, ln in (("list", sx.LaunchConfig(method=sx.METHOD_LIST)),
+                     ("auto", sx.LaunchConfig(method=sx.METHOD_AUTO)),
+                     ("auto-work", sx.LaunchConfig(method=sx.METHOD_AUTO, select_model=1, grouped=1))):
+        say(f"tiny world {log2} mask={mask} {name}")
+        assert_same(run(sx, lat, tab, r, launch=ln), ref, f"tiny {name}")
+    cen = _centres(rng, log2, F, mask, 300)
+    k = rng.integers(1, 12, 300).astype(np.uint32)
+    rq = rng.integers(0, 6 << F, 300).astype(np.uint32)
+    refk = orc.knn_brute(L, pts, k, rq, queries=cen)
+    assert_same(run(sx, lat, tab, rq, k, sx.MODE_KNN, queries=cen, launch=sx.LaunchConfig(method=sx.METHOD_LIST)),
+                refk, "tiny knn list")
