@@ -214,10 +214,12 @@ def leg_c2(args, out):
     # algorithmic bytes = point records 16 B/pt + cell_start 4 B/cell +
     # descriptors 64 B/query + row size 8 B/query + stash offset 4 B/query +
     # stashed ids 4 B/pair, over its own event-timed duration on the launch
-    # stream.  The write pass only copies the rows (4 B/pair in and out).
+    # stream.  The write pass only copies the rows: stash offset 4 B/query,
+    # point record 16 B/query (the row's id), row_ptr 16 B/query (two entries
+    # of a random row) and 4 B/pair in and out.
     ncells = lat.ncells
     count_bytes = 16 * n + 4 * (ncells + 2) + 64 * n + 8 * n + 4 * n + 4 * total
-    gather_bytes = 4 * n + 4 * n + 16 * n + 4 * total + 4 * total
+    gather_bytes = 4 * n + 16 * n + 16 * n + 4 * total + 4 * total
     achieved = count_bytes / (kern[0] * 1e-3) / 1e9
     traffic = _stored_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
