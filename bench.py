@@ -277,7 +277,7 @@ def leg_knn(args, out):
     import numpy as np
     import torch
 
-    from paper_cs_0608108_amd import sphidx, synth
+    from paper_cs_0608108_amd import autotune, sphidx, synth
 
     w = synth.knn_clustered()
     n, K = w.n, int(w.k[0])
@@ -289,11 +289,26 @@ def leg_knn(args, out):
     lat.build(*dev)
     q = sphidx.make_queries(n, None, cap, K, sphidx.MODE_KNN, 0)
     buf = sphidx.QueryBuffers(n, n * K, want_dist2=False)
-    ln = sphidx.LaunchConfig()
 
-    def step():
-        lat.build(*dev)
-        sphidx.query(lat, tab, q, buf, ln)
+    def step_with(launch):
+        def run():
+            lat.build(*dev)
+            sphidx.query(lat, tab, q, buf, launch)
+        return run
+
+    # the tuned launch for this workload (K-NN rows take neither the grouped
+    # count nor the interior shortcut, so those fields do not matter)
+    shape = dict(workload=w.name, n=n, k=K)
+    if args.no_tune:
+        cache = autotune.load_cache()
+        ver = autotune.kernel_version()
+        cfg = next((v["config"] for k, v in cache.items() if ver in k and f"workload={w.name}" in k
+                    and "method=0" in k and "schedule=1" in k), {})
+    else:
+        cfg = autotune.tune(shape, step_with, log=log)
+    ln = sphidx.LaunchConfig(**cfg)
+    log(f"knn launch config: {cfg}")
+    step = step_with(ln)
 
     for _ in range(2):
         step()
@@ -315,7 +330,7 @@ def leg_knn(args, out):
     bs = sphidx.QueryBuffers(len(rows), len(rows) * K, want_dist2=False)
     sub = {}
     for name, meth in (("sphere", sphidx.METHOD_SPHERE), ("cube", sphidx.METHOD_CUBE)):
-        lq = sphidx.LaunchConfig(method=meth)
+        lq = sphidx.LaunchConfig(method=meth, **cfg)
         sphidx.query(lat, tab, qs, bs, lq)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -338,6 +353,7 @@ def leg_knn(args, out):
     log(f"knn subsample {len(rows)}: sphere {sub['sphere']:.3f} ms, cube {sub['cube']:.3f} ms, "
         f"same {same_sub}, oracle rows bit-exact {exact}")
     out["knn"] = {"workload": w.name, "ms_per_step": round(ms, 4), "queries_per_s": round(n / (ms * 1e-3), 1),
+                  "launch": dict(cfg, schedule="persistent"),
                   "step": "rebuild + K-NN query (top-K rows, sorted by (dist2, id))",
                   "subsample": {"queries": int(len(rows)), "sphere_ms": round(sub["sphere"], 4),
                                 "cube_ms": round(sub["cube"], 4),
