@@ -288,7 +288,9 @@ def leg_knn(args, out):
     tab = sphidx.Tables(lat, 2, cap)
     lat.build(*dev)
     q = sphidx.make_queries(n, None, cap, K, sphidx.MODE_KNN, 0)
-    buf = sphidx.QueryBuffers(n, n * K, want_dist2=False)
+    # rows are at most K long: with stash room for all of them the count pass
+    # searches each row once and keeps it, and the write pass only copies
+    buf = sphidx.QueryBuffers(n, n * K, want_dist2=False, stash_pairs=n * K)
 
     def step_with(launch):
         def run():
@@ -327,7 +329,7 @@ def leg_knn(args, out):
     rows = sample_of(n, 65536, 3)
     cen = tuple(sphidx.to_dev_u32(np.asarray(a)[rows]) for a in w.pts)
     qs = sphidx.make_queries(len(rows), cen, cap, K, sphidx.MODE_KNN, 0)
-    bs = sphidx.QueryBuffers(len(rows), len(rows) * K, want_dist2=False)
+    bs = sphidx.QueryBuffers(len(rows), len(rows) * K, want_dist2=False, stash_pairs=len(rows) * K)
     sub = {}
     for name, meth in (("sphere", sphidx.METHOD_SPHERE), ("cube", sphidx.METHOD_CUBE)):
         lq = sphidx.LaunchConfig(method=meth, **cfg)

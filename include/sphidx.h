@@ -232,8 +232,9 @@ typedef struct {
 } sphidx_csr;
 
 /* The stash.  Workspace bytes beyond the minimum let the count pass keep
- * each radius row of at most sort_cap objects, already sorted, so that the
- * write pass copies it into place instead of walking the tables again.  A
+ * each radius row of at most sort_cap objects, and each K-NN row of K <= 64
+ * (searched there to the end), already sorted, so that the write pass copies
+ * it into place instead of walking the tables again.  A
  * row needs 4 bytes per object (12 when the count call passes dist2_dev).
  * Rows that do not fit are walked again by the write pass, so any size is
  * correct; sphidx_query_stash_bytes gives the size that keeps every row.

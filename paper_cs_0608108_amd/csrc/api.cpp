@@ -232,11 +232,11 @@ QArgs q_args(const sphidx_queries* q, sphidx_csr* csr, const Launch& ln) {
 // Count pass: size the stash from the bytes beyond the minimum workspace.
 // Rows are kept as ids (plus dist^2 when this call asks for them) in
 // NQUEUE regions, one per XCD, handed out to waves in chunks.
-void plan_stash(QArgs& A, const sphidx_csr* csr, const Launch& ln, uint32_t mode, bool interior_forced) {
+void plan_stash(QArgs& A, const sphidx_csr* csr, const Launch& ln, bool interior_forced) {
     A.stash = 0;
     // plain launches: a wave lives for `tile` queries only, too short to
     // fill a chunk of its own
-    if (ln.no_stash || !ln.persistent || interior_forced || mode == SPHIDX_MODE_KNN) return;
+    if (ln.no_stash || !ln.persistent || interior_forced) return;
     const size_t base = query_layout(A.Q).total;
     if (csr->workspace_bytes <= base + 4096) return;
     const size_t room = csr->workspace_bytes - base - 512;  // alignment slack
@@ -287,7 +287,7 @@ sphidx_status run_pass(int pass, const sphidx_lattice* lat, const sphidx_tables*
     TabArgs T = tab_args(tables ? tab : nullptr);
     T.lds = ln.tab_lds;
     QArgs A = q_args(q, csr, ln);
-    if (pass == 0) plan_stash(A, csr, ln, q->mode, ln.interior == 2);
+    if (pass == 0) plan_stash(A, csr, ln, ln.interior == 2);
     // counting wholly-inside cells whole saves object reads but costs a
     // second extent per row: worth it once cells hold an object or more
     // (not with the stash, which needs every object of a row)

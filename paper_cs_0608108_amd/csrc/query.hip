@@ -880,6 +880,116 @@ __device__ void bucket_sort_store(const uint64_t* td, const uint32_t* ti, uint64
 }
 
 // ---------------------------------------------------------------------------
+// Top-M searches in registers
+
+// First bound of a top-M search: the radius expected to hold `target`
+// objects (K-NN rows: the density around the centre, the home cell's count
+// with the lattice mean as a floor; radius rows of `rowlen`: the row's own
+// mean density over its ball), never above the cap; the whole cap for the
+// bounding cube and the cell list, which are scanned whole anyway.  A search
+// grows it and starts again whenever fewer than M lie within it.
+__device__ __forceinline__ uint64_t first_bound(const LatArgs& L, const Query& s, uint32_t target, uint32_t rowlen) {
+    if (!(s.flags & F_SPHERE)) return s.r2;
+    const float e = (float)(1u << L.F);
+    float rho;
+    if (s.flags & F_KNN) {
+        const uint32_t home = pack_cell(L, s.c[0], s.c[1], s.c[2]);
+        const float dens = fmaxf((float)L.n / (float)(L.ncells ? L.ncells : 1u), (float)(L.cs[home + 1] - L.cs[home]));
+        rho = 1.25f * e * cbrtf(0.2387f * (float)target / fmaxf(dens, 1e-6f));
+    } else {
+        rho = 1.1f * (float)s.r * cbrtf((float)target / (float)rowlen);
+    }
+    return rho >= (float)s.r ? s.r2 : min(s.r2, (uint64_t)((double)rho * (double)rho));
+}
+
+// The M <= 64 nearest pairs (dist^2, id) of query s above the pair (ld, li)
+// when has_lower, within the cap: lane i ends with the i-th in (rd, ri), and
+// the count found, min(M, pairs within the cap), is returned.  The bound
+// starts at B, shrinks to the M-th distance once M are held (Section II.A,
+// K nearest) and, when fewer than M lie within it, grows by half and the
+// walk starts again.  A few new pairs are inserted one by one (place = pairs
+// ahead of it, the rest move up one lane); a large batch is sorted and
+// merged (the 64 smallest of list and batch, as a bitonic sequence, then
+// sorted).
+template <int METHOD, bool TLDS>
+__device__ __forceinline__ uint32_t topm_registers(const LatArgs& L, const TabArgs& T, const uint32_t* tab_lds,
+                                                   const Query& s, const AxisWrap& aw, uint32_t* own, uint32_t M,
+                                                   uint64_t B, bool has_lower, uint64_t ld, uint32_t li, uint64_t& rd,
+                                                   uint32_t& ri) {
+    const uint32_t lane = lane_id();
+    rd = kMaxD2;
+    ri = kMaxId;
+    uint64_t kd = kMaxD2;
+    uint32_t kid = kMaxId, held = 0, cand2 = 0, walked2 = 0;
+    auto visit_r = [&](bool act, uint32_t p, const uint4& P) -> bool {
+        const uint64_t d2 = obj_dist2(aw, s, P);
+        const uint32_t id = P.w;
+        bool cv = act && d2 <= B && p != s.self;
+        if (cv && has_lower) cv = key_less(ld, li, d2, id);
+        if (cv && held >= M) cv = key_less(d2, id, kd, kid);
+        uint64_t qm = __ballot(cv);
+        if (qm == 0) return false;
+        const uint32_t nb = (uint32_t)__popcll(qm);
+        if (nb > 6) {
+            uint64_t cd = cv ? d2 : kMaxD2;
+            uint32_t ci = cv ? id : kMaxId;
+            wave_sort64(cd, ci);
+            const uint64_t xd = shfl64(cd, 63u - lane);
+            const uint32_t xi = __shfl(ci, 63u - lane);
+            if (key_less(xd, xi, rd, ri)) {
+                rd = xd;
+                ri = xi;
+            }
+            wave_bitonic_clean64(rd, ri);
+            held = min(held + nb, 64u);
+        } else {
+            while (qm) {
+                const uint32_t j = (uint32_t)__builtin_ctzll(qm);
+                qm &= qm - 1ull;
+                const uint64_t nd = lane_val64(d2, j);
+                const uint32_t ni = lane_val(id, j);
+                if (held >= M && !key_less(nd, ni, kd, kid)) continue;
+                const uint32_t pos = (uint32_t)__popcll(__ballot(key_less(rd, ri, nd, ni)));
+                const uint32_t below = lane ? lane - 1u : 0u;
+                const uint64_t sd = shfl64(rd, below);
+                const uint32_t si = __shfl(ri, below);
+                if (lane > pos) {
+                    rd = sd;
+                    ri = si;
+                } else if (lane == pos) {
+                    rd = nd;
+                    ri = ni;
+                }
+                held = min(held + 1u, 64u);
+                if (held >= M) {
+                    kd = lane_val64(rd, M - 1u);
+                    kid = lane_val(ri, M - 1u);
+                }
+            }
+        }
+        if (held >= M) {
+            kd = lane_val64(rd, M - 1u);
+            kid = lane_val(ri, M - 1u);
+        }
+        return false;
+    };
+    for (;;) {
+        walk<METHOD, TLDS, true>(L, T, tab_lds, s, false, walked2, [&]() { return held >= M ? kd : B; },
+                                 [&](const RowRef& r) -> bool {
+            return for_candidates(L, r.st0, r.cnt0, r.st1, r.cnt1, own, cand2, visit_r);
+        });
+        if (held >= M || B >= s.r2) break;
+        B = min(s.r2, B + B + (B >> 2) + 1u);  // radius x1.5
+        held = 0;
+        rd = kMaxD2;
+        ri = kMaxId;
+        kd = kMaxD2;
+        kid = kMaxId;
+    }
+    return min(held, M);
+}
+
+// ---------------------------------------------------------------------------
 // Pass 0: row sizes
 
 // Queue sets of the work counters.
@@ -931,8 +1041,10 @@ __device__ __forceinline__ void sort_row_store(const uint64_t* td, const uint32_
 // FROM_LIST: a query list (the sphere method's fallback queries, scanned with
 // the bounding cube).  STASH: radius rows of at most sort_cap hits are also
 // collected, sorted and kept in the workspace's stash, so that the write pass
-// only copies them into place; other rows go to the walk list.
-template <int METHOD, bool TLDS, bool FROM_LIST, bool STASH>
+// only copies them into place; other rows go to the walk list.  KSTASH (with
+// STASH): K-NN rows of K <= 64 are searched here, top-K in registers, and
+// kept the same way, so that no later pass walks them again.
+template <int METHOD, bool TLDS, bool FROM_LIST, bool STASH, bool KSTASH>
 __global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs A) {
     extern __shared__ __align__(16) char smem[];
     const uint32_t* tab_lds = stage_table<TLDS>(T, smem);
@@ -954,11 +1066,52 @@ __global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs 
     uint32_t cur = 0, lim = 0;
     bool dry = false;
     const uint32_t idbits = L.n > 1 ? 32u - (uint32_t)__builtin_clz(L.n - 1u) : 0u;  // ids are below n
+    // room for n more stash elements in this wave's chunk, grabbing a new
+    // chunk of the region when needed; false once the region is used up
+    auto stash_room = [&](uint32_t n) -> bool {
+        if (cur + n <= lim) return true;
+        if (dry) return false;
+        const uint32_t grab = max(A.stash_chunk, n);
+        uint32_t t = 0;
+        if (lane == 0) t = atomicAdd(A.stash_ctr + region * SPHIDX_QSTRIDE, grab);
+        t = uni(t);
+        if ((uint64_t)t + grab <= A.stash_region) {
+            cur = region * A.stash_region + t;
+            lim = cur + grab;
+            return true;
+        }
+        dry = true;
+        return false;
+    };
     for_each_query(nq, A, queue_set(A, FROM_LIST ? (int)A.list_set : kQCount), [&](uint32_t ti_) {
         const uint32_t qi = FROM_LIST ? uni(A.list[ti_]) : ti_;
         const Query s = load_query(L, A, qi);
         if (METHOD == kSphere && (s.flags & F_VALID) && !(s.flags & F_SPHERE)) return;  // fallback list
         const bool knn = s.flags & F_KNN;
+        if (KSTASH && knn && (s.flags & F_VALID) && s.k <= 64u) {
+            // the row itself: lane i ends with the i-th nearest
+            uint64_t rd;
+            uint32_t ri;
+            const uint32_t got = topm_registers<METHOD, TLDS>(L, T, tab_lds, s, aw, own, s.k,
+                                                               first_bound(L, s, s.k, 0u), false, 0ull, 0u, rd, ri);
+            if (lane == 0) A.row_ptr[s.row] = (int64_t)got;
+            uint32_t off = 0u;  // empty rows: nothing to copy
+            if (got > 0) {
+                if (stash_room(got)) {
+                    if (lane < got) {
+                        A.stash_ids[cur + lane] = ri;
+                        if (A.stash_d2) A.stash_d2[cur + lane] = (int64_t)rd;
+                    }
+                    off = cur;
+                    cur += got;
+                } else {
+                    off = kMaxId;
+                    if (lane == 0) A.walkq[atomicAdd(A.walk_count, 1u)] = qi;
+                }
+            }
+            if (lane == 0) A.soff[qi] = off;
+            return;
+        }
         uint32_t hits = 0, inner = 0, kept = 0, cand = 0, walked = 0;
         bool self_inner = false;
         auto visit = [&](bool act, uint32_t p, const uint4& P) -> bool {
@@ -995,23 +1148,7 @@ __global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs 
         if (STASH) {
             uint32_t off = 0u;  // empty rows: nothing to copy
             if ((s.flags & F_VALID) && hits > 0) {
-                bool ok = !knn && hits <= cap;
-                if (ok && cur + hits > lim) {
-                    ok = false;
-                    if (!dry) {
-                        const uint32_t grab = max(A.stash_chunk, hits);
-                        uint32_t t = 0;
-                        if (lane == 0) t = atomicAdd(A.stash_ctr + region * SPHIDX_QSTRIDE, grab);
-                        t = uni(t);
-                        if ((uint64_t)t + grab <= A.stash_region) {
-                            cur = region * A.stash_region + t;
-                            lim = cur + grab;
-                            ok = true;
-                        } else {
-                            dry = true;
-                        }
-                    }
-                }
+                const bool ok = !knn && hits <= cap && stash_room(hits);
                 if (ok) {
                     wave_sync();
                     sort_row_store(td, ti, sd, si, hist, hits, s.r2, idbits, A.stash_ids + cur,
@@ -1461,10 +1598,15 @@ __global__ __launch_bounds__(256) void topm_kernel(LatArgs L, TabArgs T, QArgs A
     const AxisWrap aw = axis_wrap(L);
     const uint32_t lane = lane_id();
     const uint32_t nq = FROM_LIST ? uni(*A.list_count) : A.Q;
+    // every query: skip the rows a stashing count pass kept and the copy
+    // placed (the list holds none of them); when this call asks for dist^2
+    // and the stash holds none, the copy placed nothing
+    const bool kept_rows = !FROM_LIST && A.stash_hdr[kHdrMode] != 0u && !(A.out_d2 && A.stash_hdr[kHdrHasD2] == 0u);
     for_each_query(nq, A, queue_set(A, kQTopm), [&](uint32_t ti_) {
         const uint32_t qi = FROM_LIST ? uni(A.list[ti_]) : ti_;
         const Query s = load_query(L, A, qi);
         if (!FROM_LIST && !(s.flags & F_KNN)) return;
+        if (kept_rows && uni(A.soff[qi]) != kMaxId) return;
         const int64_t rb = A.row_ptr[s.row];
         const uint32_t rowlen = (uint32_t)(A.row_ptr[s.row + 1] - rb);
         if (rowlen == 0 || !(s.flags & F_VALID)) return;
@@ -1476,101 +1618,16 @@ __global__ __launch_bounds__(256) void topm_kernel(LatArgs L, TabArgs T, QArgs A
         uint64_t ld = 0;
         uint32_t li = 0;
         uint32_t written = 0;
-        // objects per cell around the centre: the home cell's count, with the
-        // lattice mean as a floor (K-NN rows carry no density of their own)
-        float dens = (float)L.n / (float)(L.ncells ? L.ncells : 1u);
-        if (s.flags & F_SPHERE) {
-            const uint32_t home = pack_cell(L, s.c[0], s.c[1], s.c[2]);
-            dens = fmaxf(dens, (float)(L.cs[home + 1] - L.cs[home]));
-        }
-        const float e = (float)(1u << L.F);
         while (written < rowlen) {
             const uint32_t M = min(cap, rowlen - written);
             const uint32_t target = written + M;
-            // first bound: the radius expected to hold `target` objects (a
-            // radius row: the row's own mean density over its ball); grown
-            // and the window restarted whenever fewer than M lie within it
-            float rho;
-            if (s.flags & F_KNN)
-                rho = 1.25f * e * cbrtf(0.2387f * (float)target / fmaxf(dens, 1e-6f));
-            else
-                rho = 1.1f * (float)s.r * cbrtf((float)target / (float)rowlen);
-            uint64_t B = rho >= (float)s.r ? s.r2 : min(s.r2, (uint64_t)((double)rho * (double)rho));
-            if (!(s.flags & F_SPHERE)) B = s.r2;  // the bounding cube is scanned whole anyway
+            uint64_t B = first_bound(L, s, target, rowlen);
             if (M <= 64) {
-                // ---- a window of at most 64 in registers: lane i holds the
-                // i-th best pair.  A few new pairs are inserted one by one
-                // (place = pairs ahead of it, the rest move up one lane); a
-                // large batch is sorted and merged (the 64 smallest of list
-                // and batch, as a bitonic sequence, then sorted).
-                uint64_t rd = kMaxD2, kd = kMaxD2;
-                uint32_t ri = kMaxId, kid = kMaxId, held = 0, cand2 = 0, walked2 = 0;
-                auto visit_r = [&](bool act, uint32_t p, const uint4& P) -> bool {
-                    const uint64_t d2 = obj_dist2(aw, s, P);
-                    const uint32_t id = P.w;
-                    bool cv = act && d2 <= B && p != s.self;
-                    if (cv && has_lower) cv = key_less(ld, li, d2, id);
-                    if (cv && held >= M) cv = key_less(d2, id, kd, kid);
-                    uint64_t qm = __ballot(cv);
-                    if (qm == 0) return false;
-                    const uint32_t nb = (uint32_t)__popcll(qm);
-                    if (nb > 6) {
-                        uint64_t cd = cv ? d2 : kMaxD2;
-                        uint32_t ci = cv ? id : kMaxId;
-                        wave_sort64(cd, ci);
-                        const uint64_t xd = shfl64(cd, 63u - lane);
-                        const uint32_t xi = __shfl(ci, 63u - lane);
-                        if (key_less(xd, xi, rd, ri)) {
-                            rd = xd;
-                            ri = xi;
-                        }
-                        wave_bitonic_clean64(rd, ri);
-                        held = min(held + nb, 64u);
-                    } else {
-                        while (qm) {
-                            const uint32_t j = (uint32_t)__builtin_ctzll(qm);
-                            qm &= qm - 1ull;
-                            const uint64_t nd = lane_val64(d2, j);
-                            const uint32_t ni = lane_val(id, j);
-                            if (held >= M && !key_less(nd, ni, kd, kid)) continue;
-                            const uint32_t pos = (uint32_t)__popcll(__ballot(key_less(rd, ri, nd, ni)));
-                            const uint32_t below = lane ? lane - 1u : 0u;
-                            const uint64_t sd = shfl64(rd, below);
-                            const uint32_t si = __shfl(ri, below);
-                            if (lane > pos) {
-                                rd = sd;
-                                ri = si;
-                            } else if (lane == pos) {
-                                rd = nd;
-                                ri = ni;
-                            }
-                            held = min(held + 1u, 64u);
-                            if (held >= M) {
-                                kd = lane_val64(rd, M - 1u);
-                                kid = lane_val(ri, M - 1u);
-                            }
-                        }
-                    }
-                    if (held >= M) {
-                        kd = lane_val64(rd, M - 1u);
-                        kid = lane_val(ri, M - 1u);
-                    }
-                    return false;
-                };
-                for (;;) {
-                    walk<METHOD, TLDS, true>(L, T, tab_lds, s, false, walked2, [&]() { return held >= M ? kd : B; },
-                                             [&](const RowRef& r) -> bool {
-                        return for_candidates(L, r.st0, r.cnt0, r.st1, r.cnt1, own, cand2, visit_r);
-                    });
-                    if (held >= M || B >= s.r2) break;
-                    B = min(s.r2, B + B + (B >> 2) + 1u);  // radius x1.5
-                    held = 0;
-                    rd = kMaxD2;
-                    ri = kMaxId;
-                    kd = kMaxD2;
-                    kid = kMaxId;
-                }
-                const uint32_t got = min(held, M);
+                // ---- a window of at most 64 in registers
+                uint64_t rd;
+                uint32_t ri;
+                const uint32_t got = topm_registers<METHOD, TLDS>(L, T, tab_lds, s, aw, own, M, B, has_lower, ld, li,
+                                                                   rd, ri);
                 if (lane < got) {
                     A.out_ids[rb + written + lane] = ri;
                     if (A.out_d2) A.out_d2[rb + written + lane] = (int64_t)rd;
@@ -1855,6 +1912,9 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
     ql.persistent = 1;
     if (pass == 0) {
         const int lp = q.stash ? 3 : 0;
+        // K-NN rows searched and kept by the count pass (not with per-query
+        // statistics, which that path does not gather)
+        const bool ks = q.stash && q.mode != SPHIDX_MODE_RADIUS && !q.stats;
         if ((e = mark(ev_begin)) != hipSuccess) return e;
         if (q.group) {
             // radius queries in groups: all queries (those of the tables),
@@ -1885,27 +1945,34 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
             ql.list = q.xq;
             ql.list_count = q.xq_count;
             ql.list_set = kQExtra;
-            if (q.stash)
-                return launch_ptr(SPHIDX_PICK(count_kernel, variant, kEither, , true, true), 0, ql, w, b,
+            if (ks)
+                return launch_ptr(SPHIDX_PICK(count_kernel, variant, kEither, , true, true, true), 0, ql, w, b,
                                   query_lds_bytes(lp, q.sort_cap, w, tb), st, L, T);
-            return launch_ptr(SPHIDX_PICK(count_kernel, variant, kEither, , true, false), 0, ql, w, b,
+            if (q.stash)
+                return launch_ptr(SPHIDX_PICK(count_kernel, variant, kEither, , true, true, false), 0, ql, w, b,
+                                  query_lds_bytes(lp, q.sort_cap, w, tb), st, L, T);
+            return launch_ptr(SPHIDX_PICK(count_kernel, variant, kEither, , true, false, false), 0, ql, w, b,
                               query_lds_bytes(lp, q.sort_cap, w, tb), st, L, T);
         }
-        if (q.stash)
-            e = launch_ptr(either ? SPHIDX_PICK(count_kernel, variant, kEither, , false, true)
-                                  : SPHIDX_PICK(count_kernel, variant, kSphere, , false, true),
-                           q.Q, q, w, b, query_lds_bytes(lp, q.sort_cap, w, tb), st, L, T);
+        const void* fn;
+        if (ks)
+            fn = either ? SPHIDX_PICK(count_kernel, variant, kEither, , false, true, true)
+                        : SPHIDX_PICK(count_kernel, variant, kSphere, , false, true, true);
+        else if (q.stash)
+            fn = either ? SPHIDX_PICK(count_kernel, variant, kEither, , false, true, false)
+                        : SPHIDX_PICK(count_kernel, variant, kSphere, , false, true, false);
         else
-            e = launch_ptr(either ? SPHIDX_PICK(count_kernel, variant, kEither, , false, false)
-                                  : SPHIDX_PICK(count_kernel, variant, kSphere, , false, false),
-                           q.Q, q, w, b, query_lds_bytes(lp, q.sort_cap, w, tb), st, L, T);
+            fn = either ? SPHIDX_PICK(count_kernel, variant, kEither, , false, false, false)
+                        : SPHIDX_PICK(count_kernel, variant, kSphere, , false, false, false);
+        e = launch_ptr(fn, q.Q, q, w, b, query_lds_bytes(lp, q.sort_cap, w, tb), st, L, T);
         if (e == hipSuccess) e = mark(ev_end);
         if (e != hipSuccess || variant == 0 || either) return e;
         ql.list = q.fbq;
         ql.list_count = q.fb_count;
         ql.list_set = kQFbCount;
-        return launch_ptr(q.stash ? (const void*)count_kernel<kCube, false, true, true>
-                                  : (const void*)count_kernel<kCube, false, true, false>,
+        return launch_ptr(ks        ? (const void*)count_kernel<kCube, false, true, true, true>
+                          : q.stash ? (const void*)count_kernel<kCube, false, true, true, false>
+                                    : (const void*)count_kernel<kCube, false, true, false, false>,
                           0, ql, w, b, query_lds_bytes(lp, q.sort_cap, w, 0), st, L, T);
     }
     const size_t sh1 = query_lds_bytes(1, q.sort_cap, w, tb);
@@ -1935,6 +2002,9 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
         return launch_ptr(SPHIDX_PICK(topm_kernel, variant, kEither, , true), 0, ql, w, b, sh2, st, L, T);
     }
     if ((e = mark(ev_begin)) != hipSuccess) return e;
+    // rows kept by the count pass (does nothing otherwise), then the rest
+    gather_kernel<<<(q.Q + 255) / 256, 256, 0, st>>>(q, L.pts, L.status);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     e = launch_ptr(SPHIDX_PICK(topm_kernel, variant, kEither, , false), q.Q, q, w, b, sh2, st, L, T);
     return e == hipSuccess ? mark(ev_end) : e;
 }

@@ -164,3 +164,40 @@ def test_grouped_count_overflowing_hit_buffer(sx, orc, sort_cap):
     ln = sx.LaunchConfig(grouped=1, sort_cap=sort_cap, waves_per_block=2)
     got, _ = _cycle(sx, lat, tab, q, ln, False, False, 1.0)
     assert_same((got[0], got[1], None), ref, f"grouped overflow {sort_cap}")
+
+
+@pytest.mark.parametrize("mask", [7, 0])
+def test_stash_knn_rows_match_oracle(sx, orc, mask):
+    """K-NN rows searched and kept by the count pass (K <= 64) beside rows the
+    top-K pass still walks (K > 64, or no stash room), in K-NN and mixed
+    batches; ids-only stash with dist^2 asked by the write."""
+    rng = np.random.default_rng(200 + mask)
+    log2, F = (5, 4, 5), 10
+    pts = tiny_points(rng, log2, F, mask, 30000, outside=(mask != 7))
+    lat = _world(sx, log2, F, mask, pts)
+    tab = sx.Tables(lat, 2, 3 << F)
+    n = len(pts[0])
+    k = rng.integers(1, 90, n).astype(np.uint32)  # some above 64
+    k[:50] = 64
+    k[50:100] = 65
+    cap = rng.integers(0, 3 << F, n).astype(np.uint32)
+    keep = (sx.to_dev_u32(k), sx.to_dev_u32(cap))
+    q = sx.make_queries(n, None, keep[1], keep[0], sx.MODE_KNN, sx.EXCLUDE_SELF)
+    g = orc.Grid(orc.Lattice(log2, F, mask), pts)
+    ref = g.knn(k, cap, flags=orc.EXCLUDE_SELF)
+    km = np.where(rng.random(n) < 0.5, k, 0).astype(np.uint32)
+    keep2 = sx.to_dev_u32(km)
+    qm = sx.make_queries(n, None, keep[1], keep2, sx.MODE_MIXED, 0)
+    refm = g.mixed(km, cap)
+    g.close()
+    for frac in (1.0, 0.3):
+        for launch in (sx.LaunchConfig(), sx.LaunchConfig(grouped=1)):
+            say(f"knn stash mask={mask} frac={frac} grouped={launch.grouped}")
+            got, _ = _cycle(sx, lat, tab, q, launch, True, True, frac)
+            assert_same(got, ref, f"knn stash {frac}")
+            got, _ = _cycle(sx, lat, tab, qm, launch, True, True, frac)
+            assert_same(got, refm, f"mixed stash {frac}")
+    say("knn stash ids only, write asks dist2")
+    got, _ = _cycle(sx, lat, tab, q, sx.LaunchConfig(), False, True, 1.0)
+    assert_same(got, ref, "knn ids-only stash, dist2 written")
+    del keep, keep2
