@@ -1597,16 +1597,16 @@ __global__ __launch_bounds__(256) void topm_kernel(LatArgs L, TabArgs T, QArgs A
     }
     const AxisWrap aw = axis_wrap(L);
     const uint32_t lane = lane_id();
-    const uint32_t nq = FROM_LIST ? uni(*A.list_count) : A.Q;
-    // every query: skip the rows a stashing count pass kept and the copy
-    // placed (the list holds none of them); when this call asks for dist^2
-    // and the stash holds none, the copy placed nothing
-    const bool kept_rows = !FROM_LIST && A.stash_hdr[kHdrMode] != 0u && !(A.out_d2 && A.stash_hdr[kHdrHasD2] == 0u);
+    // every query, unless a stashing count pass kept rows and the copy placed
+    // them: then only the rows it could not keep, which it listed on the walk
+    // list (when this call asks for dist^2 and the stash holds none, the copy
+    // placed nothing and every row is searched)
+    const bool from_walk = !FROM_LIST && A.stash_hdr[kHdrMode] != 0u && !(A.out_d2 && A.stash_hdr[kHdrHasD2] == 0u);
+    const uint32_t nq = FROM_LIST ? uni(*A.list_count) : from_walk ? uni(*A.walk_count) : A.Q;
     for_each_query(nq, A, queue_set(A, kQTopm), [&](uint32_t ti_) {
-        const uint32_t qi = FROM_LIST ? uni(A.list[ti_]) : ti_;
+        const uint32_t qi = FROM_LIST ? uni(A.list[ti_]) : from_walk ? uni(A.walkq[ti_]) : ti_;
         const Query s = load_query(L, A, qi);
         if (!FROM_LIST && !(s.flags & F_KNN)) return;
-        if (kept_rows && uni(A.soff[qi]) != kMaxId) return;
         const int64_t rb = A.row_ptr[s.row];
         const uint32_t rowlen = (uint32_t)(A.row_ptr[s.row + 1] - rb);
         if (rowlen == 0 || !(s.flags & F_VALID)) return;
