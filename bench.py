@@ -196,7 +196,7 @@ def leg_c2(args, out):
         for model, tag in ((0, "auto_choice"), (1, "auto_work")):
             mo = torch.empty(n, dtype=torch.int32, device="cuda")
             auto = dataclasses.replace(tuned, method=sphidx.METHOD_AUTO, method_out=mo, select_model=model)
-            ms_auto, ph_auto, k_auto = timed(auto, k2, 1)
+            ms_auto, ph_auto, k_auto = timed(auto, k2, 3)
             rp_a = buf.row_ptr.cpu().numpy()
             ids_a = buf.ids[: int(rp_a[-1])].cpu().numpy().view(np.uint32)
             used = torch.bincount(mo.long(), minlength=4).cpu().tolist()
