@@ -543,7 +543,8 @@ def leg_sweep(args, out):
     (16^3, 32^3), boundary (wrapping, clipped), load and query distance (cell
     units, up to 3/4 of the world), the shapes of the paper's Figs. 5-10.
     Each point times the same queries with both methods (count + write, the
-    write touching every neighbour's id) and checks that their rows agree.
+    write touching every neighbour's id; 5 runs, the 2 slowest dropped) and
+    checks that their rows agree.
     All-neighbour points also time the per-query choice by volume (sphere,
     cube or non-empty cell list, Section III.B/C) and count what it chose."""
     import numpy as np
@@ -555,7 +556,9 @@ def leg_sweep(args, out):
     rows = []
     mismatches = 0
 
-    def timed_query(lat, tab, q, ln, reps=3):
+    def timed_query(lat, tab, q, ln, reps=5, drop=2):
+        """Mean ms of count + write over `reps` runs, the `drop` slowest left
+        out (the paper's protocol, Section IV.A, in small)."""
         buf = sphidx.QueryBuffers(q.count, 0, want_dist2=False)
         sphidx.count(lat, tab, q, buf, ln)
         total = int(buf.row_ptr[-1].item())
@@ -567,13 +570,14 @@ def leg_sweep(args, out):
             sphidx.write(lat, tab, q, buf, ln)
         run()
         torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(reps):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record()
             run()
-        b.record()
-        b.synchronize()
-        return a.elapsed_time(b) / reps, buf
+            b.record()
+        torch.cuda.synchronize()
+        t = sorted(a.elapsed_time(b) for a, b in ev)[: reps - drop]
+        return sum(t) / len(t), buf
 
     for log2 in (4, 5):
         for mask in (7, 0):
