@@ -49,6 +49,7 @@ __global__ void advance_step_kernel(uint32_t* step) { *step += 1u; }
 
 __global__ __launch_bounds__(256) void checksum_kernel(const int64_t* __restrict__ row_ptr, uint32_t Q,
                                                        unsigned long long* out) {
+    __shared__ uint64_t part[2][4];
     uint64_t s = 0, h = 0;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < Q; i += gridDim.x * blockDim.x) {
         uint64_t c = (uint64_t)(row_ptr[i + 1] - row_ptr[i]);
@@ -60,7 +61,19 @@ __global__ __launch_bounds__(256) void checksum_kernel(const int64_t* __restrict
         s += __shfl_xor(s, d);
         h += __shfl_xor(h, d);
     }
+    // one pair of atomics per block: the same two words take every block's
+    // sums, so their count is what bounds the kernel
+    const uint32_t wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
+        part[0][wave] = s;
+        part[1][wave] = h;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (uint32_t w = 1; w < (blockDim.x >> 6); ++w) {
+            s += part[0][w];
+            h += part[1][w];
+        }
         atomicAdd(&out[0], (unsigned long long)s);
         atomicAdd(&out[1], (unsigned long long)h);
     }
@@ -91,7 +104,7 @@ hipError_t launch_count_checksum(const int64_t* row_ptr, uint32_t Q, uint64_t* o
     hipError_t e = launch_fill_u32((uint32_t*)out, 0u, 4, st);
     if (e != hipSuccess) return e;
     uint32_t blocks = (Q + 255) / 256;
-    if (blocks > 2048) blocks = 2048;
+    if (blocks > 1024) blocks = 1024;
     if (blocks == 0) blocks = 1;
     checksum_kernel<<<blocks, 256, 0, st>>>(row_ptr, Q, (unsigned long long*)out);
     return hipGetLastError();
