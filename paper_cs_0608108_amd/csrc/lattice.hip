@@ -145,15 +145,16 @@ __device__ T block_exclusive_scan(T v, T* sh, T& total) {
     return r;
 }
 
+// Block totals (the order of a sum is free: lanes read consecutive elements).
 template <typename T>
 __global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const T* __restrict__ in, size_t n,
                                                                    T* __restrict__ partial) {
     __shared__ T sh[kScanThreads / 64 + 1];
-    size_t base = (size_t)blockIdx.x * kScanBlock + (size_t)threadIdx.x * kScanItems;
+    const size_t base = (size_t)blockIdx.x * kScanBlock + threadIdx.x;
     T s = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k)
-        if (base + k < n) s += in[base + k];
+        if (base + (size_t)k * kScanThreads < n) s += in[base + (size_t)k * kScanThreads];
     T tot;
     block_exclusive_scan<T>(s, sh, tot);
     if (threadIdx.x == 0) partial[blockIdx.x] = tot;
@@ -180,24 +181,47 @@ __global__ __launch_bounds__(kScanThreads) void scan_partials_kernel(T* __restri
     if (threadIdx.x == 0) partial[nb] = tot;
 }
 
-template <typename T>
+// Each thread scans its own run of kScanItems elements; with VEC (data
+// 16-byte aligned) a whole run is moved with 16-byte loads and stores.
+template <typename T, bool VEC>
 __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(T* __restrict__ data, size_t n,
                                                                  const T* __restrict__ partial, uint32_t nb) {
     __shared__ T sh[kScanThreads / 64 + 1];
-    size_t base = (size_t)blockIdx.x * kScanBlock + (size_t)threadIdx.x * kScanItems;
+    constexpr int kVec = kScanItems * (int)sizeof(T) / 16;
+    const size_t base = (size_t)blockIdx.x * kScanBlock + (size_t)threadIdx.x * kScanItems;
+    const bool whole = VEC && base + kScanItems <= n;
     T v[kScanItems];
+    if (whole) {
+        const uint4* p = (const uint4*)(data + base);
+        uint4 w[kVec];
+#pragma unroll
+        for (int k = 0; k < kVec; ++k) w[k] = p[k];
+        __builtin_memcpy(v, w, sizeof(v));
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) v[k] = (base + k < n) ? data[base + k] : (T)0;
+    }
     T s = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        v[k] = (base + k < n) ? data[base + k] : (T)0;
-        s += v[k];
-    }
+    for (int k = 0; k < kScanItems; ++k) s += v[k];
     T tot;
     T off = block_exclusive_scan<T>(s, sh, tot) + partial[blockIdx.x];
+    T o[kScanItems];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < n) data[base + k] = off;
+        o[k] = off;
         off += v[k];
+    }
+    if (whole) {
+        uint4 w[kVec];
+        __builtin_memcpy(w, o, sizeof(o));
+        uint4* p = (uint4*)(data + base);
+#pragma unroll
+        for (int k = 0; k < kVec; ++k) p[k] = w[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k)
+            if (base + k < n) data[base + k] = o[k];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) data[n] = partial[nb];
 }
@@ -210,7 +234,10 @@ hipError_t scan_exclusive(T* data, size_t n, T* partial, hipStream_t st) {
     if (nb == 0) nb = 1;
     scan_reduce_kernel<T><<<nb, kScanThreads, 0, st>>>(data, n, partial);
     scan_partials_kernel<T><<<1, kScanThreads, 0, st>>>(partial, nb);
-    scan_down_kernel<T><<<nb, kScanThreads, 0, st>>>(data, n, partial, nb);
+    if (((uintptr_t)data & 15u) == 0)
+        scan_down_kernel<T, true><<<nb, kScanThreads, 0, st>>>(data, n, partial, nb);
+    else
+        scan_down_kernel<T, false><<<nb, kScanThreads, 0, st>>>(data, n, partial, nb);
     return hipGetLastError();
 }
 
