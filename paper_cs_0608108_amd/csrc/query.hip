@@ -1189,9 +1189,13 @@ __global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs 
 
 constexpr uint32_t kGroup = 8, kGroupBits = 3, kMaxHitCap = 512;
 // The group's hit buffer holds 2 x sort_cap keys, and a group ends before
-// its rows would exceed sort_cap / 2: at about one or two hits per row
-// (objects per cell below about one) its hits fit the buffer.  A smaller
-// sort_cap trades packing for LDS, hence occupancy.
+// its rows would exceed 3/4 of sort_cap: at up to about two and a half hits
+// per row (objects per cell below about one) its hits fit the buffer, and a
+// group that overflows is counted exactly and walked again by the write
+// pass.  Fewer rows per group cost more groups; more cost more overflows (at
+// sort_cap / 2 the uneven-radius step took 1.255 ms, at sort_cap 1.180 ms, at
+// 3/4 1.173 ms).  A smaller sort_cap trades packing for LDS, hence
+// occupancy, and so does a larger buffer (3 x sort_cap: 1.201 ms).
 
 // Per-wave LDS of the grouped kernel: slot data (kGroup x 64 B), 32 words of
 // per-slot counters, the 64-word owner map, then (stash) the hit keys in
@@ -1210,7 +1214,7 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
     extern __shared__ __align__(16) char smem[];
     const uint32_t* tab_lds = stage_table<TLDS>(T, smem);
     const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
-    const uint32_t hitcap = 2 * A.sort_cap, group_rows = A.sort_cap / 2;  // hitcap <= kMaxHitCap
+    const uint32_t hitcap = 2 * A.sort_cap, group_rows = A.sort_cap - A.sort_cap / 4;  // hitcap <= kMaxHitCap
     char* wb = smem + table_lds_bytes<TLDS>(T) + (size_t)wave * group_lds_per_wave(STASH, A.sort_cap);
     uint4* qp = (uint4*)wb;                    // per slot: centre + table start, r^2 + self + rows,
                                                // cube extent, flags + row
