@@ -193,6 +193,9 @@ def leg_c2(args, out):
         # cells (the paper's volumes) and by estimated lane work; the
         # non-empty cell list is kept (and rebuilt) only here
         lat.attach_cell_list()
+        # one discarded run first: the first timing after attaching has read
+        # up to 2 ms more per rebuild on the GPU machine, once only
+        timed(dataclasses.replace(tuned, method=sphidx.METHOD_AUTO), 3, 2)
         for model, tag in ((0, "auto_choice"), (1, "auto_work")):
             mo = torch.empty(n, dtype=torch.int32, device="cuda")
             auto = dataclasses.replace(tuned, method=sphidx.METHOD_AUTO, method_out=mo, select_model=model)
