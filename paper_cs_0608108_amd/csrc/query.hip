@@ -430,13 +430,20 @@ __device__ __forceinline__ uint32_t axis_far(int o, uint32_t f, uint32_t F) {
     return max(f, e - 1u - f);
 }
 
-// floor(sqrt(v)) for v < 2^62.
+// floor(sqrt(v)) for v < 2^62.  The hardware reciprocal square root
+// (relative error about 2^-23) and one Newton step give sqrt(v) to about
+// 2^-45 relative, well within one unit below 2^31; exact integer steps then
+// settle the floor.  (v = 0 makes the estimate NaN: it is not used.)
 __device__ __forceinline__ uint32_t isqrt64(uint64_t v) {
-    uint64_t x = (uint64_t)__builtin_sqrt((double)v);
-    if (x * x > v) --x;
-    if (x * x > v) --x;
-    if ((x + 1) * (x + 1) <= v) ++x;
-    return (uint32_t)x;
+    const double d = (double)v;
+    const double y = __builtin_amdgcn_rsq(d);
+    double x = d * y;
+    x = __builtin_fma(x, __builtin_fma(-x, 0.5 * y, 0.5), x);
+    uint32_t s = v ? (uint32_t)x : 0u;
+    if ((uint64_t)s * s > v) --s;
+    if ((uint64_t)s * s > v) --s;
+    if ((uint64_t)(s + 1u) * (s + 1u) <= v) ++s;
+    return s;
 }
 
 // Turn an unwrapped x-run [a, b] of the row starting at cell `base` (and its
@@ -631,7 +638,7 @@ __device__ __forceinline__ uint64_t obj_dist2(const AxisWrap& w, const Query& s,
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int32_t dd = (int32_t)(((pv[a] - s.q[a]) + w.half[a]) & w.mask[a]) - (int32_t)w.half[a];
-        d2 += sq((uint32_t)(dd < 0 ? -dd : dd));
+        d2 += (uint64_t)((int64_t)dd * dd);
     }
     return d2;
 }
@@ -1187,7 +1194,7 @@ __global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs 
 // Queries it does not take (K-NN, keys that would not fit 64 bits) go to
 // the extra list for the one-query-per-wave kernel.
 
-constexpr uint32_t kGroup = 8, kGroupBits = 3, kMaxHitCap = 512;
+constexpr uint32_t kGroup = 8, kGroupBits = 3, kMaxHitCap = 512, kLayers = 4;  // kLayers x 64 >= sort_cap
 // The group's hit buffer holds 2 x sort_cap keys, and a group ends before
 // its rows would exceed 3/4 of sort_cap: at up to about two and a half hits
 // per row (objects per cell below about one) its hits fit the buffer, and a
@@ -1197,11 +1204,12 @@ constexpr uint32_t kGroup = 8, kGroupBits = 3, kMaxHitCap = 512;
 // 3/4 1.173 ms).  A smaller sort_cap trades packing for LDS, hence
 // occupancy, and so does a larger buffer (3 x sort_cap: 1.201 ms).
 
-// Per-wave LDS of the grouped kernel: slot data (kGroup x 64 B), 32 words of
+// Per-wave LDS of the grouped kernel: slot data (kGroup x 80 B), 32 words of
 // per-slot counters, the 64-word owner map, then (stash) the hit keys in
-// arrival order, the same by bucket, and the bucket counts.
+// arrival order, the same by bucket, and the bucket counts, or (no stash)
+// sort_cap 16-byte row records.
 __host__ __device__ constexpr size_t group_lds_per_wave(bool stash, uint32_t cap) {
-    return 512 + 128 + 256 + (stash ? (size_t)cap * 2 * 20 : 0);
+    return 640 + 128 + 256 + (stash ? (size_t)cap * 2 * 20 : (size_t)cap * 16);
 }
 
 // dist^2 field of a group hit key (slot | dist^2 | id)
@@ -1217,8 +1225,8 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
     const uint32_t hitcap = 2 * A.sort_cap, group_rows = A.sort_cap - A.sort_cap / 4;  // hitcap <= kMaxHitCap
     char* wb = smem + table_lds_bytes<TLDS>(T) + (size_t)wave * group_lds_per_wave(STASH, A.sort_cap);
     uint4* qp = (uint4*)wb;                    // per slot: centre + table start, r^2 + self + rows,
-                                               // cube extent, flags + row
-    uint32_t* cnt = (uint32_t*)(wb + 512);     // [0, 8) hits, [8, 16) row start, [16, 24) hits,
+                                               // cube extent, flags + row, W/2 - centre + self
+    uint32_t* cnt = (uint32_t*)(wb + 640);     // [0, 8) hits, [8, 16) row start, [16, 24) hits,
     uint32_t* qst = cnt + 8;                   // [24, 32) bucket scale (float)
     uint32_t* qn = cnt + 16;
     float* qsc = (float*)(cnt + 24);
@@ -1226,6 +1234,9 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
     uint64_t* hb = (uint64_t*)(own + 64);      // hitcap keys in arrival order
     uint64_t* hs = hb + hitcap;                // hitcap keys by bucket
     uint32_t* hh = (uint32_t*)(hs + hitcap);   // hitcap bucket counts, then starts
+    // sort_cap row records of the chunk being walked (in the stash case the
+    // bucket buffer, free until the sort)
+    uint4* rinfo = STASH ? (uint4*)hs : (uint4*)(own + 64);
     const AxisWrap aw = axis_wrap(L);
     const uint32_t idbits = L.n > 1 ? 32u - (uint32_t)__builtin_clz(L.n - 1u) : 0u;
     const uint32_t d2bits = 64u - kGroupBits - idbits;
@@ -1281,11 +1292,14 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
             if (mine) {
                 const uint64_t r2 = (uint64_t)d1.x * d1.x;
                 const uint32_t self = (A.qx == nullptr && (A.flags & SPHIDX_EXCLUDE_SELF)) ? qi : kMaxId;
-                uint4* p = qp + 4 * lane;
+                uint4* p = qp + 5 * lane;
                 p[0] = make_uint4(d0.x, d0.y, d0.z, d1.w);
                 p[1] = make_uint4((uint32_t)r2, (uint32_t)(r2 >> 32), self, rows);
                 p[2] = make_uint4(d3.x, d3.y, d3.z, d2.z);
                 p[3] = make_uint4(d2.w, d3.w, d1.z, row);
+                // the candidate test's form of the centre: the minimum-image
+                // offset is ((p + (W/2 - c)) mod W) - W/2
+                p[4] = make_uint4(aw.half[0] - d0.x, aw.half[1] - d0.y, aw.half[2] - d0.z, self);
             }
             if (lane < kGroup) cnt[lane] = 0u;
             {
@@ -1301,90 +1315,116 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
             const uint32_t R = lane_val(incl, 63);
             const uint32_t excl = incl - rows;
             uint32_t hcount = 0;
-            for (uint32_t base = 0; base < R; base += 64) {
-                // ---- this lane's row: owner slot and entry
-                own[lane] = 0;
-                wave_sync();
-                if (rows > 0 && excl < base + 64 && incl > base) own[excl > base ? excl - base : 0] = lane + 1;
-                wave_sync();
-                const uint32_t fr = base + lane;
-                const bool act = fr < R;
-                const uint32_t gmax = scan_max(own[lane]);
-                const uint32_t gs = act ? gmax - 1u : 0u;
-                const uint32_t ent = fr - bperm(excl, gs);
-                const uint4* p = qp + 4 * gs;
-                const uint4 pa = p[0], pb = p[1], pc = p[2], pd = p[3];
-                Query sq;
-                sq.q[0] = pa.x;
-                sq.q[1] = pa.y;
-                sq.q[2] = pa.z;
-                sq.tb = pa.w;
-                sq.r2 = (uint64_t)pb.x | ((uint64_t)pb.y << 32);
-                sq.self = pb.z;
-                sq.lo[0] = (int32_t)pc.x;
-                sq.lo[1] = (int32_t)pc.y;
-                sq.lo[2] = (int32_t)pc.z;
-                sq.nn[0] = pc.w;
-                sq.nn[1] = pd.x;
-                sq.nn[2] = pd.y;
-                sq.flags = pd.z;
-                const uint32_t e1 = 1u << L.F;
-                for (int a = 0; a < 3; ++a) {
-                    sq.c[a] = sq.q[a] >> L.F;
-                    sq.f[a] = sq.q[a] & (e1 - 1u);
-                    sq.up[a] = e1 - sq.f[a];
-                    sq.dn[a] = sq.f[a] + 1u;
+            // The group's rows go in chunks of sort_cap (at most kLayers x 64)
+            // rows: first every row of the chunk, 64 per layer, one per lane,
+            // gives its object ranges, numbered by a prefix over the chunk and
+            // kept in LDS; then the chunk's candidates, 64 per step, in one
+            // stream, with the next step's records loaded while this step's
+            // are tested.
+            for (uint32_t rb = 0; rb < R; rb += A.sort_cap) {
+                const uint32_t clen = min(A.sort_cap, R - rb);
+                uint32_t cex[kLayers], cin[kLayers];
+#pragma unroll
+                for (uint32_t k = 0; k < kLayers; ++k) cex[k] = cin[k] = 0u;
+                uint32_t carry = 0;
+                for (uint32_t k = 0; k * 64u < clen; ++k) {
+                    // ---- this lane's row: owner slot and entry
+                    const uint32_t base = rb + k * 64u;
+                    own[lane] = 0;
+                    wave_sync();
+                    if (rows > 0 && excl < base + 64 && incl > base) own[excl > base ? excl - base : 0] = lane + 1;
+                    wave_sync();
+                    const bool act = k * 64u + lane < clen;
+                    const uint32_t fr = base + lane;
+                    const uint32_t gmax = scan_max(own[lane]);
+                    const uint32_t gs = act ? gmax - 1u : 0u;
+                    const uint32_t ent = fr - bperm(excl, gs);
+                    const uint4* p = qp + 5 * gs;
+                    const uint4 pa = p[0], pb = p[1], pc = p[2], pd = p[3];
+                    Query sq;
+                    sq.q[0] = pa.x;
+                    sq.q[1] = pa.y;
+                    sq.q[2] = pa.z;
+                    sq.tb = pa.w;
+                    sq.r2 = (uint64_t)pb.x | ((uint64_t)pb.y << 32);
+                    sq.self = pb.z;
+                    sq.lo[0] = (int32_t)pc.x;
+                    sq.lo[1] = (int32_t)pc.y;
+                    sq.lo[2] = (int32_t)pc.z;
+                    sq.nn[0] = pc.w;
+                    sq.nn[1] = pd.x;
+                    sq.nn[2] = pd.y;
+                    sq.flags = pd.z;
+                    const uint32_t e1 = 1u << L.F;
+                    for (int a = 0; a < 3; ++a) {
+                        sq.c[a] = sq.q[a] >> L.F;
+                        sq.f[a] = sq.q[a] & (e1 - 1u);
+                        sq.up[a] = e1 - sq.f[a];
+                        sq.dn[a] = sq.f[a] + 1u;
+                    }
+                    const bool is_out = act && (sq.flags & F_OUTSIDE) && ent + 1u == pb.w;
+                    const bool sph = METHOD == kSphere || (METHOD == kEither && (sq.flags & F_SPHERE));
+                    const bool live = act && !is_out;
+                    RowRef r;
+                    if (sph) {
+                        const uint32_t* rws = TLDS ? tab_lds : T.rows;
+                        const uint32_t w = live ? rws[sq.tb + ent] : 0u;
+                        r = sphere_row(L, sq, w, live, sq.r2, false);
+                    } else {
+                        const double inv_ny = sq.nn[1] ? 1.0 / (double)sq.nn[1] : 0.0;
+                        r = cube_row(L, sq, live ? ent : 0u, live, inv_ny);
+                    }
+                    if (is_out) {
+                        // every object outside the region lives in one cell (Section II.B)
+                        r.st0 = L.cs[L.ncells];
+                        r.cnt0 = L.cs[L.ncells + 1] - r.st0;
+                        r.cnt1 = 0u;
+                    }
+                    const uint32_t tl = act ? r.cnt0 + r.cnt1 : 0u;
+                    const uint32_t ci = scan_add(tl);
+                    const uint32_t ce = carry + ci - tl;
+                    // per row: position bases of its two ranges, the slot
+                    // where the second starts, and the query slot
+                    rinfo[k * 64u + lane] = make_uint4(r.st0 - ce, ce + r.cnt0, r.st1 - (ce + r.cnt0), gs);
+#pragma unroll
+                    for (uint32_t j = 0; j < kLayers; ++j) {
+                        cex[j] = j == k ? ce : cex[j];
+                        cin[j] = j == k ? ce + tl : cin[j];
+                    }
+                    carry += lane_val(ci, 63);
                 }
-                const bool is_out = act && (sq.flags & F_OUTSIDE) && ent + 1u == pb.w;
-                const bool sph = METHOD == kSphere || (METHOD == kEither && (sq.flags & F_SPHERE));
-                const bool live = act && !is_out;
-                RowRef r;
-                if (sph) {
-                    const uint32_t* rws = TLDS ? tab_lds : T.rows;
-                    const uint32_t w = live ? rws[sq.tb + ent] : 0u;
-                    r = sphere_row(L, sq, w, live, sq.r2, false);
-                } else {
-                    const double inv_ny = sq.nn[1] ? 1.0 / (double)sq.nn[1] : 0.0;
-                    r = cube_row(L, sq, live ? ent : 0u, live, inv_ny);
-                }
-                if (is_out) {
-                    // every object outside the region lives in one cell (Section II.B)
-                    r.st0 = L.cs[L.ncells];
-                    r.cnt0 = L.cs[L.ncells + 1] - r.st0;
-                    r.cnt1 = 0u;
-                }
-                // ---- the candidates of these rows, 64 per step
-                const uint32_t tl = r.cnt0 + r.cnt1;
-                const uint32_t cincl = scan_add(tl);
-                const uint32_t ctot = lane_val(cincl, 63);
-                const uint32_t cexcl = cincl - tl;
-                const uint32_t smx0 = r.st0 - cexcl, bnd = cexcl + r.cnt0, smx1 = r.st1 - bnd;
-                for (uint32_t cb = 0; cb < ctot; cb += 64) {
+                const uint32_t CT = carry;
+                // ---- owner row of each of the 64 slots from cb: a row marks
+                // where its range starts in the step (a row begun earlier
+                // marks slot 0), and a max-scan hands every slot to its row
+                auto locate = [&](uint32_t cb, uint32_t& pos, uint32_t& sl) -> bool {
                     wave_sync();
                     own[lane] = 0;
                     wave_sync();
-                    if (tl > 0 && cexcl < cb + 64 && cincl > cb) own[cexcl > cb ? cexcl - cb : 0] = lane + 1;
+#pragma unroll
+                    for (uint32_t k = 0; k < kLayers; ++k)
+                        if (cin[k] > cex[k] && cex[k] < cb + 64 && cin[k] > cb)
+                            own[cex[k] > cb ? cex[k] - cb : 0] = k * 64u + lane + 1u;
                     wave_sync();
                     const uint32_t o = scan_max(own[lane]) - 1u;
+                    const uint4 ri = rinfo[o];
                     const uint32_t g = cb + lane;
-                    const bool cact = g < ctot;
-                    // cross-lane reads outside any condition: a permute from
-                    // a lane masked off by a branch would read 0
-                    const uint32_t bo = bperm(bnd, o);
-                    const uint32_t p0 = bperm(smx0, o) + g;
-                    const uint32_t p1 = bperm(smx1, o) + g;
-                    const uint32_t pos = g < bo ? p0 : p1;
-                    const uint32_t sl = bperm(gs, o);
-                    uint4 P = make_uint4(0u, 0u, 0u, kMaxId);
-                    if (cact) P = L.pts[pos];
-                    const uint4 ca = qp[4 * sl], cq = qp[4 * sl + 1];
-                    Query cs;
-                    cs.q[0] = ca.x;
-                    cs.q[1] = ca.y;
-                    cs.q[2] = ca.z;
-                    const uint64_t d2 = obj_dist2(aw, cs, P);
-                    const uint64_t r2 = (uint64_t)cq.x | ((uint64_t)cq.y << 32);
-                    const bool hit = cact && d2 <= r2 && pos != cq.z;
+                    pos = (g < ri.y ? ri.x : ri.z) + g;
+                    sl = ri.w;
+                    return g < CT;
+                };
+                auto test = [&](const uint4& P, uint32_t pos, uint32_t sl, bool cact) {
+                    const uint4 ch = qp[5 * sl + 4];
+                    const uint2 cr = *(const uint2*)(qp + 5 * sl + 1);
+                    const uint32_t pv[3] = {P.x, P.y, P.z}, hv[3] = {ch.x, ch.y, ch.z};
+                    uint64_t d2 = 0;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const int32_t dd = (int32_t)((pv[a] + hv[a]) & aw.mask[a]) - (int32_t)aw.half[a];
+                        d2 += (uint64_t)((int64_t)dd * dd);
+                    }
+                    const uint64_t r2 = (uint64_t)cr.x | ((uint64_t)cr.y << 32);
+                    const bool hit = cact && d2 <= r2 && pos != ch.w;
                     const uint64_t H = __ballot(hit);
                     // hits per slot: each run of slots of one query adds its
                     // share of the ballot once (runs are contiguous)
@@ -1403,6 +1443,26 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
                         if (hit && hp < hitcap)
                             hb[hp] = ((uint64_t)sl << (64u - kGroupBits)) | (d2 << idbits) | (uint64_t)P.w;
                         hcount += (uint32_t)__popcll(H);
+                    }
+                };
+                if (CT > 0) {
+                    uint32_t pos = 0, sl = 0;
+                    bool cact = locate(0, pos, sl);
+                    uint4 P = make_uint4(0u, 0u, 0u, kMaxId);
+                    if (cact) P = L.pts[pos];
+                    for (uint32_t cb = 0; cb < CT; cb += 64) {
+                        uint32_t npos = 0, nsl = 0;
+                        bool nact = false;
+                        uint4 NP = make_uint4(0u, 0u, 0u, kMaxId);
+                        if (cb + 64 < CT) {
+                            nact = locate(cb + 64, npos, nsl);
+                            if (nact) NP = L.pts[npos];
+                        }
+                        test(P, pos, sl, cact);
+                        P = NP;
+                        pos = npos;
+                        sl = nsl;
+                        cact = nact;
                     }
                 }
                 wave_sync();
@@ -1437,7 +1497,7 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
                     if (lane < kGroup) {
                         qst[lane] = qs0;
                         qn[lane] = nq;
-                        const uint4 pb = qp[4 * lane + 1];
+                        const uint4 pb = qp[5 * lane + 1];
                         const uint64_t r2 = (uint64_t)pb.x | ((uint64_t)pb.y << 32);
                         qsc[lane] = (mine && r2 > 0) ? (float)nq / (float)r2 : 0.0f;
                     }

@@ -167,6 +167,33 @@ def test_grouped_count_overflowing_hit_buffer(sx, orc, sort_cap):
 
 
 @pytest.mark.parametrize("mask", [7, 0])
+@pytest.mark.parametrize("method", ["sphere", "cube"])
+def test_grouped_rows_beyond_one_chunk(sx, orc, mask, method):
+    """Radii of 3 to 7 cells against sort_cap 64 and 128: one query's rows
+    span several chunks of the grouped walk (and several groups' hits
+    overflow the buffer), with and without the stash."""
+    rng = np.random.default_rng(140 + mask)
+    log2, F = (5, 5, 5), 8
+    pts = tiny_points(rng, log2, F, mask, 20000, outside=(mask != 7))
+    lat = _world(sx, log2, F, mask, pts)
+    tab = sx.Tables(lat, 2, 7 << F)
+    r = rng.integers(3 << F, (7 << F) + 1, size=len(pts[0])).astype(np.uint32)
+    r_dev = sx.to_dev_u32(r)
+    q = sx.make_queries(len(pts[0]), None, r_dev, None, sx.MODE_RADIUS, 0)
+    g = orc.Grid(orc.Lattice(log2, F, mask), pts)
+    ref = g.radius(r)
+    g.close()
+    m = sx.METHOD_SPHERE if method == "sphere" else sx.METHOD_CUBE
+    for cap in (64, 128):
+        for frac in (1.0, 0.0):
+            say(f"grouped chunks mask={mask} method={method} sort_cap={cap} stash={frac}")
+            ln = sx.LaunchConfig(method=m, grouped=1, sort_cap=cap, waves_per_block=2)
+            got, _ = _cycle(sx, lat, tab, q, ln, True, True, frac)
+            assert_same(got, ref, f"grouped chunks {method} cap {cap} stash {frac}")
+    del r_dev
+
+
+@pytest.mark.parametrize("mask", [7, 0])
 def test_stash_knn_rows_match_oracle(sx, orc, mask):
     """K-NN rows searched and kept by the count pass (K <= 64) beside rows the
     top-K pass still walks (K > 64, or no stash room), in K-NN and mixed
