@@ -1194,22 +1194,37 @@ __global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs 
 // Queries it does not take (K-NN, keys that would not fit 64 bits) go to
 // the extra list for the one-query-per-wave kernel.
 
-constexpr uint32_t kGroup = 8, kGroupBits = 3, kMaxHitCap = 512, kLayers = 4;  // kLayers x 64 >= sort_cap
-// The group's hit buffer holds 2 x sort_cap keys, and a group ends before
-// its rows would exceed 3/4 of sort_cap: at up to about two and a half hits
-// per row (objects per cell below about one) its hits fit the buffer, and a
-// group that overflows is counted exactly and walked again by the write
-// pass.  Fewer rows per group cost more groups; more cost more overflows (at
-// sort_cap / 2 the uneven-radius step took 1.255 ms, at sort_cap 1.180 ms, at
-// 3/4 1.173 ms).  A smaller sort_cap trades packing for LDS, hence
-// occupancy, and so does a larger buffer (3 x sort_cap: 1.201 ms).
+constexpr uint32_t kGroup = 8, kGroupBits = 3;
+// hit buffer keys and rows per group, in eighths of sort_cap
+constexpr uint32_t kHitEighths = 8, kRowEighths = 6;
+constexpr uint32_t kMaxHitCap = 256 * kHitEighths / 8, kLayers = 4;
+// The group's hit buffer holds sort_cap keys, and a group ends before its
+// rows would exceed 3/4 of sort_cap.  When the hits overflow the buffer the
+// group keeps its leading queries whose hits fit (hits arrive query by
+// query), and the next group starts at the first query left out and walks
+// it again; the wave's row budget shrinks to what fitted and grows back by
+// an eighth per group that fits, so that dense regions do not repeat the
+// waste.  Only a query whose own hits exceed the buffer is left to the
+// write pass.  A smaller buffer buys occupancy (LDS) at the price of more
+// overflows.  On the uneven-radius workload (1 M queries, ms per step):
+// 2 x sort_cap keys, an overflowing group left whole to the write pass,
+// 1.154; 1.5 x 1.092, 1.25 x 1.062; keeping the leading queries, 1.25 x
+// 1.028, 1 x 1.006 (0.988 within 80 VGPRs), 7/8 x 1.039; rows up to 7/8 of
+// sort_cap at 1 x, 1.004.
 
 // Per-wave LDS of the grouped kernel: slot data (kGroup x 80 B), 32 words of
 // per-slot counters, the 64-word owner map, then (stash) the hit keys in
 // arrival order, the same by bucket, and the bucket counts, or (no stash)
 // sort_cap 16-byte row records.
+__host__ __device__ constexpr uint32_t group_hitcap(uint32_t cap) { return cap * kHitEighths / 8; }
+__host__ __device__ constexpr uint32_t group_rows(uint32_t cap) { return cap * kRowEighths / 8; }
+// rows per chunk of the walk (at most kLayers x 64): their 16-byte records
+// fill the bucket buffer and the bucket counts, both free until the sort
+__host__ __device__ constexpr uint32_t group_chunk(uint32_t cap) {
+    return group_hitcap(cap) * 12 / 16 < 256u ? group_hitcap(cap) * 12 / 16 : 256u;
+}
 __host__ __device__ constexpr size_t group_lds_per_wave(bool stash, uint32_t cap) {
-    return 640 + 128 + 256 + (stash ? (size_t)cap * 2 * 20 : (size_t)cap * 16);
+    return 640 + 128 + 256 + (stash ? (size_t)group_hitcap(cap) * 20 : (size_t)group_chunk(cap) * 16);
 }
 
 // dist^2 field of a group hit key (slot | dist^2 | id)
@@ -1217,12 +1232,17 @@ __device__ __forceinline__ uint64_t key_d2(uint64_t k, uint32_t idbits, uint32_t
     return (k >> idbits) & ((1ull << d2bits) - 1ull);
 }
 
+// At most 80 VGPRs, so that six waves share each SIMD (the LDS of a
+// sort_cap 256 hit buffer allows as many).
 template <int METHOD, bool TLDS, bool STASH, bool FROM_LIST>
-__global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, QArgs A) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void group_count_kernel(LatArgs L,
+                                                                                                 TabArgs T,
+                                                                                                 QArgs A) {
     extern __shared__ __align__(16) char smem[];
     const uint32_t* tab_lds = stage_table<TLDS>(T, smem);
     const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
-    const uint32_t hitcap = 2 * A.sort_cap, group_rows = A.sort_cap - A.sort_cap / 4;  // hitcap <= kMaxHitCap
+    const uint32_t hitcap = group_hitcap(A.sort_cap), grows = group_rows(A.sort_cap);  // hitcap <= kMaxHitCap
+    uint32_t rlim = grows;  // rows per group (shrinks where hits overflow the buffer)
     char* wb = smem + table_lds_bytes<TLDS>(T) + (size_t)wave * group_lds_per_wave(STASH, A.sort_cap);
     uint4* qp = (uint4*)wb;                    // per slot: centre + table start, r^2 + self + rows,
                                                // cube extent, flags + row, W/2 - centre + self
@@ -1249,7 +1269,7 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
         for (uint32_t g0 = b, ng = 0; g0 < e; g0 += ng) {
             const uint32_t cand = min(kGroup, e - g0);
             // ---- slots: lane l < cand looks at query g0 + l (of the list);
-            // the group keeps the leading slots whose rows fit group_rows (at
+            // the group keeps the leading slots whose rows fit rlim (at
             // least one)
             const uint32_t qi = FROM_LIST ? (lane < cand ? A.list[g0 + lane] : 0u) : g0 + lane;
             uint32_t rows = 0, row = 0;
@@ -1278,16 +1298,12 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
             }
             {
                 const uint32_t pre_incl = scan_add(rows);
-                const uint64_t fits = __ballot(lane < cand && pre_incl <= group_rows);
+                const uint64_t fits = __ballot(lane < cand && pre_incl <= rlim);
                 ng = max(1u, (uint32_t)__popcll(fits));
             }
             if (lane >= ng) {
                 rows = 0;
                 mine = extra = invalid = false;
-            }
-            if (invalid) {
-                A.row_ptr[row] = 0;
-                if (STASH) A.soff[qi] = 0u;
             }
             if (mine) {
                 const uint64_t r2 = (uint64_t)d1.x * d1.x;
@@ -1302,14 +1318,6 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
                 p[4] = make_uint4(aw.half[0] - d0.x, aw.half[1] - d0.y, aw.half[2] - d0.z, self);
             }
             if (lane < kGroup) cnt[lane] = 0u;
-            {
-                // the queries left to the one-query-per-wave kernel
-                const uint64_t xm = __ballot(extra);
-                uint32_t xb = 0;
-                if (xm != 0 && lane == 0) xb = atomicAdd(A.xq_count, (uint32_t)__popcll(xm));
-                xb = uni(xb);
-                if (extra) A.xq[xb + lanes_below(xm)] = qi;
-            }
             wave_sync();
             const uint32_t incl = scan_add(rows);
             const uint32_t R = lane_val(incl, 63);
@@ -1321,8 +1329,9 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
             // kept in LDS; then the chunk's candidates, 64 per step, in one
             // stream, with the next step's records loaded while this step's
             // are tested.
-            for (uint32_t rb = 0; rb < R; rb += A.sort_cap) {
-                const uint32_t clen = min(A.sort_cap, R - rb);
+            const uint32_t CH = group_chunk(A.sort_cap);  // <= kLayers x 64
+            for (uint32_t rb = 0; rb < R; rb += CH) {
+                const uint32_t clen = min(CH, R - rb);
                 uint32_t cex[kLayers], cin[kLayers];
 #pragma unroll
                 for (uint32_t k = 0; k < kLayers; ++k) cex[k] = cin[k] = 0u;
@@ -1385,7 +1394,7 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
                     const uint32_t ce = carry + ci - tl;
                     // per row: position bases of its two ranges, the slot
                     // where the second starts, and the query slot
-                    rinfo[k * 64u + lane] = make_uint4(r.st0 - ce, ce + r.cnt0, r.st1 - (ce + r.cnt0), gs);
+                    if (act) rinfo[k * 64u + lane] = make_uint4(r.st0 - ce, ce + r.cnt0, r.st1 - (ce + r.cnt0), gs);
 #pragma unroll
                     for (uint32_t j = 0; j < kLayers; ++j) {
                         cex[j] = j == k ? ce : cex[j];
@@ -1468,13 +1477,40 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
                 wave_sync();
             }
             // ---- row sizes
-            uint32_t nq = 0;
-            if (mine) {
-                nq = cnt[lane];
-                A.row_ptr[row] = (int64_t)nq;
+            uint32_t nq = mine ? cnt[lane] : 0u;
+            uint32_t total = hcount;
+            if (STASH && hcount > hitcap && ng > 1) {
+                // the hit buffer overflowed: keep the leading slots whose hits
+                // fit (hits arrive slot by slot, so theirs are the buffer's
+                // first keys); the next group starts at the first slot left
+                // out and walks it again
+                const uint32_t hi = scan_add(nq);
+                ng = max(1u, (uint32_t)__popcll(__ballot(lane < ng && hi <= hitcap)));
+                if (lane >= ng) {
+                    mine = extra = invalid = false;
+                    nq = 0u;
+                }
+                total = lane_val(hi, ng - 1u);
+                // later groups of this wave take no more rows than fitted
+                // here, and grow back by an eighth per group that fits
+                rlim = max(1u, lane_val(incl, ng - 1u));
+            } else if (STASH) {
+                rlim = min(grows, rlim + max(1u, grows / 8u));
             }
+            if (invalid) {
+                A.row_ptr[row] = 0;
+                if (STASH) A.soff[qi] = 0u;
+            }
+            {
+                // the queries left to the one-query-per-wave kernel
+                const uint64_t xm = __ballot(extra);
+                uint32_t xb = 0;
+                if (xm != 0 && lane == 0) xb = atomicAdd(A.xq_count, (uint32_t)__popcll(xm));
+                xb = uni(xb);
+                if (extra) A.xq[xb + lanes_below(xm)] = qi;
+            }
+            if (mine) A.row_ptr[row] = (int64_t)nq;
             if (STASH) {
-                const uint32_t total = hcount;
                 bool ok = total <= hitcap;
                 if (ok && total > 0 && cur + total > lim) {
                     ok = false;
@@ -1510,9 +1546,9 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
                         const uint32_t bi = min((uint32_t)((float)key_d2(k, idbits, d2bits) * qsc[sl]), n - 1u);
                         return qst[sl] + bi;
                     };
-                    uint32_t slot[kMaxHitCap / 64];
+                    uint32_t slot[(kMaxHitCap + 63) / 64];
 #pragma unroll
-                    for (uint32_t k = 0; k < kMaxHitCap / 64; ++k) {
+                    for (uint32_t k = 0; k < (kMaxHitCap + 63) / 64; ++k) {
                         const uint32_t t = lane + 64u * k;
                         if (t < total) slot[k] = atomicAdd(&hh[bucket(hb[t])], 1u);
                     }
@@ -1532,7 +1568,7 @@ __global__ __launch_bounds__(256) void group_count_kernel(LatArgs L, TabArgs T, 
                         }
                     wave_sync();
 #pragma unroll
-                    for (uint32_t k = 0; k < kMaxHitCap / 64; ++k) {
+                    for (uint32_t k = 0; k < (kMaxHitCap + 63) / 64; ++k) {
                         const uint32_t t = lane + 64u * k;
                         if (t < total) {
                             const uint64_t key = hb[t];
