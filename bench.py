@@ -166,6 +166,24 @@ def leg_c2(args, out):
     log(f"persistent: {ms:.3f} ms/step; build {phases[0]:.3f} count {phases[1]:.3f} write {phases[2]:.3f} ms; "
         f"count kernel {kern[0]:.3f} write kernel {kern[1]:.3f} ms")
 
+    # cells and candidate objects per query, sphere tables against the
+    # bin-lattice cube: the per-query statistics of one count pass each
+    # (untimed; the rows found above are kept on the host)
+    cells = {}
+    for name, meth in (("sphere", sphidx.METHOD_SPHERE), ("cube", sphidx.METHOD_CUBE)):
+        st = torch.zeros(4 * n, dtype=torch.int32, device="cuda")
+        sphidx.count(lat, tab, q, buf, sphidx.LaunchConfig(method=meth, stats=st))
+        a = st.cpu().numpy().view(np.uint32).reshape(n, 4).astype(np.float64)
+        cells[name] = {"rows_walked": round(float(a[:, 0].mean()), 3), "cells_kept": round(float(a[:, 1].mean()), 3),
+                       "candidates": round(float(a[:, 2].mean()), 3)}
+        del st
+    cells["cube_cells"] = cells["cube"]["cells_kept"]
+    cells["hits"] = round(total / n, 3)
+    cells["kept_over_cube"] = round(cells["sphere"]["cells_kept"] / cells["cube"]["cells_kept"], 4)
+    cells["candidates_over_cube"] = round(cells["sphere"]["candidates"] / cells["cube"]["candidates"], 4)
+    out["cells_per_query"] = cells
+    log(f"per query: sphere {cells['sphere']}, cube {cells['cube']}, hits {cells['hits']}")
+
     if not args.no_baselines:
         k2 = max(3, args.steps // 2)
         two_walks = dataclasses.replace(tuned, no_stash=1)
