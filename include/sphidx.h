@@ -358,6 +358,34 @@ sphidx_status sphidx_move_agents_counted(const sphidx_lattice_desc* desc, uint64
                                          uint32_t* x_dev, uint32_t* y_dev, uint32_t* z_dev, uint32_t n,
                                          void* stream);
 
+/* Incremental maintenance of a lattice of moving objects (Section I: the
+ * objects' cells are kept up to date as they move, instead of indexing them
+ * again from their coordinates).  The lattice's own records are moved in
+ * place, in their sorted order, by the displacement of sphidx_move_agents
+ * (keyed by each record's object id), written to scratch_dev, and the
+ * lattice is rebuilt from them by the same counting sort.  Objects that stay
+ * in their cell, most of them at small steps, keep their place in memory
+ * order, so the rebuild's atomics and stores fall on neighbouring addresses,
+ * and no by-id coordinate array is read or written.
+ *   lat          a lattice built with sphidx_build_lattice (its object ids
+ *                are 0 .. n-1); after the call it holds the moved objects
+ *   step, step_dev  as in sphidx_move_agents(_counted): with step_dev the
+ *                step is read there and the counter advanced afterwards
+ *   scratch_dev  device buffer of at least 16 * n bytes, 16-byte aligned,
+ *                owned by the caller (free for other use between calls)
+ * The object ids, cell starts and cell contents equal those of
+ * sphidx_move_agents followed by sphidx_build_lattice on by-id arrays
+ * (the order inside a cell can differ, as between any two builds).
+ * Errors: SPHIDX_ERR_INVALID_ARG (null lattice, missing or misaligned
+ * scratch), SPHIDX_ERR_CAPACITY (scratch too small). */
+sphidx_status sphidx_move_resident(sphidx_lattice* lat, uint64_t seed, uint32_t step, uint32_t* step_dev,
+                                   void* scratch_dev, size_t scratch_bytes, void* stream);
+
+/* The lattice's objects as by-id coordinates: x_dev[id] = record x (normalised:
+ * cyclic axes wrapped), and so on, for the n objects of the last build. */
+sphidx_status sphidx_lattice_positions(const sphidx_lattice* lat, uint32_t* x_dev, uint32_t* y_dev, uint32_t* z_dev,
+                                       void* stream);
+
 /* out_dev[0] = sum of row sizes, out_dev[1] = sum_i mix64((i << 32) | size_i)
  * (mod 2^64), from row_ptr (Q + 1 entries).  out_dev is uint64[2]. */
 sphidx_status sphidx_count_checksum(const int64_t* row_ptr_dev, uint32_t Q, uint64_t* out_dev, void* stream);

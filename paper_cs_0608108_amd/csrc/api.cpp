@@ -557,6 +557,32 @@ sphidx_status sphidx_move_agents_counted(const sphidx_lattice_desc* desc, uint64
     return dev_err(launch_move_agents(*desc, seed, 0, step_dev, x_dev, y_dev, z_dev, n, (hipStream_t)stream));
 }
 
+sphidx_status sphidx_move_resident(sphidx_lattice* lat, uint64_t seed, uint32_t step, uint32_t* step_dev,
+                                   void* scratch_dev, size_t scratch_bytes, void* stream) {
+    if (!lat) return SPHIDX_ERR_INVALID_ARG;
+    const uint32_t n = lat->n;
+    if (n > 0 && (!scratch_dev || (uintptr_t)scratch_dev % 16)) return SPHIDX_ERR_INVALID_ARG;
+    if (scratch_bytes < (size_t)n * sizeof(uint4)) return SPHIDX_ERR_CAPACITY;
+    const hipStream_t st = (hipStream_t)stream;
+    uint4* moved = (uint4*)scratch_dev;
+    hipError_t e = hipSuccess;
+    if (step_dev) {
+        e = launch_move_records(lat->desc, seed, step_dev, lat->pts, moved, n, st);
+    } else {
+        // a host step: the same kernel with the step as an argument
+        e = launch_move_records_at(lat->desc, seed, step, lat->pts, moved, n, st);
+    }
+    if (e == hipSuccess) e = launch_build_records(lat, moved, n, st);
+    return dev_err(e);
+}
+
+sphidx_status sphidx_lattice_positions(const sphidx_lattice* lat, uint32_t* x_dev, uint32_t* y_dev, uint32_t* z_dev,
+                                       void* stream) {
+    if (!lat) return SPHIDX_ERR_INVALID_ARG;
+    if (lat->n > 0 && (!x_dev || !y_dev || !z_dev)) return SPHIDX_ERR_INVALID_ARG;
+    return dev_err(launch_records_to_ids(lat->pts, lat->n, x_dev, y_dev, z_dev, (hipStream_t)stream));
+}
+
 sphidx_status sphidx_count_checksum(const int64_t* row_ptr_dev, uint32_t Q, uint64_t* out_dev, void* stream) {
     if (!row_ptr_dev || !out_dev) return SPHIDX_ERR_INVALID_ARG;
     return dev_err(launch_count_checksum(row_ptr_dev, Q, out_dev, (hipStream_t)stream));

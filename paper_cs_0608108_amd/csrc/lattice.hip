@@ -32,6 +32,7 @@ struct BuildArgs {
     const uint32_t* x;
     const uint32_t* y;
     const uint32_t* z;
+    const uint4* recs;  // rebuild from records: {x, y, z, id} by position
     uint32_t* count;  // == cell_start storage
     uint32_t* rank;
     uint4* pts;
@@ -84,6 +85,29 @@ __global__ __launch_bounds__(256) void scatter_kernel(BuildArgs a) {
     uint32_t cell = object_cell(a, vx, vy, vz, bad);
     uint32_t pos = a.count[cell] + a.rank[i];
     a.pts[pos] = make_uint4(vx, vy, vz, i);
+}
+
+// The same two steps over records {x, y, z, id} (the lattice's own, moved in
+// place): the rank is kept per record position, and the record keeps its id.
+__global__ __launch_bounds__(256) void hist_records_kernel(BuildArgs a) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const uint4 P = a.recs[i];
+    uint32_t vx = P.x, vy = P.y, vz = P.z;
+    bool bad;
+    uint32_t cell = object_cell(a, vx, vy, vz, bad);
+    if (bad) atomicOr(a.status, SPHIDX_FLAG_RANGE);
+    a.rank[i] = atomicAdd(&a.count[cell], 1u);
+}
+
+__global__ __launch_bounds__(256) void scatter_records_kernel(BuildArgs a) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const uint4 P = a.recs[i];
+    uint32_t vx = P.x, vy = P.y, vz = P.z;
+    bool bad;
+    uint32_t cell = object_cell(a, vx, vy, vz, bad);
+    a.pts[a.count[cell] + a.rank[i]] = make_uint4(vx, vy, vz, P.w);
 }
 
 // Packed region cell of a sorted record (normalised, inside the region).
@@ -263,6 +287,7 @@ BuildArgs build_args(const sphidx_lattice* lat, const uint32_t* x, const uint32_
     a.x = x;
     a.y = y;
     a.z = z;
+    a.recs = nullptr;
     a.count = lat->cell_start;
     a.rank = lat->rank;
     a.pts = lat->pts;
@@ -311,3 +336,20 @@ hipError_t launch_scan_i64(int64_t* data, uint32_t n, void* tmp, hipStream_t st)
 }
 
 size_t scan_u32_tmp_words(size_t n) { return (n + kScanBlock - 1) / kScanBlock + 2; }
+
+// Rebuild from records (incremental maintenance): the same counting sort over
+// `recs` (n records, not the lattice's own array) into the lattice's records.
+hipError_t launch_build_records(const sphidx_lattice* lat, const uint4* recs, uint32_t n, hipStream_t st) {
+    BuildArgs a = build_args(lat, nullptr, nullptr, nullptr, n);
+    a.recs = recs;
+    size_t ncount = (size_t)lat->ncells + 2;
+    hipError_t e = launch_fill_u32(lat->cell_start, 0u, ncount + 1, st);
+    if (e != hipSuccess) return e;
+    uint32_t blocks = (n + 255) / 256;
+    if (n > 0) hist_records_kernel<<<blocks, 256, 0, st>>>(a);
+    e = scan_exclusive<uint32_t>(lat->cell_start, ncount, lat->scan_tmp, st);
+    if (e != hipSuccess) return e;
+    if (n > 0) scatter_records_kernel<<<blocks, 256, 0, st>>>(a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_cell_list(lat, st);
+}

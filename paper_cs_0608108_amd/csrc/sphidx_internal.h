@@ -166,6 +166,13 @@ size_t scan_i64_tmp_bytes(uint32_t n);
 hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const QArgs& q,
                              uint32_t waves_per_block, uint32_t blocks_per_cu, hipStream_t st,
                              hipEvent_t ev_begin, hipEvent_t ev_end);
+hipError_t launch_build_records(const sphidx_lattice* lat, const uint4* recs, uint32_t n, hipStream_t st);
+hipError_t launch_move_records(const sphidx_lattice_desc& d, uint64_t seed, uint32_t* step_dev, const uint4* src,
+                               uint4* dst, uint32_t n, hipStream_t st);
+hipError_t launch_move_records_at(const sphidx_lattice_desc& d, uint64_t seed, uint32_t step, const uint4* src,
+                                  uint4* dst, uint32_t n, hipStream_t st);
+hipError_t launch_records_to_ids(const uint4* pts, uint32_t n, uint32_t* x, uint32_t* y, uint32_t* z,
+                                 hipStream_t st);
 hipError_t launch_move_agents(const sphidx_lattice_desc& d, uint64_t seed, uint32_t step, uint32_t* step_dev,
                               uint32_t* x, uint32_t* y, uint32_t* z, uint32_t n, hipStream_t st);
 hipError_t launch_count_checksum(const int64_t* row_ptr, uint32_t Q, uint64_t* out, hipStream_t st);

@@ -92,6 +92,8 @@ SIGNATURES = {
     "sphidx_cube_scan_knn": (ctypes.c_int, [P, ctypes.POINTER(Queries), ctypes.POINTER(CSRDesc), P]),
     "sphidx_move_agents": (ctypes.c_int, [ctypes.POINTER(LatticeDesc), U64, U32, P, P, P, U32, P]),
     "sphidx_move_agents_counted": (ctypes.c_int, [ctypes.POINTER(LatticeDesc), U64, P, P, P, P, U32, P]),
+    "sphidx_move_resident": (ctypes.c_int, [P, U64, U32, P, P, ctypes.c_size_t, P]),
+    "sphidx_lattice_positions": (ctypes.c_int, [P, P, P, P, P]),
     "sphidx_count_checksum": (ctypes.c_int, [P, U32, P, P]),
     "sphidx_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sphidx_version": (ctypes.c_char_p, []),
@@ -479,6 +481,19 @@ def move_agents(desc: LatticeDesc, seed, step, x, y, z, stream=None):
 def move_agents_counted(desc: LatticeDesc, seed, step_dev, x, y, z, stream=None):
     check(load().sphidx_move_agents_counted(ctypes.byref(desc), int(seed), _ptr(step_dev), _ptr(x), _ptr(y),
                                             _ptr(z), int(x.numel()), _stream(stream)), "move_agents_counted")
+
+
+def move_resident(lat, seed, scratch, step=0, step_dev=None, stream=None):
+    """Move the lattice's own records (incremental maintenance) and rebuild
+    from them; `scratch` is a device tensor of at least 16 * n bytes."""
+    check(load().sphidx_move_resident(lat.handle, int(seed), int(step), None if step_dev is None else _ptr(step_dev),
+                                      _ptr(scratch), int(scratch.numel() * scratch.element_size()), _stream(stream)),
+          "move_resident")
+
+
+def lattice_positions(lat, x, y, z, stream=None):
+    """By-id coordinates of the lattice's objects into device arrays x, y, z."""
+    check(load().sphidx_lattice_positions(lat.handle, _ptr(x), _ptr(y), _ptr(z), _stream(stream)), "lattice_positions")
 
 
 def count_checksum(row_ptr, Q, out, stream=None):

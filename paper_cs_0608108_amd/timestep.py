@@ -2,7 +2,10 @@
 
 One step = move every agent (seeded counter-hash displacement, read from a
 device step counter) -> rebuild the lattice -> all-agents radius query
-(count pass, scan, write pass) -> checksum of the per-row counts.  Every
+(count pass, scan, write pass) -> checksum of the per-row counts.  With
+`resident=True` the first two are one incremental update instead: the
+lattice's own sorted records are moved and the lattice is rebuilt from them,
+and the by-id positions are written only when asked for.  Every
 call is a stream-ordered kernel launch with no host synchronisation, no
 device allocation and no memset, so the whole step is captured once as a
 HIP graph and replayed.  The output buffers are sized once from the first
@@ -19,7 +22,7 @@ from . import sphidx
 
 class AgentSim:
     def __init__(self, log2_cells, frac_bits, cyclic_mask, pts, r_fx, seed, subcell_bits=2, headroom=1.25,
-                 launch: sphidx.LaunchConfig | None = None, flags=0, cell_list=False):
+                 launch: sphidx.LaunchConfig | None = None, flags=0, cell_list=False, resident=False):
         self.n = len(pts[0])
         self.desc = sphidx.desc_of(log2_cells, frac_bits, cyclic_mask)
         self.lat = sphidx.Lattice(log2_cells, frac_bits, cyclic_mask, self.n)
@@ -41,12 +44,18 @@ class AgentSim:
         # the stash lets the count pass keep the sorted rows: the write pass
         # then copies them instead of walking the tables a second time
         self.buf = sphidx.QueryBuffers(self.n, cap, want_dist2=False, stash_pairs=cap)
+        self.resident = bool(resident)
+        # moved records of the incremental update (16 bytes per agent)
+        self.scratch = torch.empty(4 * self.n if resident else 0, dtype=torch.int32, device="cuda")
         self.graph = None
         self.steps_done = 0
 
     def _step_kernels(self):
-        sphidx.move_agents_counted(self.desc, self.seed, self.step_dev, *self.pos)
-        self.lat.build(*self.pos)
+        if self.resident:
+            sphidx.move_resident(self.lat, self.seed, self.scratch, step_dev=self.step_dev)
+        else:
+            sphidx.move_agents_counted(self.desc, self.seed, self.step_dev, *self.pos)
+            self.lat.build(*self.pos)
         sphidx.count(self.lat, self.tab, self.q, self.buf, self.launch)
         sphidx.write(self.lat, self.tab, self.q, self.buf, self.launch)
         sphidx.count_checksum(self.buf.row_ptr, self.n, self.chk)
@@ -76,6 +85,8 @@ class AgentSim:
         return int(c[0]), int(c[1])
 
     def positions(self):
+        if self.resident:
+            sphidx.lattice_positions(self.lat, *self.pos)
         return tuple(sphidx.to_host_u32(p) for p in self.pos)
 
     def csr(self):

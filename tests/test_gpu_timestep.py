@@ -32,6 +32,10 @@ def sx():
     # volume at 150 agents in 32^3 cells, or forced for every query
     (7, (5, 5, 5), 150, 15, {"method": 2, "cell_list": True}),
     (5, (5, 4, 6), 3000, 16, {"method": 3, "cell_list": True}),
+    # incremental maintenance: the lattice's own records are moved and the
+    # lattice rebuilt from them (by-id positions only when read)
+    (7, (5, 5, 5), 32768, 17, {"resident": True}),
+    (5, (5, 4, 6), 20000, 18, {"resident": True, "grouped": 1, "waves_per_block": 2}),
 ])
 def test_timestep_graph_replays_match_oracle(sx, orc, mask, log2, n, seed, launch):
     import torch
@@ -44,7 +48,9 @@ def test_timestep_graph_replays_match_oracle(sx, orc, mask, log2, n, seed, launc
     say(f"timestep mask={mask} log2={log2} n={n} seed={seed} launch={launch}")
     launch = dict(launch)
     cell_list = launch.pop("cell_list", False)
-    sim = timestep.AgentSim(log2, F, mask, pts, r, seed, launch=sx.LaunchConfig(**launch), cell_list=cell_list)
+    resident = launch.pop("resident", False)
+    sim = timestep.AgentSim(log2, F, mask, pts, r, seed, launch=sx.LaunchConfig(**launch), cell_list=cell_list,
+                            resident=resident)
     L = orc.Lattice(log2, F, mask)
     cur = tuple(np.asarray(a, dtype=np.uint32) for a in pts)
 
@@ -83,3 +89,61 @@ def test_timestep_graph_replays_match_oracle(sx, orc, mask, log2, n, seed, launc
     torch.cuda.synchronize()
     check(step, full=True)
     assert sim.steps_done == step + 1
+
+
+def _cells_sorted(h):
+    """(cell, id) order of a lattice's records with their coordinates: the
+    order inside a cell is the build's own, so compare cell by cell."""
+    cs = h["cell_start"]
+    pos = np.arange(len(h["ids"]))
+    cell = np.searchsorted(cs, pos, side="right") - 1
+    o = np.lexsort((h["ids"], cell))
+    return cell[o], h["ids"][o], h["xs"][o], h["ys"][o], h["zs"][o]
+
+
+@pytest.mark.parametrize("mask", [7, 0, 5])
+def test_resident_move_equals_move_then_build(sx, mask):
+    """Incremental maintenance (Section I): moving the lattice's records and
+    rebuilding from them gives the cell starts, cell contents and positions
+    of moving the by-id arrays and building again, step after step; objects
+    outside a clipped region and unusable coordinates included."""
+    import torch
+
+    from gpu_util import tiny_points
+    rng = np.random.default_rng(170 + mask)
+    log2, F, seed = (5, 4, 5), 10, 23
+    pts = tiny_points(rng, log2, F, mask, 6000, outside=(mask != 7), invalid=(mask == 0))
+    n = len(pts[0])
+    desc = sx.desc_of(log2, F, mask)
+    dev_a = [sx.to_dev_u32(a) for a in pts]
+    dev_b = [sx.to_dev_u32(a) for a in pts]
+    lat_a = sx.Lattice(log2, F, mask, n)
+    lat_b = sx.Lattice(log2, F, mask, n)
+    lat_a.build(*dev_a)
+    lat_b.build(*dev_b)
+    step_a = torch.zeros(1, dtype=torch.int32, device="cuda")
+    step_b = torch.zeros(1, dtype=torch.int32, device="cuda")
+    scratch = torch.empty(4 * n, dtype=torch.int32, device="cuda")
+    out = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in range(3)]
+    for step in range(4):
+        say(f"resident mask={mask} step={step}")
+        if step < 3:
+            sx.move_agents_counted(desc, seed, step_a, *dev_a)
+            sx.move_resident(lat_b, seed, scratch, step_dev=step_b)
+        else:  # the host-step form
+            sx.move_agents(desc, seed, 40, *dev_a)
+            sx.move_resident(lat_b, seed, scratch, step=40)
+        lat_a.build(*dev_a)
+        ha, hb = lat_a.host_arrays(), lat_b.host_arrays()
+        assert np.array_equal(ha["cell_start"], hb["cell_start"]), step
+        for u, v in zip(_cells_sorted(ha), _cells_sorted(hb)):
+            assert np.array_equal(u, v), step
+        sx.lattice_positions(lat_b, *out)
+        for a in range(3):
+            assert np.array_equal(sx.to_host_u32(out[a]), sx.to_host_u32(dev_a[a])), (step, a)
+    assert int(step_b.item()) == 3
+    # scratch smaller than 16 bytes per object, or misaligned
+    with pytest.raises(sx.SphidxError):
+        sx.move_resident(lat_b, seed, scratch[: 4 * n - 1])
+    with pytest.raises(sx.SphidxError):
+        sx.move_resident(lat_b, seed, scratch[1:])

@@ -237,6 +237,8 @@ def test_build_validation(sx):
     assert lib.sphidx_build_lattice(lat, None, None, None, 101, None) == sx.ERR_CAPACITY
     assert lib.sphidx_build_lattice(lat, None, None, None, 5, None) == sx.ERR_INVALID_ARG
     assert lib.sphidx_build_lattice(None, None, None, None, 5, None) == sx.ERR_INVALID_ARG
+    assert lib.sphidx_move_resident(None, 1, 0, None, None, 0, None) == sx.ERR_INVALID_ARG
+    assert lib.sphidx_lattice_positions(None, None, None, None, None) == sx.ERR_INVALID_ARG
     lib.sphidx_lattice_destroy(lat)
 
 
