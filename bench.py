@@ -34,6 +34,7 @@ from __future__ import annotations
 
 import argparse
 import dataclasses
+import gc
 import hashlib
 import json
 import os
@@ -780,10 +781,16 @@ def main():
     out = {"metric": METRIC, "value": None, "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "int64", "data": "synthetic"}
+    # no cyclic garbage collection inside the timed regions: a collection
+    # pass while the GPU waits for the next launch lands in the events of
+    # that phase (one 35 ms pause showed up as 1.7 ms on a 20-step mean);
+    # garbage is collected between the legs instead
+    gc.disable()
     for x in legs:
         log(f"== leg {x}")
         {"c2": leg_c2, "knn": leg_knn, "timestep": leg_timestep, "serving": leg_serving,
          "sweep": leg_sweep, "tables": leg_tables}[x](args, out)
+        gc.collect()
     print(json.dumps(out))
 
 
