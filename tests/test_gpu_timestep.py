@@ -147,3 +147,18 @@ def test_resident_move_equals_move_then_build(sx, mask):
         sx.move_resident(lat_b, seed, scratch[: 4 * n - 1])
     with pytest.raises(sx.SphidxError):
         sx.move_resident(lat_b, seed, scratch[1:])
+
+
+def test_resident_move_on_an_empty_lattice(sx):
+    import torch
+    lat = sx.Lattice((4, 4, 4), 8, 7, 16)
+    e = torch.empty(0, dtype=torch.int32, device="cuda")
+    lat.build(e, e, e)
+    step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    sx.move_resident(lat, 5, e, step_dev=step)
+    sx.lattice_positions(lat, e, e, e)
+    h = lat.host_arrays()
+    assert len(h["ids"]) == 0 and (h["cell_start"] == 0).all()
+    assert int(step.item()) == 1
+    code, flags = lat.status()
+    assert code == sx.OK and flags == 0
