@@ -310,9 +310,10 @@ def leg_knn(args, out):
     tab = sphidx.Tables(lat, 2, cap)
     lat.build(*dev)
     q = sphidx.make_queries(n, None, cap, K, sphidx.MODE_KNN, 0)
-    # rows are at most K long: with stash room for all of them the count pass
-    # searches each row once and keeps it, and the write pass only copies
-    buf = sphidx.QueryBuffers(n, n * K, want_dist2=False, stash_pairs=n * K)
+    # rows are at most K long: with stash room the count pass searches each
+    # row once and keeps it, and the write pass only copies.  Rows searched
+    # in groups as radius rows keep their whole radius row (about 2K pairs)
+    buf = sphidx.QueryBuffers(n, n * K, want_dist2=False, stash_pairs=3 * n * K)
 
     def step_with(launch):
         def run():
@@ -320,8 +321,8 @@ def leg_knn(args, out):
             sphidx.query(lat, tab, q, buf, launch)
         return run
 
-    # the tuned launch for this workload (K-NN rows take neither the grouped
-    # count nor the interior shortcut, so those fields do not matter)
+    # the tuned launch for this workload (grouped: the K-NN rows are searched
+    # as radius rows at a first radius, several queries per wavefront)
     shape = dict(workload=w.name, n=n, k=K)
     if args.no_tune:
         cache = autotune.load_cache()
@@ -351,7 +352,7 @@ def leg_knn(args, out):
     rows = sample_of(n, 65536, 3)
     cen = tuple(sphidx.to_dev_u32(np.asarray(a)[rows]) for a in w.pts)
     qs = sphidx.make_queries(len(rows), cen, cap, K, sphidx.MODE_KNN, 0)
-    bs = sphidx.QueryBuffers(len(rows), len(rows) * K, want_dist2=False, stash_pairs=len(rows) * K)
+    bs = sphidx.QueryBuffers(len(rows), len(rows) * K, want_dist2=False, stash_pairs=3 * len(rows) * K)
     sub = {}
     for name, meth in (("sphere", sphidx.METHOD_SPHERE), ("cube", sphidx.METHOD_CUBE)):
         lq = sphidx.LaunchConfig(method=meth, **cfg)

@@ -312,12 +312,24 @@ __global__ __launch_bounds__(256) void setup_kernel(LatArgs L, TabArgs T, QArgs 
         fallback = valid && METHOD == kSphere && !usable;
         // (chosen per query: the main kernels take every walk themselves)
         to_list = valid && METHOD == kSphere && !sphere && A.select != 1u;
-        uint32_t tb = 0, tend = 0;
+        uint32_t tb = 0, tend = 0, kb = 0, kend = 0;
         if (sphere && valid) {
             // row tables are specialised on the (y, z) sub-cell position
             const uint32_t cls = ((q[1] & (e - 1u)) >> (L.F - T.s)) | (((q[2] & (e - 1u)) >> (L.F - T.s)) << T.s);
             tb = T.cstart[cls];
             tend = T.rindex[(size_t)cls * T.nr + j];
+            if (knn) {
+                // K-NN: a first search radius expected to hold about 2K
+                // objects at the home cell's density (the lattice mean as a
+                // floor), and its table prefix; the grouped count searches
+                // it as a radius row and keeps the first K when it holds K
+                const uint32_t home = pack_cell(L, q[0] >> L.F, q[1] >> L.F, q[2] >> L.F);
+                const float dens = fmaxf((float)L.n / (float)L.ncells, (float)(L.cs[home + 1] - L.cs[home]));
+                const float rho = 1.25f * (float)e * cbrtf(0.2387f * (float)k / fmaxf(dens, 1e-6f));
+                kb = rho >= (float)r ? r : max(1u, (uint32_t)rho);
+                const uint32_t jb = (uint32_t)(((uint64_t)kb + (1u << T.rshift) - 1u) >> T.rshift);
+                kend = T.rindex[(size_t)cls * T.nr + jb];
+            }
         }
         if (list) {
             // the walk takes nn[1] * nn[2] entries: the whole list
@@ -334,7 +346,9 @@ __global__ __launch_bounds__(256) void setup_kernel(LatArgs L, TabArgs T, QArgs 
         uint4* d = A.desc + 4 * (size_t)i;
         d[0] = make_uint4(q[0], q[1], q[2], row);
         d[1] = make_uint4(r, k, flags, tb);
-        d[2] = make_uint4(tend, ncube, nn[0], nn[1]);
+        // (sphere K-NN queries walk no cube: its fields carry the first radius)
+        const bool kfirst = sphere && valid && knn;
+        d[2] = make_uint4(tend, kfirst ? kb : ncube, kfirst ? kend : nn[0], nn[1]);
         d[3] = make_uint4((uint32_t)lo3[0], (uint32_t)lo3[1], (uint32_t)lo3[2], nn[2]);
     }
     // queries for the fallback list's kernels (bounding cube or cell list):
@@ -1234,7 +1248,9 @@ __device__ __forceinline__ uint64_t key_d2(uint64_t k, uint32_t idbits, uint32_t
 
 // At most 80 VGPRs, so that six waves share each SIMD (the LDS of a
 // sort_cap 256 hit buffer allows as many).
-template <int METHOD, bool TLDS, bool STASH, bool FROM_LIST>
+// KNN: K-NN queries of the batch are searched in the groups too (a radius
+// batch takes the variant without that code).
+template <int METHOD, bool TLDS, bool STASH, bool FROM_LIST, bool KNN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void group_count_kernel(LatArgs L,
                                                                                                  TabArgs T,
                                                                                                  QArgs A) {
@@ -1273,7 +1289,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
             // least one)
             const uint32_t qi = FROM_LIST ? (lane < cand ? A.list[g0 + lane] : 0u) : g0 + lane;
             uint32_t rows = 0, row = 0;
-            bool mine = false, extra = false, invalid = false;
+            bool mine = false, extra = false, invalid = false, knn = false;
             uint4 d0 = make_uint4(0, 0, 0, 0), d1 = d0, d2 = d0, d3 = d0;
             if (lane < cand) {
                 d0 = A.desc[4 * (size_t)qi];
@@ -1289,6 +1305,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                     invalid = true;
                 } else if (METHOD == kSphere && !sph) {
                     // counted by the fallback list's kernel
+                } else if (KNN && (flags & F_KNN)) {
+                    // K-NN (sphere tables, K up to a quarter of the buffer):
+                    // a radius row at the first search radius d2.y, the
+                    // table prefix d2.z; its first K are the K nearest when
+                    // it holds K (Section II.A: beyond the radius every
+                    // object is farther)
+                    const uint64_t b2 = (uint64_t)d2.y * d2.y;
+                    const uint32_t b2bits = b2 ? 64u - (uint32_t)__builtin_clzll(b2) : 0u;
+                    if (!sph || (flags & F_LIST) || b2bits > d2bits || 4u * d1.y > hitcap) {
+                        extra = true;
+                    } else {
+                        mine = true;
+                        knn = true;
+                        rows = d2.z + ((flags & F_OUTSIDE) ? 1u : 0u);
+                    }
                 } else if ((flags & (F_KNN | F_LIST)) || r2bits > d2bits) {
                     extra = true;
                 } else {
@@ -1303,16 +1334,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
             }
             if (lane >= ng) {
                 rows = 0;
-                mine = extra = invalid = false;
+                mine = extra = invalid = knn = false;
             }
             if (mine) {
-                const uint64_t r2 = (uint64_t)d1.x * d1.x;
+                const uint64_t r2 = (KNN && knn) ? (uint64_t)d2.y * d2.y : (uint64_t)d1.x * d1.x;
                 const uint32_t self = (A.qx == nullptr && (A.flags & SPHIDX_EXCLUDE_SELF)) ? qi : kMaxId;
                 uint4* p = qp + 5 * lane;
                 p[0] = make_uint4(d0.x, d0.y, d0.z, d1.w);
                 p[1] = make_uint4((uint32_t)r2, (uint32_t)(r2 >> 32), self, rows);
-                p[2] = make_uint4(d3.x, d3.y, d3.z, d2.z);
-                p[3] = make_uint4(d2.w, d3.w, d1.z, row);
+                // (a K-NN slot walks no cube: K and whether its search radius
+                // covers the cap take the cube fields)
+                p[2] = make_uint4(d3.x, d3.y, d3.z, (KNN && knn) ? d1.y : d2.z);
+                p[3] = make_uint4(d2.w, (KNN && knn) ? (d2.y >= d1.x ? 1u : 0u) : d3.w, d1.z, row);
                 // the candidate test's form of the centre: the minimum-image
                 // offset is ((p + (W/2 - c)) mod W) - W/2
                 p[4] = make_uint4(aw.half[0] - d0.x, aw.half[1] - d0.y, aw.half[2] - d0.z, self);
@@ -1487,7 +1520,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                 const uint32_t hi = scan_add(nq);
                 ng = max(1u, (uint32_t)__popcll(__ballot(lane < ng && hi <= hitcap)));
                 if (lane >= ng) {
-                    mine = extra = invalid = false;
+                    mine = extra = invalid = knn = false;
                     nq = 0u;
                 }
                 total = lane_val(hi, ng - 1u);
@@ -1496,6 +1529,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                 rlim = max(1u, lane_val(incl, ng - 1u));
             } else if (STASH) {
                 rlim = min(grows, rlim + max(1u, grows / 8u));
+            }
+            // K-NN rows: the first K, or every object when the search radius
+            // covers the cap; a row with fewer than K inside a smaller radius
+            // is searched again by the one-query-per-wave kernel
+            uint32_t nrow = nq;
+            if (KNN && knn) {
+                const uint32_t kk = qp[5 * lane + 2].w;
+                if (nq >= kk) {
+                    nrow = kk;
+                } else if (qp[5 * lane + 3].y == 0u) {
+                    mine = false;
+                    extra = true;
+                }
             }
             if (invalid) {
                 A.row_ptr[row] = 0;
@@ -1509,7 +1555,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                 xb = uni(xb);
                 if (extra) A.xq[xb + lanes_below(xm)] = qi;
             }
-            if (mine) A.row_ptr[row] = (int64_t)nq;
+            if (mine) A.row_ptr[row] = (int64_t)nrow;
             if (STASH) {
                 bool ok = total <= hitcap;
                 if (ok && total > 0 && cur + total > lim) {
@@ -1535,7 +1581,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                         qn[lane] = nq;
                         const uint4 pb = qp[5 * lane + 1];
                         const uint64_t r2 = (uint64_t)pb.x | ((uint64_t)pb.y << 32);
-                        qsc[lane] = (mine && r2 > 0) ? (float)nq / (float)r2 : 0.0f;
+                        qsc[lane] = (nq > 0 && r2 > 0) ? (float)nq / (float)r2 : 0.0f;
                     }
                     for (uint32_t t = lane; t < total; t += 64) hh[t] = 0u;
                     wave_sync();
@@ -2021,13 +2067,18 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
             // then the fallback list's (bounding cube); the rest through the
             // extra list, one query per wavefront
             const size_t gl = query_lds_bytes(q.stash ? 5 : 4, q.sort_cap, w, tb);
+            const bool gk = q.mode != SPHIDX_MODE_RADIUS;  // K-NN queries in the batch
             if (q.stash)
-                e = launch_ptr(either ? SPHIDX_PICK(group_count_kernel, variant, kEither, , true, false)
-                                      : SPHIDX_PICK(group_count_kernel, variant, kSphere, , true, false),
+                e = launch_ptr(gk ? (either ? SPHIDX_PICK(group_count_kernel, variant, kEither, , true, false, true)
+                                            : SPHIDX_PICK(group_count_kernel, variant, kSphere, , true, false, true))
+                                  : (either ? SPHIDX_PICK(group_count_kernel, variant, kEither, , true, false, false)
+                                            : SPHIDX_PICK(group_count_kernel, variant, kSphere, , true, false, false)),
                                q.Q, q, w, b, gl, st, L, T);
             else
-                e = launch_ptr(either ? SPHIDX_PICK(group_count_kernel, variant, kEither, , false, false)
-                                      : SPHIDX_PICK(group_count_kernel, variant, kSphere, , false, false),
+                e = launch_ptr(gk ? (either ? SPHIDX_PICK(group_count_kernel, variant, kEither, , false, false, true)
+                                            : SPHIDX_PICK(group_count_kernel, variant, kSphere, , false, false, true))
+                                  : (either ? SPHIDX_PICK(group_count_kernel, variant, kEither, , false, false, false)
+                                            : SPHIDX_PICK(group_count_kernel, variant, kSphere, , false, false, false)),
                                q.Q, q, w, b, gl, st, L, T);
             if (e == hipSuccess) e = mark(ev_end);
             if (e != hipSuccess) return e;
@@ -2037,8 +2088,8 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
                 qg.list_count = q.fb_count;
                 qg.list_set = kQFbCount;
                 const size_t gl0 = query_lds_bytes(q.stash ? 5 : 4, q.sort_cap, w, 0);
-                e = launch_ptr(q.stash ? (const void*)group_count_kernel<kCube, false, true, true>
-                                       : (const void*)group_count_kernel<kCube, false, false, true>,
+                e = launch_ptr(q.stash ? (const void*)group_count_kernel<kCube, false, true, true, false>
+                                       : (const void*)group_count_kernel<kCube, false, false, true, false>,
                                0, qg, w, b, gl0, st, L, T);
                 if (e != hipSuccess) return e;
             }

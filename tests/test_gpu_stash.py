@@ -194,6 +194,45 @@ def test_grouped_rows_beyond_one_chunk(sx, orc, mask, method):
 
 
 @pytest.mark.parametrize("mask", [7, 0])
+def test_grouped_knn_radius_rows_match_oracle(sx, orc, mask):
+    """K-NN rows searched in groups as radius rows at a first search radius:
+    dense clusters (rows kept from a radius that holds K), sparse regions and
+    small caps (fewer than K inside: searched again one query per wavefront,
+    or every object when the radius covers the cap), K above a quarter of
+    the hit buffer (one query per wavefront), buffers that overflow."""
+    from paper_cs_0608108_amd import synth
+    log2, F = (5, 5, 5), 12
+    spec = synth.LatticeSpec(log2, F, mask)
+    dense = synth.gaussian_cluster_points(spec, 24000, 41 + mask, 8, 1.5 * (1 << F))
+    sparse = synth.uniform_points(spec, 6000, 43 + mask)
+    pts = tuple(np.concatenate([dense[a], sparse[a]]).astype(np.uint32) for a in range(3))
+    lat = _world(sx, log2, F, mask, pts)
+    tab = sx.Tables(lat, 2, 4 << F)
+    n = len(pts[0])
+    rng = np.random.default_rng(300 + mask)
+    k = rng.choice(np.array([1, 4, 16, 40, 70], dtype=np.uint32), n)
+    cap = rng.integers(1 << (F - 2), (4 << F) + 1, n).astype(np.uint32)
+    keep = (sx.to_dev_u32(k), sx.to_dev_u32(cap))
+    q = sx.make_queries(n, None, keep[1], keep[0], sx.MODE_KNN, sx.EXCLUDE_SELF)
+    km = np.where(rng.random(n) < 0.5, k, 0).astype(np.uint32)
+    keep2 = sx.to_dev_u32(km)
+    qm = sx.make_queries(n, None, keep[1], keep2, sx.MODE_MIXED, 0)
+    g = orc.Grid(orc.Lattice(log2, F, mask), pts)
+    ref = g.knn(k, cap, flags=orc.EXCLUDE_SELF)
+    refm = g.mixed(km, cap)
+    g.close()
+    for cap_lds in (64, 256):
+        for frac in (1.0, 0.3, 0.0):
+            say(f"grouped knn mask={mask} sort_cap={cap_lds} stash={frac}")
+            ln = sx.LaunchConfig(grouped=1, sort_cap=cap_lds, waves_per_block=2)
+            got, _ = _cycle(sx, lat, tab, q, ln, True, True, frac)
+            assert_same(got, ref, f"grouped knn {cap_lds} {frac}")
+            got, _ = _cycle(sx, lat, tab, qm, ln, True, True, frac)
+            assert_same(got, refm, f"grouped mixed {cap_lds} {frac}")
+    del keep, keep2
+
+
+@pytest.mark.parametrize("mask", [7, 0])
 def test_stash_knn_rows_match_oracle(sx, orc, mask):
     """K-NN rows searched and kept by the count pass (K <= 64) beside rows the
     top-K pass still walks (K > 64, or no stash room), in K-NN and mixed
