@@ -193,6 +193,14 @@ __device__ __forceinline__ uint32_t pack_cell(const LatArgs& L, uint32_t x, uint
 }
 
 // One thread per query: centre, radius, K, method and walk extent.
+// K-NN first search radius in the grouped count, as a multiple of the radius
+// of the ball that holds K objects at the home cell's density (about 1.7K
+// expected inside).  Smaller leaves more rows short of K (searched again),
+// larger overflows more hit buffers; on clustered K = 16 the step took 5.93,
+// 5.29, 5.23, 5.24, 5.34, 5.53, 6.50 and 8.45 ms at 1.1, 1.15, 1.18, 1.2,
+// 1.22, 1.25, 1.35 and 1.5.
+constexpr float kFirstRadius = 1.2f;
+
 template <int METHOD>
 __global__ __launch_bounds__(256) void setup_kernel(LatArgs L, TabArgs T, QArgs A) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -319,13 +327,13 @@ __global__ __launch_bounds__(256) void setup_kernel(LatArgs L, TabArgs T, QArgs 
             tb = T.cstart[cls];
             tend = T.rindex[(size_t)cls * T.nr + j];
             if (knn) {
-                // K-NN: a first search radius expected to hold about 2K
+                // K-NN: a first search radius expected to hold about 1.7K
                 // objects at the home cell's density (the lattice mean as a
                 // floor), and its table prefix; the grouped count searches
                 // it as a radius row and keeps the first K when it holds K
                 const uint32_t home = pack_cell(L, q[0] >> L.F, q[1] >> L.F, q[2] >> L.F);
                 const float dens = fmaxf((float)L.n / (float)L.ncells, (float)(L.cs[home + 1] - L.cs[home]));
-                const float rho = 1.25f * (float)e * cbrtf(0.2387f * (float)k / fmaxf(dens, 1e-6f));
+                const float rho = kFirstRadius * (float)e * cbrtf(0.2387f * (float)k / fmaxf(dens, 1e-6f));
                 kb = rho >= (float)r ? r : max(1u, (uint32_t)rho);
                 const uint32_t jb = (uint32_t)(((uint64_t)kb + (1u << T.rshift) - 1u) >> T.rshift);
                 kend = T.rindex[(size_t)cls * T.nr + jb];
