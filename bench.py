@@ -244,8 +244,11 @@ def leg_c2(args, out):
     gather_bytes = 4 * n + 16 * n + 16 * n + 4 * total + 4 * total
     achieved = count_bytes / (kern[0] * 1e-3) / 1e9
     traffic = _stored_traffic()
+    # what bounds it instead: the share of the SIMDs' cycles spent issuing
+    # VALU instructions (SQ counters, same source hash), or None
+    valu = _stored_counters().get("count_kernel_valu_busy_frac")
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "valu_busy_frac": valu,
                 "kernel": ("group_count_kernel" if cfg.get("grouped") else "count_kernel")
                 + " (walk, test, sort, stash)",
                 "algorithmic_bytes": count_bytes, "kernel_ms": round(float(kern[0]), 4),
@@ -795,19 +798,23 @@ def main():
     print(json.dumps(out))
 
 
-def _stored_traffic():
-    """HBM bytes per write launch from committed rocprofv3 counter runs, used
-    only while the kernel source still has the hash recorded with them."""
+def _stored_counters():
+    """Counter figures of the count kernel from committed rocprofv3 runs
+    (profiles/traffic.json), used only while the kernel source still has the
+    hash recorded with them; {} otherwise."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
-        return None
+        return {}
     with open(p) as f:
         rec = json.load(f)
     src = os.path.join(ROOT, "paper_cs_0608108_amd", "csrc", "query.hip")
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if rec.get("query_hip_sha256_16") != h:
-        return None
-    return rec.get("count_kernel_bytes")
+    return rec if rec.get("query_hip_sha256_16") == h else {}
+
+
+def _stored_traffic():
+    """HBM bytes per launch of the count kernel (FETCH_SIZE + WRITE_SIZE)."""
+    return _stored_counters().get("count_kernel_bytes")
 
 
 if __name__ == "__main__":
