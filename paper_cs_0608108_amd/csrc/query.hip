@@ -1213,8 +1213,11 @@ __global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs 
 // and small radii fill whole steps.  Hits of the group are collected as
 // one 64-bit key (query slot, dist^2, id) each, and one bucket sort orders
 // the group's rows together; with the stash they are kept in one chunk.
-// Queries it does not take (K-NN, keys that would not fit 64 bits) go to
-// the extra list for the one-query-per-wave kernel.
+// K-NN queries (the KNN variant) take part as radius rows at their first
+// search radius and keep the first K.  Queries it does not take (K-NN of
+// large K or off the sphere tables, keys that would not fit 64 bits, rows
+// short of K inside the first radius) go to the extra list for the
+// one-query-per-wave kernel.
 
 constexpr uint32_t kGroup = 8, kGroupBits = 3;
 // hit buffer keys and rows per group, in eighths of sort_cap
