@@ -1222,7 +1222,7 @@ __global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs 
 constexpr uint32_t kGroup = 8, kGroupBits = 3;
 // hit buffer keys and rows per group, in eighths of sort_cap
 constexpr uint32_t kHitEighths = 8, kRowEighths = 6;
-constexpr uint32_t kMaxHitCap = 256 * kHitEighths / 8, kLayers = 4;
+constexpr uint32_t kMaxHitCap = 256 * kHitEighths / 8;
 // The group's hit buffer holds sort_cap keys, and a group ends before its
 // rows would exceed 3/4 of sort_cap.  When the hits overflow the buffer the
 // group keeps its leading queries whose hits fit (hits arrive query by
@@ -1243,11 +1243,13 @@ constexpr uint32_t kMaxHitCap = 256 * kHitEighths / 8, kLayers = 4;
 // sort_cap 16-byte row records.
 __host__ __device__ constexpr uint32_t group_hitcap(uint32_t cap) { return cap * kHitEighths / 8; }
 __host__ __device__ constexpr uint32_t group_rows(uint32_t cap) { return cap * kRowEighths / 8; }
-// rows per chunk of the walk (at most kLayers x 64): their 16-byte records
+// rows per chunk of the walk (at most 256): their 16-byte records
 // fill the bucket buffer and the bucket counts, both free until the sort
 __host__ __device__ constexpr uint32_t group_chunk(uint32_t cap) {
     return group_hitcap(cap) * 12 / 16 < 256u ? group_hitcap(cap) * 12 / 16 : 256u;
 }
+// 64-row layers of the largest chunk (sort_cap 256)
+constexpr uint32_t kLayers = (group_chunk(256) + 63) / 64;
 __host__ __device__ constexpr size_t group_lds_per_wave(bool stash, uint32_t cap) {
     return 640 + 128 + 256 + (stash ? (size_t)group_hitcap(cap) * 20 : (size_t)group_chunk(cap) * 16);
 }
