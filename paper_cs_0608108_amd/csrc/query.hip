@@ -1461,7 +1461,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                         if (cin[k] > cex[k] && cex[k] < cb + 64 && cin[k] > cb)
                             own[cex[k] > cb ? cex[k] - cb : 0] = k * 64u + lane + 1u;
                     wave_sync();
-                    const uint32_t o = scan_max(own[lane]) - 1u;
+                    // (a step past the end marks nothing: row 0 stands in)
+                    const uint32_t o = max(scan_max(own[lane]), 1u) - 1u;
                     const uint4 ri = rinfo[o];
                     const uint32_t g = cb + lane;
                     pos = (g < ri.y ? ri.x : ri.z) + g;
@@ -1501,23 +1502,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                     }
                 };
                 if (CT > 0) {
-                    uint32_t pos = 0, sl = 0;
-                    bool cact = locate(0, pos, sl);
-                    uint4 P = make_uint4(0u, 0u, 0u, kMaxId);
-                    if (cact) P = L.pts[pos];
-                    for (uint32_t cb = 0; cb < CT; cb += 64) {
-                        uint32_t npos = 0, nsl = 0;
-                        bool nact = false;
-                        uint4 NP = make_uint4(0u, 0u, 0u, kMaxId);
-                        if (cb + 64 < CT) {
-                            nact = locate(cb + 64, npos, nsl);
-                            if (nact) NP = L.pts[npos];
-                        }
-                        test(P, pos, sl, cact);
-                        P = NP;
-                        pos = npos;
-                        sl = nsl;
-                        cact = nact;
+                    // two register sets taken in turn: the step after the one
+                    // under test is already loading.  Lanes past the end load
+                    // record 0 (present whenever a candidate is) and test
+                    // nothing.
+                    uint32_t pa = 0, sa = 0, pb = 0, sb = 0;
+                    bool aa = locate(0, pa, sa), ab = false;
+                    uint4 PA = L.pts[aa ? pa : 0u], PB = PA;
+                    // (the step past the end, located once per chunk, has no
+                    // active lane)
+                    for (uint32_t cb = 0; cb < CT; cb += 128) {
+                        ab = locate(cb + 64, pb, sb);
+                        PB = L.pts[ab ? pb : 0u];
+                        test(PA, pa, sa, aa);
+                        if (cb + 64 >= CT) break;
+                        aa = locate(cb + 128, pa, sa);
+                        PA = L.pts[aa ? pa : 0u];
+                        test(PB, pb, sb, ab);
                     }
                 }
                 wave_sync();
