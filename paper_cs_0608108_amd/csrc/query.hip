@@ -683,23 +683,37 @@ __device__ __forceinline__ bool for_candidates(const LatArgs& L, uint32_t st0, u
     const uint32_t smx0 = st0 - excl;
     const uint32_t bnd = excl + cnt0;
     const uint32_t smx1 = st1 - bnd;
-    for (uint32_t cb = 0; cb < total; cb += 64) {
-        // mark where each lane's range starts inside this step's 64 slots,
-        // then a max-scan hands every slot to the lane that owns it
+    // slot cb + lane: mark where each lane's range starts inside the step's
+    // 64 slots, then a max-scan hands every slot to the lane that owns it (a
+    // step past the end marks nothing: lane 0 stands in)
+    auto locate = [&](uint32_t cb, uint32_t& p) -> bool {
+        wave_sync();
         own[lane] = 0;
         wave_sync();
         if (tl > 0 && excl < cb + 64 && incl > cb) own[excl > cb ? excl - cb : 0] = lane + 1;
         wave_sync();
-        const uint32_t o = scan_max(own[lane]) - 1u;
+        const uint32_t o = max(scan_max(own[lane]), 1u) - 1u;
         const uint32_t g = cb + lane;
         const uint32_t b = bperm(bnd, o);
         const uint32_t p0 = bperm(smx0, o) + g;
         const uint32_t p1 = bperm(smx1, o) + g;
-        const uint32_t p = g < b ? p0 : p1;
-        const bool act = g < total;
-        uint4 P = make_uint4(0u, 0u, 0u, kMaxId);
-        if (act) P = L.pts[p];
-        if (visit(act, p, P)) return true;
+        p = g < b ? p0 : p1;
+        return g < total;
+    };
+    // two register sets taken in turn: the step after the one being visited
+    // is already loading (lanes past the end load record 0, present whenever
+    // a candidate is, and visit nothing)
+    uint32_t pa = 0, pb = 0;
+    bool aa = locate(0, pa), ab = false;
+    uint4 PA = L.pts[aa ? pa : 0u], PB = PA;
+    for (uint32_t cb = 0; cb < total; cb += 128) {
+        ab = locate(cb + 64, pb);
+        PB = L.pts[ab ? pb : 0u];
+        if (visit(aa, pa, PA)) return true;
+        if (cb + 64 >= total) break;
+        aa = locate(cb + 128, pa);
+        PA = L.pts[aa ? pa : 0u];
+        if (visit(ab, pb, PB)) return true;
     }
     return false;
 }
