@@ -276,7 +276,12 @@ typedef struct {
                             recorded when Q = 0) */
     uint32_t no_stash;   /* 1: never keep rows in the workspace stash (see sphidx_csr) */
     uint32_t grouped;    /* 1: the count pass takes radius queries in groups of several per
-                            wavefront (persistent schedule); 0: one query per wavefront */
+                            wavefront (persistent schedule), and K-NN queries of the sphere
+                            tables with 4K <= sort_cap as radius rows at a first search
+                            radius (expected to hold about 1.7K objects), keeping the first
+                            K when it holds K (rows short of K are searched again one query
+                            per wavefront; the stash then needs about 2K pairs per query);
+                            0: one query per wavefront */
     /* METHOD_AUTO (Appendix: weighting factor and reversal distances).  A radius query takes
      * the sphere when select_weight/256 * (sphere cells) <= (cube cells), else the cube; then
      * the non-empty list instead if it holds fewer cells than the one chosen (plain counts).
