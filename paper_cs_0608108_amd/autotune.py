@@ -63,7 +63,7 @@ def time_config(run_once, reps=3):
 
 def candidates(schedule):
     if schedule == sphidx.SCHED_PERSISTENT:
-        for w, t, b, c, l, i, g in itertools.product((2, 4), (16, 64, 256), (4, 8), (128, 256), (0, 1), (1, 2),
+        for w, t, b, c, l, i, g in itertools.product((2, 4), (16, 64, 256), (4, 6, 8), (128, 256), (0, 1), (1, 2),
                                                      (0, 1)):
             yield dict(waves_per_block=w, tile=t, blocks_per_cu=b, sort_cap=c, table_in_lds=l, interior=i,
                        grouped=g)
