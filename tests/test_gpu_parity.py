@@ -26,6 +26,9 @@ def _launches(sx):
     return {
         "sphere-persistent": L(method=sx.METHOD_SPHERE, schedule=sx.SCHED_PERSISTENT),
         "sphere-grouped": L(method=sx.METHOD_SPHERE, schedule=sx.SCHED_PERSISTENT, grouped=1),
+        # grouped with the wholly-inside shortcut off: dense small worlds
+        # would otherwise take the one-query-per-wavefront count
+        "sphere-grouped-flat": L(method=sx.METHOD_SPHERE, schedule=sx.SCHED_PERSISTENT, grouped=1, interior=1),
         "cube-grouped": L(method=sx.METHOD_CUBE, schedule=sx.SCHED_PERSISTENT, grouped=1),
         "sphere-plain": L(method=sx.METHOD_SPHERE, schedule=sx.SCHED_PLAIN),
         "sphere-small-cap": L(method=sx.METHOD_SPHERE, schedule=sx.SCHED_PERSISTENT, sort_cap=64, tile=1,
@@ -226,7 +229,7 @@ def test_knn_clustered(sx, orc, K):
     ref = grid.knn(np.full(len(pts[0]), K, np.uint32), np.full(len(pts[0]), rmax, np.uint32))
     lat = lattice(sx, lat_s.log2_cells, lat_s.frac_bits, 7, pts)
     tab = sx.Tables(lat, 2, rmax)
-    for name in ("sphere-persistent", "sphere-plain", "sphere-small-cap", "cube"):
+    for name in ("sphere-persistent", "sphere-plain", "sphere-small-cap", "cube", "sphere-grouped"):
         got = run(sx, lat, tab, rmax, k=K, mode=sx.MODE_KNN, launch=_launches(sx)[name])
         assert_same(got, ref, f"knn K={K} {name}")
 
@@ -246,7 +249,8 @@ def test_knn_random_worlds_and_mixed_batches(sx, orc, mask):
     rmax = rng.integers(0, 4 * e, n).astype(np.uint32)
     for flags in (0, 1):
         ref = grid.knn(k, rmax, flags=flags)
-        for name in ("sphere-persistent", "sphere-small-cap", "cube-plain", "auto", "list-plain"):
+        for name in ("sphere-persistent", "sphere-small-cap", "cube-plain", "auto", "list-plain",
+                     "sphere-grouped-flat"):
             assert_same(run(sx, lat, tab, rmax, k=k, mode=sx.MODE_KNN, flags=flags, launch=_launches(sx)[name]),
                         ref, f"knn {name} flags={flags}")
     # mixed: K-NN where k > 0, radius otherwise; explicit centres
@@ -254,7 +258,8 @@ def test_knn_random_worlds_and_mixed_batches(sx, orc, mask):
     kk = np.where(rng.random(500) < 0.5, rng.integers(1, 30, 500), 0).astype(np.uint32)
     rr = rng.integers(0, 4 * e, 500).astype(np.uint32)
     ref = grid.mixed(kk, rr, queries=qs)
-    for name in ("sphere-persistent", "sphere-plain", "cube", "auto-grouped-weighted", "list-plain"):
+    for name in ("sphere-persistent", "sphere-plain", "cube", "auto-grouped-weighted", "list-plain",
+                 "sphere-grouped-flat"):
         assert_same(run(sx, lat, tab, rr, k=kk, mode=sx.MODE_MIXED, queries=qs, launch=_launches(sx)[name]),
                     ref, f"mixed {name}")
 
