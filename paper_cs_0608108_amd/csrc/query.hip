@@ -1604,27 +1604,41 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                 }
                 const uint32_t qs0 = scan_add(nq) - nq;
                 if (ok && total > 0) {
+                    // every hit's dist^2 is at most its slot's r^2: shifted
+                    // right by gsh, the largest r^2 of the group fits 24 bits,
+                    // so a bucket needs one 32-bit conversion
+                    uint64_t r2 = 0;
+                    if (lane < kGroup) {
+                        const uint4 pb = qp[5 * lane + 1];
+                        r2 = nq > 0 ? (uint64_t)pb.x | ((uint64_t)pb.y << 32) : 0ull;
+                    }
+                    const uint32_t rbits = lane_val(scan_max(r2 ? 64u - (uint32_t)__builtin_clzll(r2) : 0u), 63);
+                    const uint32_t gsh = rbits > 24u ? rbits - 24u : 0u;
+                    const uint32_t dsh = idbits + gsh, dmask = (1u << (rbits - gsh)) - 1u;
                     if (lane < kGroup) {
                         qst[lane] = qs0;
                         qn[lane] = nq;
-                        const uint4 pb = qp[5 * lane + 1];
-                        const uint64_t r2 = (uint64_t)pb.x | ((uint64_t)pb.y << 32);
-                        qsc[lane] = (nq > 0 && r2 > 0) ? (float)nq / (float)r2 : 0.0f;
+                        qsc[lane] = r2 > 0 ? (float)nq / (float)((uint32_t)(r2 >> gsh) + 1u) : 0.0f;
                     }
                     for (uint32_t t = lane; t < total; t += 64) hh[t] = 0u;
                     wave_sync();
-                    // bucket of a key: its slot's rows start + floor(n * d^2 / r^2)
+                    // bucket of a key: its slot's rows start + about
+                    // n * d^2 / r^2, below n, never smaller for a larger d^2
                     auto bucket = [&](uint64_t k) -> uint32_t {
                         const uint32_t sl = (uint32_t)(k >> (64u - kGroupBits));
-                        const uint32_t n = qn[sl];
-                        const uint32_t bi = min((uint32_t)((float)key_d2(k, idbits, d2bits) * qsc[sl]), n - 1u);
+                        const uint32_t d = (uint32_t)(k >> dsh) & dmask;
+                        const uint32_t bi = min((uint32_t)((float)d * qsc[sl]), qn[sl] - 1u);
                         return qst[sl] + bi;
                     };
-                    uint32_t slot[(kMaxHitCap + 63) / 64];
+                    uint32_t slot[(kMaxHitCap + 63) / 64], bk[(kMaxHitCap + 63) / 64];
 #pragma unroll
                     for (uint32_t k = 0; k < (kMaxHitCap + 63) / 64; ++k) {
                         const uint32_t t = lane + 64u * k;
-                        if (t < total) slot[k] = atomicAdd(&hh[bucket(hb[t])], 1u);
+                        bk[k] = 0u;
+                        if (t < total) {
+                            bk[k] = bucket(hb[t]);
+                            slot[k] = atomicAdd(&hh[bk[k]], 1u);
+                        }
                     }
                     wave_sync();
                     const uint32_t per = (total + 63u) >> 6;
@@ -1644,10 +1658,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
 #pragma unroll
                     for (uint32_t k = 0; k < (kMaxHitCap + 63) / 64; ++k) {
                         const uint32_t t = lane + 64u * k;
-                        if (t < total) {
-                            const uint64_t key = hb[t];
-                            hs[hh[bucket(key)] + slot[k]] = key;
-                        }
+                        if (t < total) hs[hh[bk[k]] + slot[k]] = hb[t];
                     }
                     wave_sync();
                     for (uint32_t t = lane; t < total; t += 64) {
