@@ -1483,7 +1483,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                     sl = ri.w;
                     return g < CT;
                 };
-                auto test = [&](const uint4& P, uint32_t pos, uint32_t sl, bool cact) {
+                auto test = [&](const uint4& P, uint32_t pos, uint32_t sl, bool cact, uint32_t cb) {
                     const uint4 ch = qp[5 * sl + 4];
                     const uint2 cr = *(const uint2*)(qp + 5 * sl + 1);
                     const uint32_t pv[3] = {P.x, P.y, P.z}, hv[3] = {ch.x, ch.y, ch.z};
@@ -1496,24 +1496,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                     const uint64_t r2 = (uint64_t)cr.x | ((uint64_t)cr.y << 32);
                     const bool hit = cact && d2 <= r2 && pos != ch.w;
                     const uint64_t H = __ballot(hit);
-                    // hits per slot: each run of slots of one query adds its
-                    // share of the ballot once (runs are contiguous)
-                    const uint32_t prev = bperm(sl, (lane + 63u) & 63u);
-                    const bool leader = cact && (lane == 0 || sl != prev);
-                    const uint64_t lm = __ballot(leader);
-                    if (leader && H != 0) {
-                        const uint64_t above = lane == 63 ? 0ull : (lm >> (lane + 1)) << (lane + 1);
-                        const uint64_t upto = above ? ((above & (~above + 1ull)) - 1ull) : ~0ull;
-                        const uint64_t seg = upto & ~((1ull << lane) - 1ull);
-                        const uint32_t c = (uint32_t)__popcll(H & seg);
-                        if (c) atomicAdd(&cnt[sl], c);
-                    }
-                    if (STASH) {
-                        const uint32_t hp = hcount + lanes_below(H);
-                        if (hit && hp < hitcap)
-                            hb[hp] = ((uint64_t)sl << (64u - kGroupBits)) | (d2 << idbits) | (uint64_t)P.w;
-                        hcount += (uint32_t)__popcll(H);
-                    }
+                    const uint32_t hp = hcount + lanes_below(H);
+                    // hits per slot: a slot's candidates take contiguous lanes
+                    // and its hits arrive in order, so the last lane of its
+                    // run in a step records the group's hit count so far
+                    const uint32_t nsl = bperm(sl, (lane + 1u) & 63u);
+                    if (cact && (lane == 63u || cb + lane + 1u >= CT || nsl != sl)) cnt[sl] = hp + (hit ? 1u : 0u);
+                    if (STASH && hit && hp < hitcap)
+                        hb[hp] = ((uint64_t)sl << (64u - kGroupBits)) | (d2 << idbits) | (uint64_t)P.w;
+                    hcount += (uint32_t)__popcll(H);
                 };
                 if (CT > 0) {
                     // two register sets taken in turn: the step after the one
@@ -1528,17 +1519,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                     for (uint32_t cb = 0; cb < CT; cb += 128) {
                         ab = locate(cb + 64, pb, sb);
                         PB = L.pts[ab ? pb : 0u];
-                        test(PA, pa, sa, aa);
+                        test(PA, pa, sa, aa, cb);
                         if (cb + 64 >= CT) break;
                         aa = locate(cb + 128, pa, sa);
                         PA = L.pts[aa ? pa : 0u];
-                        test(PB, pb, sb, ab);
+                        test(PB, pb, sb, ab, cb + 64);
                     }
                 }
                 wave_sync();
             }
-            // ---- row sizes
-            uint32_t nq = mine ? cnt[lane] : 0u;
+            // ---- row sizes: each slot's hits end where its last run left
+            // the count (a slot without candidates left none: the max-scan
+            // carries the previous slot's end)
+            const uint32_t hend = scan_max(lane < kGroup ? cnt[lane] : 0u);
+            const uint32_t hbeg = bperm(hend, (lane + 63u) & 63u);
+            uint32_t nq = mine ? hend - (lane ? hbeg : 0u) : 0u;
             uint32_t total = hcount;
             if (STASH && hcount > hitcap && ng > 1) {
                 // the hit buffer overflowed: keep the leading slots whose hits
