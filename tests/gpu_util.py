@@ -31,13 +31,13 @@ def per_query(sx, v):
     return sx.to_dev_u32(np.asarray(v, dtype=np.uint32))
 
 
-def run(sx, lat, tab, r, k=None, mode=0, queries=None, flags=0, launch=None, want_dist2=True):
+def run(sx, lat, tab, r, k=None, mode=0, queries=None, flags=0, launch=None, want_dist2=True, stash=False):
     Q = lat.n if queries is None else len(queries[0])
     cen = None if queries is None else tuple(sx.to_dev_u32(a) for a in queries)
     rad = per_query(sx, r)
     kk = per_query(sx, k)
     q = sx.make_queries(Q, cen, rad, kk, mode, flags)
-    out = sx.run(lat, tab, q, launch, want_dist2=want_dist2)
+    out = sx.run(lat, tab, q, launch, want_dist2=want_dist2, stash=stash)
     del cen, rad, kk
     return out
 

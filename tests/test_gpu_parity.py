@@ -212,6 +212,13 @@ def test_radius_uneven_clipped_full_size(sx, orc):
     tab = sx.Tables(lat, 2, 4 * 65536)
     for name in ("sphere-persistent", "sphere-plain", "cube"):
         assert_same(run(sx, lat, tab, w.r_fx, launch=_launches(sx)[name]), ref, f"C2 {name}")
+    # the launches the benchmark times: groups of queries whose rows are
+    # sorted and kept in the count pass, grabs of 256 and of 64 queries
+    for tile, bpc in ((256, 8), (64, 6)):
+        ln = sx.LaunchConfig(method=sx.METHOD_SPHERE, schedule=sx.SCHED_PERSISTENT, grouped=1, interior=1,
+                             sort_cap=256, waves_per_block=4, tile=tile, blocks_per_cu=bpc)
+        say("C2 grouped with the stash", tile, bpc)
+        assert_same(run(sx, lat, tab, w.r_fx, launch=ln, stash=True), ref, f"C2 grouped stash tile {tile}")
 
 
 # ---------------------------------------------------------------------------
@@ -311,12 +318,20 @@ def test_edge_cases(sx, orc):
     lat = lattice(sx, log2, F, mask, dup)
     ref = orc.radius_brute(L, dup, np.zeros(200, np.uint32))
     assert_same(run(sx, lat, tab, 0), ref, "r = 0 duplicates")
+    # grouped, rows sorted in the count pass: every query of a group has
+    # r = 0, so every hit has dist^2 0 and a row's order is its ids' alone
+    for name in ("sphere-grouped", "sphere-grouped-flat"):
+        for stash in (False, True):
+            assert_same(run(sx, lat, tab, 0, launch=_launches(sx)[name], stash=stash), ref,
+                        f"r = 0 duplicates {name} stash={stash}")
     # positions exactly on cell boundaries and at the world edge
     edge = tuple(np.array([0, e, 2 * e, 8 * e - 1, 4 * e, 4 * e - 1], np.uint32) for _ in range(3))
     lat = lattice(sx, log2, F, mask, edge)
     for r in (0, 1, e, 2 * e - 1, 2 * e):
         ref = orc.radius_brute(L, edge, np.full(6, r, np.uint32))
         assert_same(run(sx, lat, tab, r), ref, f"edges r={r}")
+        assert_same(run(sx, lat, tab, r, launch=_launches(sx)["sphere-grouped-flat"], stash=True), ref,
+                    f"edges grouped r={r}")
 
 
 # ---------------------------------------------------------------------------
