@@ -241,6 +241,44 @@ def test_knn_clustered(sx, orc, K):
         assert_same(got, ref, f"knn K={K} {name}")
 
 
+def test_knn_clustered_full_size_sampled_rows(sx, orc):
+    """The clustered K-NN workload at full size (4,194,304 points in 64
+    clusters, K = 16, search cap 8 cells) in the launches the benchmark
+    times: groups of queries searched as radius rows at a first radius,
+    rows kept in the count pass.  20,000 sampled rows are checked against
+    the oracle's K nearest of the same centres."""
+    import torch
+
+    from paper_cs_0608108_amd import synth
+    w = synth.knn_clustered()
+    n, K, cap = w.n, int(w.k[0]), int(w.r_fx[0])
+    lat = lattice(sx, w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask, w.pts)
+    tab = sx.Tables(lat, 2, cap)
+    q = sx.make_queries(n, None, cap, K, sx.MODE_KNN, 0)
+    rows = np.unique(np.random.default_rng(31).integers(0, n, 20000))
+    g = orc.Grid(orc.Lattice(w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask), w.pts)
+    ref = g.knn(K, cap, queries=tuple(np.asarray(a)[rows] for a in w.pts))
+    g.close()
+    for tile, bpc in ((64, 6), (256, 8)):
+        ln = sx.LaunchConfig(method=sx.METHOD_SPHERE, schedule=sx.SCHED_PERSISTENT, grouped=1, interior=1,
+                             sort_cap=256, waves_per_block=4, tile=tile, blocks_per_cu=bpc)
+        say("C3 grouped with the stash", tile, bpc)
+        buf = sx.QueryBuffers(n, n * K, want_dist2=False, stash_pairs=3 * n * K)
+        sx.query(lat, tab, q, buf, ln)
+        torch.cuda.synchronize()
+        rp = buf.row_ptr.cpu().numpy()
+        assert int(rp[-1]) == n * K
+        idx = np.concatenate([np.arange(rp[r], rp[r + 1]) for r in rows])
+        ids = buf.ids[torch.from_numpy(idx).to(buf.ids.device)].cpu().numpy().view(np.uint32)
+        srp = np.zeros(len(rows) + 1, np.int64)
+        srp[1:] = np.cumsum(rp[rows + 1] - rp[rows])
+        assert np.array_equal(srp, ref.row_ptr), f"C3 row lengths, tile {tile}"
+        assert np.array_equal(ids, ref.ids), f"C3 sampled rows, tile {tile}"
+        del buf
+    code, flags = lat.status()
+    assert code == sx.OK and flags == 0
+
+
 @pytest.mark.parametrize("mask", [0, 7])
 def test_knn_random_worlds_and_mixed_batches(sx, orc, mask):
     rng = np.random.default_rng(77 + mask)
