@@ -162,3 +162,49 @@ def test_resident_move_on_an_empty_lattice(sx):
     assert int(step.item()) == 1
     code, flags = lat.status()
     assert code == sx.OK and flags == 0
+
+
+@pytest.mark.parametrize("resident", [False, True])
+def test_full_size_timestep_in_the_benchmark_launch(sx, orc, resident):
+    """The moving-agent workload at full size (8,388,608 agents in a cyclic
+    256^3 lattice, r = 3 cells) in the launch the benchmark times (groups of
+    queries, rows kept in the count pass): one eager step and three graph
+    replays, then every position and 20,000 sampled rows against the oracle's
+    replay; with `resident` the records are moved in place instead of the
+    lattice being rebuilt from positions."""
+    import torch
+
+    from paper_cs_0608108_amd import synth, timestep
+    w = synth.agents_timestep()
+    n, seed, r = w.n, w.extra["seed"], int(w.r_fx[0])
+    ln = sx.LaunchConfig(method=sx.METHOD_SPHERE, schedule=sx.SCHED_PERSISTENT, grouped=1, interior=1,
+                         sort_cap=256, waves_per_block=4, tile=64, blocks_per_cu=8)
+    sim = timestep.AgentSim(w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask, w.pts, r, seed, launch=ln,
+                            resident=resident)
+    say(f"C4 full size resident={resident}")
+    sim.step()
+    torch.cuda.synchronize()
+    sim.capture()
+    for _ in range(3):
+        sim.replay()
+        torch.cuda.synchronize()
+    code, flags = sim.status()
+    assert code == sx.OK and flags == 0
+    L = orc.Lattice(w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask)
+    cur = w.pts
+    for t in range(sim.steps_done):
+        cur = orc.move(L, seed, t, cur)
+    got = sim.positions()
+    for a in range(3):
+        assert np.array_equal(got[a], cur[a]), f"axis {a} after {sim.steps_done} steps"
+    rp = sim.buf.row_ptr.cpu().numpy()
+    rows = np.unique(np.random.default_rng(41).integers(0, n, 20000))
+    idx = np.concatenate([np.arange(rp[i], rp[i + 1]) for i in rows])
+    ids = sim.buf.ids[torch.from_numpy(idx).to(sim.buf.ids.device)].cpu().numpy().view(np.uint32)
+    g = orc.Grid(L, cur)
+    ref = g.radius(r, queries=tuple(np.asarray(c)[rows] for c in cur))
+    g.close()
+    srp = np.zeros(len(rows) + 1, np.int64)
+    srp[1:] = np.cumsum(rp[rows + 1] - rp[rows])
+    assert np.array_equal(srp, ref.row_ptr), "row lengths"
+    assert np.array_equal(ids, ref.ids), "sampled rows"
