@@ -66,6 +66,7 @@ def _load():
         "orc_grid_free": (None, [P]),
         "orc_grid_counts": (None, [P, P]),
         "orc_grid_radius": (P, [P, U32, P, P, P, P, U32]),
+        "orc_grid_radius_counts": (None, [P, U32, P, P, P, P, U32, P]),
         "orc_grid_knn": (P, [P, U32, P, P, P, P, P, U32]),
         "orc_grid_mixed": (P, [P, U32, P, P, P, P, P, U32]),
         "orc_result_total": (I64, [P]),
@@ -223,6 +224,14 @@ class Grid:
         r = _per_query(r_fx, nq)
         res = _load().orc_grid_radius(self._h, nq, _ptr(qx), _ptr(qy), _ptr(qz), _ptr(r), flags)
         return _collect(res, nq)
+
+    def radius_counts(self, r_fx, queries=None, flags=0) -> np.ndarray:
+        """Row sizes of the radius query (int64 [Q]), without the rows."""
+        qx, qy, qz, nq = _queries(queries, self.n)
+        r = _per_query(r_fx, nq)
+        out = np.empty(nq, dtype=np.int64)
+        _load().orc_grid_radius_counts(self._h, nq, _ptr(qx), _ptr(qy), _ptr(qz), _ptr(r), flags, _ptr(out))
+        return out
 
     def knn(self, k, rmax_fx, queries=None, flags=0) -> CSR:
         qx, qy, qz, nq = _queries(queries, self.n)

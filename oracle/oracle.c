@@ -444,6 +444,48 @@ orc_result *orc_grid_radius(const orc_grid *g, uint32_t nq, const uint32_t *qx,
     return rows_to_result(rows, nq);
 }
 
+/* Row sizes only: for each query, the number of objects within r (Section
+ * II.A), the same cube-set scan as orc_grid_radius without keeping the
+ * pairs.  out[i] = |R(q_i)|, 0 for an unusable centre.  This is what a
+ * neighbour-count checksum over many queries needs, without the memory of
+ * every row. */
+void orc_grid_radius_counts(const orc_grid *g, uint32_t nq, const uint32_t *qx, const uint32_t *qy,
+                            const uint32_t *qz, const uint32_t *r_fx, uint32_t flags, int64_t *out) {
+    const orc_desc *d = &g->d;
+    int all_agents = (qx == NULL);
+    int64_t M = max_axis_cells(d) + 2;
+#pragma omp parallel
+    {
+        int64_t *l = (int64_t *)malloc((size_t)M * 3 * sizeof(int64_t));
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t i = 0; i < (int64_t)nq; ++i) {
+            orc_center q = all_agents ? g->pts[i] : make_center(d, qx[i], qy[i], qz[i]);
+            out[i] = 0;
+            if (!q.ok) continue;
+            int64_t skip = (all_agents && (flags & ORC_EXCLUDE_SELF)) ? i : -1;
+            uint64_t r2 = (uint64_t)r_fx[i] * (uint64_t)r_fx[i];
+            int64_t nx = axis_cube_cells(d, 0, q.c[0], r_fx[i], l);
+            int64_t ny = axis_cube_cells(d, 1, q.c[1], r_fx[i], l + M);
+            int64_t nz = axis_cube_cells(d, 2, q.c[2], r_fx[i], l + 2 * M);
+            int64_t cnt = 0;
+            for (int64_t c = 0; c < nx * ny * nz + (any_clipped(d) ? 1 : 0); ++c) {
+                int64_t cell = g->ncells; /* the last pass: the outside cell */
+                if (c < nx * ny * nz) {
+                    int64_t ix = c % nx, iy = (c / nx) % ny, iz = c / (nx * ny);
+                    cell = (l[2 * M + iz] * axis_cells(d, 1) + l[M + iy]) * axis_cells(d, 0) + l[ix];
+                }
+                for (int64_t t = g->start[cell]; t < g->start[cell + 1]; ++t) {
+                    uint32_t j = g->order[t];
+                    if ((int64_t)j == skip) continue;
+                    if ((uint64_t)dist2(d, g->pts[j].c, q.c) <= r2) ++cnt;
+                }
+            }
+            out[i] = cnt;
+        }
+        free(l);
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* K nearest (Section II.A, last paragraph): the first min(K, |R|) entries   */
 /* of the radius result R at the search cap rmax, in (dist2, id) order.      */

@@ -284,6 +284,78 @@ def test_grid_tier_equals_brute_force(orc, mask, shape):
     np.testing.assert_array_equal(a.ids, b.ids)
 
 
+def _histogram_by_definition(log2, F, mask, pts):
+    """Objects per cell, written from the definitions: on a cyclic axis the
+    coordinate is taken modulo the world width, a cell index is the
+    coordinate shifted right by F (Section II.B), cells are packed z-major;
+    an object with a clipped coordinate at or beyond the world width lives
+    in the one outside cell (index = number of cells); an object with a
+    clipped coordinate >= 2^30 is unusable and in no cell."""
+    L = [1 << v for v in log2]
+    ncells = L[0] * L[1] * L[2]
+    hist = np.zeros(ncells + 1, dtype=np.int64)
+    for j in range(len(pts[0])):
+        c, out, bad = [], False, False
+        for a in range(3):
+            v = int(pts[a][j])
+            W = L[a] << F
+            if (mask >> a) & 1:
+                v %= W
+            elif v >= 1 << 30:
+                bad = True
+            elif v >= W:
+                out = True
+            c.append(v >> F)
+        if bad:
+            continue
+        hist[ncells if out else (c[2] * L[1] + c[1]) * L[0] + c[0]] += 1
+    return hist
+
+
+@pytest.mark.parametrize("mask", range(8))
+@pytest.mark.parametrize("shape", CASES)
+def test_grid_counts_are_the_cell_histogram(orc, mask, shape):
+    """The oracle grid's per-cell counts (the histogram the lattice rebuild is
+    checked against) equal a histogram taken straight from the definitions,
+    with objects outside the region and unusable ones included."""
+    log2, F = shape
+    rng = np.random.default_rng(5000 + mask * 10 + F)
+    pts = _tiny(rng, log2, F, mask, 400, outside=True)
+    g = orc.Grid(orc.Lattice(log2, F, mask), pts)
+    got = g.counts()
+    g.close()
+    want = _histogram_by_definition(log2, F, mask, pts)
+    np.testing.assert_array_equal(got.astype(np.int64), want)
+    n_bad = sum(1 for j in range(len(pts[0]))
+                if any(not (mask >> a) & 1 and int(pts[a][j]) >= 1 << 30 for a in range(3)))
+    assert int(got.sum()) == len(pts[0]) - n_bad
+
+
+@pytest.mark.parametrize("mask", range(8))
+@pytest.mark.parametrize("shape", CASES)
+def test_radius_counts_equal_brute_force_row_sizes(orc, mask, shape):
+    """Row sizes without the rows (the neighbour-count checksum's input) equal
+    the row lengths of the brute-force tier, all agents with and without the
+    own object, and explicit centres (some outside the region)."""
+    log2, F = shape
+    rng = np.random.default_rng(6000 + mask * 10 + F)
+    L = orc.Lattice(log2, F, mask)
+    n = 300
+    pts = _tiny(rng, log2, F, mask, n, outside=True)
+    E = 1 << F
+    g = orc.Grid(L, pts)
+    for flags in (0, orc.EXCLUDE_SELF):
+        r = rng.integers(0, 6 * E, n).astype(np.uint32)
+        r[:5] = 0
+        a = orc.radius_brute(L, pts, r, flags=flags)
+        np.testing.assert_array_equal(g.radius_counts(r, flags=flags), np.diff(a.row_ptr))
+    qs = _tiny(rng, log2, F, mask, 64, outside=True)
+    r = rng.integers(0, 6 * E, 64).astype(np.uint32)
+    a = orc.radius_brute(L, pts, r, queries=qs)
+    np.testing.assert_array_equal(g.radius_counts(r, queries=qs), np.diff(a.row_ptr))
+    g.close()
+
+
 @pytest.mark.parametrize("mask", [0, 3, 7])
 @pytest.mark.parametrize("shape", CASES)
 def test_knn_tiers_agree(orc, mask, shape):
