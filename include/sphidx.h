@@ -125,6 +125,14 @@ sphidx_status sphidx_lattice_attach_cell_list(sphidx_lattice* lat, void* list_de
  * NULL) and clear it.  Returns RANGE or CAPACITY when those bits were set. */
 sphidx_status sphidx_lattice_status(sphidx_lattice* lat, void* stream, uint32_t* flags_out);
 
+/* The same by stream: synchronise `stream`, then read and clear the status
+ * words of every lattice that calls on this stream (builds, moves, queries,
+ * cell-list attachment) have touched since the last sphidx_stream_status
+ * for it, and return their bits OR-ed in *flags_out (may be NULL).  Returns
+ * RANGE or CAPACITY when those bits were set, DEVICE when a HIP call fails.
+ * A destroyed lattice is forgotten.  Thread-safe. */
+sphidx_status sphidx_stream_status(void* stream, uint32_t* flags_out);
+
 /* ---------------------------------------------------------------------- */
 /* Sphere tables (Section II.A; sub-cell specialisation, Section III.A).    */
 /*                                                                          */
@@ -333,6 +341,14 @@ sphidx_status sphidx_write(const sphidx_lattice* lat, const sphidx_tables* tab, 
 /* Both passes. */
 sphidx_status sphidx_query(const sphidx_lattice* lat, const sphidx_tables* tab, const sphidx_queries* q,
                            sphidx_csr* csr, const sphidx_launch* launch, void* stream);
+
+/* Pass 1 of a radius query with the default launch (mode forced to
+ * RADIUS): the row sizes of Section II.A's neighbourhoods, scanned into
+ * csr->row_ptr_dev (row_ptr[Q] = total pairs).  The workspace of `csr` is
+ * required (the count pass keeps its query descriptors there for the write
+ * pass); its ids, dist2 and capacity are not touched. */
+sphidx_status sphidx_radius_count(const sphidx_lattice* lat, const sphidx_tables* tab,
+                                  const sphidx_queries* q, sphidx_csr* csr, void* stream);
 
 /* Named forms of sphidx_query with the default launch: radius (mode forced
  * to RADIUS), K nearest (mode forced to KNN), and the bin-lattice baseline

@@ -444,6 +444,18 @@ orc_result *orc_grid_radius(const orc_grid *g, uint32_t nq, const uint32_t *qx,
     return rows_to_result(rows, nq);
 }
 
+/* Objects of one grid cell within r of q (skip_id excluded). */
+static int64_t cell_count_within(const orc_grid *g, int64_t cell, const orc_center *q, uint64_t r2,
+                                 int64_t skip_id) {
+    int64_t cnt = 0;
+    for (int64_t k = g->start[cell]; k < g->start[cell + 1]; ++k) {
+        uint32_t j = g->order[k];
+        if ((int64_t)j == skip_id) continue;
+        if ((uint64_t)dist2(&g->d, g->pts[j].c, q->c) <= r2) ++cnt;
+    }
+    return cnt;
+}
+
 /* Row sizes only: for each query, the number of objects within r (Section
  * II.A), the same cube-set scan as orc_grid_radius without keeping the
  * pairs.  out[i] = |R(q_i)|, 0 for an unusable centre.  This is what a
@@ -468,18 +480,14 @@ void orc_grid_radius_counts(const orc_grid *g, uint32_t nq, const uint32_t *qx, 
             int64_t ny = axis_cube_cells(d, 1, q.c[1], r_fx[i], l + M);
             int64_t nz = axis_cube_cells(d, 2, q.c[2], r_fx[i], l + 2 * M);
             int64_t cnt = 0;
-            for (int64_t c = 0; c < nx * ny * nz + (any_clipped(d) ? 1 : 0); ++c) {
-                int64_t cell = g->ncells; /* the last pass: the outside cell */
-                if (c < nx * ny * nz) {
-                    int64_t ix = c % nx, iy = (c / nx) % ny, iz = c / (nx * ny);
-                    cell = (l[2 * M + iz] * axis_cells(d, 1) + l[M + iy]) * axis_cells(d, 0) + l[ix];
-                }
-                for (int64_t t = g->start[cell]; t < g->start[cell + 1]; ++t) {
-                    uint32_t j = g->order[t];
-                    if ((int64_t)j == skip) continue;
-                    if ((uint64_t)dist2(d, g->pts[j].c, q.c) <= r2) ++cnt;
-                }
-            }
+            for (int64_t iz = 0; iz < nz; ++iz)
+                for (int64_t iy = 0; iy < ny; ++iy)
+                    for (int64_t ix = 0; ix < nx; ++ix) {
+                        int64_t cell = (l[2 * M + iz] * axis_cells(d, 1) + l[M + iy]) * axis_cells(d, 0) + l[ix];
+                        cnt += cell_count_within(g, cell, &q, r2, skip);
+                    }
+            /* objects outside a non-cyclic region: the one outside cell */
+            if (any_clipped(d)) cnt += cell_count_within(g, g->ncells, &q, r2, skip);
             out[i] = cnt;
         }
         free(l);

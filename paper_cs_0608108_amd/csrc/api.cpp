@@ -1,7 +1,10 @@
 // C ABI of libsphidx: argument validation, workspace layout and dispatch.
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <utility>
+#include <vector>
 
 #include "sphidx_internal.h"
 
@@ -259,6 +262,43 @@ void* scan_tmp_of(sphidx_csr* csr, uint32_t Q) { return (char*)csr->workspace_de
 
 sphidx_status dev_err(hipError_t e) { return e == hipSuccess ? SPHIDX_OK : SPHIDX_ERR_DEVICE; }
 
+// Lattices whose status words a stream has touched since the last
+// sphidx_stream_status on it: (stream, lattice) pairs, noted by every entry
+// point that enqueues work on a lattice.
+std::mutex g_touch_mu;
+std::vector<std::pair<void*, const sphidx_lattice*>> g_touched;
+
+void note_stream(const sphidx_lattice* lat, void* stream) {
+    std::lock_guard<std::mutex> lk(g_touch_mu);
+    for (const auto& t : g_touched)
+        if (t.first == stream && t.second == lat) return;
+    g_touched.emplace_back(stream, lat);
+}
+
+void forget_lattice(const sphidx_lattice* lat) {
+    std::lock_guard<std::mutex> lk(g_touch_mu);
+    g_touched.erase(std::remove_if(g_touched.begin(), g_touched.end(),
+                                   [lat](const std::pair<void*, const sphidx_lattice*>& t) { return t.second == lat; }),
+                    g_touched.end());
+}
+
+// Read and clear one lattice's status word in stream order (synchronises).
+sphidx_status take_status(const sphidx_lattice* lat, hipStream_t st, uint32_t* v) {
+    *v = 0;
+    if (hipMemcpyAsync(v, lat->status, 4, hipMemcpyDeviceToHost, st) != hipSuccess) return SPHIDX_ERR_DEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) return SPHIDX_ERR_DEVICE;
+    if (launch_fill_u32(lat->status, 0u, 1, st) != hipSuccess) return SPHIDX_ERR_DEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) return SPHIDX_ERR_DEVICE;
+    return SPHIDX_OK;
+}
+
+sphidx_status status_of_flags(uint32_t v) {
+    if (v & SPHIDX_FLAG_RANGE) return SPHIDX_ERR_RANGE;
+    if (v & SPHIDX_FLAG_CAPACITY) return SPHIDX_ERR_CAPACITY;
+    return SPHIDX_OK;
+}
+
+
 // Upload freshly built or loaded tables when a device is present.  Without
 // one (a CPU-only host) the tables stay host-only: they can be inspected,
 // saved and loaded, and are uploaded on first use by a query.
@@ -283,6 +323,7 @@ sphidx_status run_pass(int pass, const sphidx_lattice* lat, const sphidx_tables*
         s = tables_upload(const_cast<sphidx_tables*>(tab));
         if (s != SPHIDX_OK) return s;
     }
+    note_stream(lat, (void*)st);
     LatArgs L = lat_args(lat);
     TabArgs T = tab_args(tables ? tab : nullptr);
     T.lds = ln.tab_lds;
@@ -349,13 +390,18 @@ sphidx_status sphidx_lattice_create(const sphidx_lattice_desc* desc, uint32_t ma
     return SPHIDX_OK;
 }
 
-void sphidx_lattice_destroy(sphidx_lattice* lat) { delete lat; }
+void sphidx_lattice_destroy(sphidx_lattice* lat) {
+    if (!lat) return;
+    forget_lattice(lat);
+    delete lat;
+}
 
 sphidx_status sphidx_build_lattice(sphidx_lattice* lat, const uint32_t* x_dev, const uint32_t* y_dev,
                                    const uint32_t* z_dev, uint32_t n, void* stream) {
     if (!lat || n > lat->max_points) return lat ? SPHIDX_ERR_CAPACITY : SPHIDX_ERR_INVALID_ARG;
     if (n > 0 && (!x_dev || !y_dev || !z_dev)) return SPHIDX_ERR_INVALID_ARG;
     lat->n = n;
+    note_stream(lat, stream);
     return dev_err(launch_build(lat, x_dev, y_dev, z_dev, n, (hipStream_t)stream));
 }
 
@@ -374,6 +420,7 @@ sphidx_status sphidx_lattice_attach_cell_list(sphidx_lattice* lat, void* list_de
     if ((uintptr_t)list_dev % kAlign) return SPHIDX_ERR_INVALID_ARG;
     if (bytes < sphidx_cell_list_bytes(lat)) return SPHIDX_ERR_CAPACITY;
     lat->cell_list = (char*)list_dev;
+    note_stream(lat, stream);
     const sphidx_status s = dev_err(launch_cell_list(lat, (hipStream_t)stream));
     if (s != SPHIDX_OK) lat->cell_list = nullptr;
     return s;
@@ -390,16 +437,37 @@ sphidx_status sphidx_lattice_get_view(const sphidx_lattice* lat, sphidx_lattice_
 
 sphidx_status sphidx_lattice_status(sphidx_lattice* lat, void* stream, uint32_t* flags_out) {
     if (!lat) return SPHIDX_ERR_INVALID_ARG;
-    hipStream_t st = (hipStream_t)stream;
     uint32_t v = 0;
-    if (hipMemcpyAsync(&v, lat->status, 4, hipMemcpyDeviceToHost, st) != hipSuccess) return SPHIDX_ERR_DEVICE;
-    if (hipStreamSynchronize(st) != hipSuccess) return SPHIDX_ERR_DEVICE;
-    if (launch_fill_u32(lat->status, 0u, 1, st) != hipSuccess) return SPHIDX_ERR_DEVICE;
-    if (hipStreamSynchronize(st) != hipSuccess) return SPHIDX_ERR_DEVICE;
+    const sphidx_status s = take_status(lat, (hipStream_t)stream, &v);
+    if (s != SPHIDX_OK) return s;
     if (flags_out) *flags_out = v;
-    if (v & SPHIDX_FLAG_RANGE) return SPHIDX_ERR_RANGE;
-    if (v & SPHIDX_FLAG_CAPACITY) return SPHIDX_ERR_CAPACITY;
-    return SPHIDX_OK;
+    return status_of_flags(v);
+}
+
+sphidx_status sphidx_stream_status(void* stream, uint32_t* flags_out) {
+    std::vector<const sphidx_lattice*> lats;
+    {
+        std::lock_guard<std::mutex> lk(g_touch_mu);
+        for (auto it = g_touched.begin(); it != g_touched.end();) {
+            if (it->first == stream) {
+                lats.push_back(it->second);
+                it = g_touched.erase(it);
+            } else {
+                ++it;
+            }
+        }
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (lats.empty() && hipStreamSynchronize(st) != hipSuccess) return SPHIDX_ERR_DEVICE;
+    uint32_t all = 0;
+    for (const sphidx_lattice* lat : lats) {
+        uint32_t v = 0;
+        const sphidx_status s = take_status(lat, st, &v);
+        if (s != SPHIDX_OK) return s;
+        all |= v;
+    }
+    if (flags_out) *flags_out = all;
+    return status_of_flags(all);
 }
 
 sphidx_status sphidx_build_sphere_tables(const sphidx_lattice_desc* desc, uint32_t subcell_bits,
@@ -522,6 +590,17 @@ static sphidx_status with_mode(const sphidx_lattice* lat, const sphidx_tables* t
     return sphidx_query(lat, tab, &qq, csr, &ln, stream);
 }
 
+sphidx_status sphidx_radius_count(const sphidx_lattice* lat, const sphidx_tables* tab, const sphidx_queries* q,
+                                  sphidx_csr* csr, void* stream) {
+    if (!q) return SPHIDX_ERR_INVALID_ARG;
+    sphidx_queries qq = *q;
+    qq.mode = SPHIDX_MODE_RADIUS;
+    sphidx_launch ln;
+    std::memset(&ln, 0, sizeof(ln));
+    ln.schedule = SPHIDX_SCHED_PERSISTENT;
+    return sphidx_count(lat, tab, &qq, csr, &ln, stream);
+}
+
 sphidx_status sphidx_radius_query(const sphidx_lattice* lat, const sphidx_tables* tab, const sphidx_queries* q,
                                   sphidx_csr* csr, void* stream) {
     return with_mode(lat, tab, q, csr, SPHIDX_MODE_RADIUS, SPHIDX_METHOD_SPHERE, stream);
@@ -564,6 +643,7 @@ sphidx_status sphidx_move_resident(sphidx_lattice* lat, uint64_t seed, uint32_t 
     if (n > 0 && (!scratch_dev || (uintptr_t)scratch_dev % 16)) return SPHIDX_ERR_INVALID_ARG;
     if (scratch_bytes < (size_t)n * sizeof(uint4)) return SPHIDX_ERR_CAPACITY;
     const hipStream_t st = (hipStream_t)stream;
+    note_stream(lat, stream);
     uint4* moved = (uint4*)scratch_dev;
     hipError_t e = hipSuccess;
     if (step_dev) {

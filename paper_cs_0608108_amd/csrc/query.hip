@@ -1959,6 +1959,12 @@ __global__ __launch_bounds__(256) void gather_kernel(QArgs A, const uint4* pts, 
             dst = A.row_ptr[row];
             len = (uint32_t)(A.row_ptr[row + 1] - dst);
             if (len > 0 && A.out_d2 && !has_d2) {
+                // the stash holds no dist^2 for this row: it is walked again,
+                // by the main write kernel (from the walk list) or, for a row
+                // off the sphere tables, by the list kernels, which walk rows
+                // whose offset says "not kept"; marked so once, a later write
+                // does not list it again
+                A.soff[qi] = kMaxId;
                 A.walkq[atomicAdd(A.walk_count, 1u)] = (uint32_t)qi;
                 len = 0;
             }

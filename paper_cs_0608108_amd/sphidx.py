@@ -67,6 +67,7 @@ SIGNATURES = {
     "sphidx_build_lattice": (ctypes.c_int, [P, P, P, P, U32, P]),
     "sphidx_lattice_get_view": (ctypes.c_int, [P, ctypes.POINTER(LatticeView)]),
     "sphidx_lattice_status": (ctypes.c_int, [P, P, ctypes.POINTER(U32)]),
+    "sphidx_stream_status": (ctypes.c_int, [P, ctypes.POINTER(U32)]),
     "sphidx_cell_list_bytes": (SZ, [P]),
     "sphidx_lattice_attach_cell_list": (ctypes.c_int, [P, P, SZ, P]),
     "sphidx_build_sphere_tables": (ctypes.c_int, [ctypes.POINTER(LatticeDesc), U32, U32, ctypes.POINTER(P)]),
@@ -86,6 +87,7 @@ SIGNATURES = {
                                     ctypes.POINTER(LaunchDesc), P]),
     "sphidx_query": (ctypes.c_int, [P, P, ctypes.POINTER(Queries), ctypes.POINTER(CSRDesc),
                                     ctypes.POINTER(LaunchDesc), P]),
+    "sphidx_radius_count": (ctypes.c_int, [P, P, ctypes.POINTER(Queries), ctypes.POINTER(CSRDesc), P]),
     "sphidx_radius_query": (ctypes.c_int, [P, P, ctypes.POINTER(Queries), ctypes.POINTER(CSRDesc), P]),
     "sphidx_knn_query": (ctypes.c_int, [P, P, ctypes.POINTER(Queries), ctypes.POINTER(CSRDesc), P]),
     "sphidx_cube_scan_radius": (ctypes.c_int, [P, ctypes.POINTER(Queries), ctypes.POINTER(CSRDesc), P]),
@@ -441,6 +443,14 @@ def count(lat, tab, q: Queries, buf: QueryBuffers, launch: LaunchConfig | None =
     cs = buf.c()
     check(load().sphidx_count(lat.handle, tab.handle if tab else None, ctypes.byref(q), ctypes.byref(cs),
                               ctypes.byref(ln), _stream(stream)), "count")
+
+
+def stream_status(stream=None):
+    """(status code, flags) of every lattice the stream's calls touched since
+    the last report; synchronises the stream and clears the words."""
+    f = U32(0)
+    code = load().sphidx_stream_status(_stream(stream), ctypes.byref(f))
+    return code, int(f.value)
 
 
 def write(lat, tab, q: Queries, buf: QueryBuffers, launch: LaunchConfig | None = None, stream=None):

@@ -241,12 +241,12 @@ def test_knn_clustered(sx, orc, K):
         assert_same(got, ref, f"knn K={K} {name}")
 
 
-def test_knn_clustered_full_size_sampled_rows(sx, orc):
+def test_knn_clustered_full_size_every_row(sx, orc):
     """The clustered K-NN workload at full size (4,194,304 points in 64
     clusters, K = 16, search cap 8 cells) in the launches the benchmark
     times: groups of queries searched as radius rows at a first radius,
-    rows kept in the count pass.  20,000 sampled rows are checked against
-    the oracle's K nearest of the same centres."""
+    rows kept in the count pass.  Every row (ids and squared distances) is
+    checked against the oracle's K nearest of all points."""
     import torch
 
     from paper_cs_0608108_amd import synth
@@ -255,25 +255,19 @@ def test_knn_clustered_full_size_sampled_rows(sx, orc):
     lat = lattice(sx, w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask, w.pts)
     tab = sx.Tables(lat, 2, cap)
     q = sx.make_queries(n, None, cap, K, sx.MODE_KNN, 0)
-    rows = np.unique(np.random.default_rng(31).integers(0, n, 20000))
+    say("C3 oracle: K nearest of all 4,194,304 points")
     g = orc.Grid(orc.Lattice(w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask), w.pts)
-    ref = g.knn(K, cap, queries=tuple(np.asarray(a)[rows] for a in w.pts))
+    ref = g.knn(K, cap)
     g.close()
+    assert int(ref.row_ptr[-1]) == n * K
     for tile, bpc in ((64, 6), (256, 8)):
         ln = sx.LaunchConfig(method=sx.METHOD_SPHERE, schedule=sx.SCHED_PERSISTENT, grouped=1, interior=1,
                              sort_cap=256, waves_per_block=4, tile=tile, blocks_per_cu=bpc)
         say("C3 grouped with the stash", tile, bpc)
-        buf = sx.QueryBuffers(n, n * K, want_dist2=False, stash_pairs=3 * n * K)
+        buf = sx.QueryBuffers(n, n * K, want_dist2=True, stash_pairs=3 * n * K)
         sx.query(lat, tab, q, buf, ln)
         torch.cuda.synchronize()
-        rp = buf.row_ptr.cpu().numpy()
-        assert int(rp[-1]) == n * K
-        idx = np.concatenate([np.arange(rp[r], rp[r + 1]) for r in rows])
-        ids = buf.ids[torch.from_numpy(idx).to(buf.ids.device)].cpu().numpy().view(np.uint32)
-        srp = np.zeros(len(rows) + 1, np.int64)
-        srp[1:] = np.cumsum(rp[rows + 1] - rp[rows])
-        assert np.array_equal(srp, ref.row_ptr), f"C3 row lengths, tile {tile}"
-        assert np.array_equal(ids, ref.ids), f"C3 sampled rows, tile {tile}"
+        assert_same(buf.host(), ref, f"C3 every row, tile {tile}")
         del buf
     code, flags = lat.status()
     assert code == sx.OK and flags == 0
@@ -435,6 +429,42 @@ def test_range_flag_for_unusable_query_centres(sx, orc):
     assert rp[2] - rp[1] == 0
     ref = orc.radius_brute(orc.Lattice(log2, F, mask), pts, np.full(3, 600, np.uint32), queries=qs)
     assert_same((rp, ids, d2), ref, "range")
+
+
+def test_stream_status_and_named_radius_count(sx, orc):
+    """sphidx_stream_status reports the flags set by the stream's calls on any
+    lattice (then nothing until new work), and sphidx_radius_count gives the
+    row sizes of sphidx_count in radius mode."""
+    import ctypes
+
+    import torch
+    log2, F, mask = (3, 3, 3), 8, 0
+    pts = tuple(np.arange(0, 2000, 7, dtype=np.uint32) for _ in range(3))
+    lat = lattice(sx, log2, F, mask, pts)
+    tab = sx.Tables(lat, 2, 600)
+    sx.stream_status()  # drain what earlier work on this stream left
+    lat.build(*lat._pts_dev)
+    assert sx.stream_status() == (sx.OK, 0)
+    qs = tuple(sx.to_dev_u32(np.array([10, 1 << 30, 500], np.uint32)) for _ in range(3))
+    q = sx.make_queries(3, qs, 600, None, sx.MODE_KNN)  # the named count forces radius mode
+    buf = sx.QueryBuffers(3, 0)
+    cs = buf.c()
+    sx.check(sx.load().sphidx_radius_count(lat.handle, tab.handle, ctypes.byref(q), ctypes.byref(cs),
+                                           sx._stream()), "radius_count")
+    code, flags = sx.stream_status()
+    assert code == sx.ERR_RANGE and flags & sx.FLAG_RANGE
+    assert sx.stream_status() == (sx.OK, 0)
+    ref = orc.radius_brute(orc.Lattice(log2, F, mask), pts, np.full(3, 600, np.uint32),
+                           queries=tuple(q_.cpu().numpy().view(np.uint32) for q_ in qs))
+    np.testing.assert_array_equal(buf.row_ptr.cpu().numpy(), ref.row_ptr)
+    # a capacity overflow on another lattice, same stream
+    lat2 = lattice(sx, log2, F, mask, pts)
+    q2 = sx.make_queries(lat2.n, None, 600)
+    small = sx.QueryBuffers(lat2.n, 1)
+    sx.query(lat2, tab, q2, small)
+    code, flags = sx.stream_status()
+    assert code == sx.ERR_CAPACITY and flags == sx.FLAG_CAPACITY
+    torch.cuda.synchronize()
 
 
 def test_move_agents_and_checksum_match_oracle(sx, orc):

@@ -56,3 +56,49 @@ def test_batches_in_the_mix_equal_alone_and_oracle(sx, orc, slots, pool_mb):
         _rows_equal(a.result[:2], (ref.row_ptr, ref.ids), f"batch {b.index} alone vs oracle")
     g.close()
     assert sum(not b.rejected for b in batches) >= len(batches) - 2
+
+
+def test_full_size_serving_lattice_mixed_batches(sx, orc):
+    """The serving workload at its own size: 16,777,216 points uniform in a
+    cyclic 512^3 lattice, tables to 16 cells, batches of the serving mix
+    (radius 1-16 cells, K from {1, 8, 32, 128} with the 16-cell cap), among
+    them radius-16-cell queries and K = 128 queries, run through the
+    continuous-batching executor with 3 slots; every row against the
+    oracle."""
+    import torch
+
+    from paper_cs_0608108_amd import serving, synth
+    w = synth.serving_lattice()
+    spec, seed = w.lat, w.extra["seed"]
+    say(f"C5 full size: n={w.n}")
+    lat = sx.Lattice(spec.log2_cells, spec.frac_bits, spec.cyclic_mask, w.n)
+    dev = [sx.to_dev_u32(a) for a in w.pts]
+    lat.build(*dev)
+    tab = sx.Tables(lat, 2, 16 * spec.edge)
+    sizes = [1, 5, 64, 700, 1500, 2000, 300]
+    batches = []
+    for i, s in enumerate(sizes):
+        q, r, k = synth.serving_batch(spec, seed, 1000 + i, s)
+        r, k = r.copy(), k.copy()
+        if s >= 64:
+            # the largest radius and the largest K of the mix, at the cap
+            r[:8], k[:8] = 16 * spec.edge, 0
+            r[8:16], k[8:16] = 16 * spec.edge, 128
+        batches.append(serving.Batch(i, 0.0, q, r, k))
+    nr16 = sum(int(((b.radius == 16 * spec.edge) & (b.k == 0)).sum()) for b in batches)
+    nk128 = sum(int((b.k == 128).sum()) for b in batches)
+    assert nr16 >= 40 and nk128 >= 40
+    ex = serving.GpuExecutor(lat, tab, 3, max(sizes), 256 << 20)
+    serving.run_admission_model(batches, ex, 3, 256 << 20, keep=True)
+    torch.cuda.synchronize()
+    code, flags = lat.status()
+    assert code == sx.OK and not (flags & sx.FLAG_CAPACITY), (code, flags)
+    say("C5 oracle grid")
+    g = orc.Grid(orc.Lattice(spec.log2_cells, spec.frac_bits, spec.cyclic_mask), w.pts)
+    for b in batches:
+        assert not b.rejected, b.index
+        ref = g.mixed(b.k, b.radius, queries=b.centres)
+        _rows_equal(b.result, (ref.row_ptr, ref.ids), f"full-size batch {b.index} ({b.size} queries)")
+    g.close()
+    del ex, lat, tab, dev
+    torch.cuda.empty_cache()

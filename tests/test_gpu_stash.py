@@ -116,6 +116,51 @@ def test_stash_with_fallback_and_knn_rows(sx, orc):
     del keep
 
 
+def test_ids_only_stash_then_dist2_writes_with_fallback_and_knn_rows(sx, orc):
+    """A count that keeps ids only, then two writes that ask for dist^2: rows
+    off the sphere tables (radii above the cap, centres outside a clipped
+    region) and K-NN rows of a mixed batch are walked again, each once, by
+    both writes, in one-query-per-wave and grouped launches."""
+    import torch
+    rng = np.random.default_rng(12)
+    log2, F = (5, 5, 4), 10
+    mask = 1
+    pts = tiny_points(rng, log2, F, mask, 25000, outside=True)
+    lat = _world(sx, log2, F, mask, pts)
+    tab = sx.Tables(lat, 2, 2 << F)  # radii above 2 cells fall back to the cube scan
+    Qn = 6000
+    W = [(1 << (log2[a] + F)) for a in range(3)]
+    cen = [rng.integers(0, W[a] + (W[a] // 8 if a else 0), size=Qn).astype(np.uint32) for a in range(3)]
+    r = rng.integers(0, 4 << F, size=Qn).astype(np.uint32)
+    k = np.where(rng.random(Qn) < 0.3, rng.integers(1, 40, size=Qn), 0).astype(np.uint32)
+    keep = (tuple(sx.to_dev_u32(c) for c in cen), sx.to_dev_u32(r), sx.to_dev_u32(k))
+    q = sx.make_queries(Qn, keep[0], keep[1], keep[2], sx.MODE_MIXED, 0)
+    g = orc.Grid(orc.Lattice(log2, F, mask), pts)
+    ref = g.mixed(k, r, queries=tuple(cen))
+    g.close()
+    fb = int(((r > (2 << F)) & (k == 0)).sum())
+    assert fb > 100 and int((k > 0).sum()) > 1000
+    for grouped in (0, 1):
+        say(f"ids-only stash, two dist2 writes, grouped={grouped}")
+        launch = sx.LaunchConfig(grouped=grouped)
+        buf = sx.QueryBuffers(Qn, 0, want_dist2=False)
+        sx.count(lat, tab, q, buf, launch)
+        total = int(buf.row_ptr[-1].item())
+        buf.grow(max(total, 1))
+        buf.reserve_stash(max(total, 1))
+        sx.count(lat, tab, q, buf, launch)
+        buf.dist2 = torch.empty(max(buf.capacity, 1), dtype=torch.int64, device="cuda")
+        for it in range(2):
+            buf.ids.fill_(-1)
+            buf.dist2.fill_(-1)
+            sx.write(lat, tab, q, buf, launch)
+            torch.cuda.synchronize()
+            code, flags = lat.status()
+            assert code == sx.OK and not (flags & sx.FLAG_CAPACITY), (code, flags)
+            assert_same(buf.host(), ref, f"grouped {grouped}, write {it}")
+    del keep
+
+
 def test_stash_repeated_cycles_full_size(sx, orc):
     """The uneven-radius workload at full size, three count/write cycles on
     one workspace with the stash sized once."""

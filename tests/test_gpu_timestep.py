@@ -169,9 +169,10 @@ def test_full_size_timestep_in_the_benchmark_launch(sx, orc, resident):
     """The moving-agent workload at full size (8,388,608 agents in a cyclic
     256^3 lattice, r = 3 cells) in the launch the benchmark times (groups of
     queries, rows kept in the count pass): one eager step and three graph
-    replays, then every position and 20,000 sampled rows against the oracle's
-    replay; with `resident` the records are moved in place instead of the
-    lattice being rebuilt from positions."""
+    replays, then every position, the neighbour-count checksum over all
+    8,388,608 rows and 20,000 sampled rows against the oracle's replay; with
+    `resident` the records are moved in place instead of the lattice being
+    rebuilt from positions."""
     import torch
 
     from paper_cs_0608108_amd import synth, timestep
@@ -203,7 +204,12 @@ def test_full_size_timestep_in_the_benchmark_launch(sx, orc, resident):
     ids = sim.buf.ids[torch.from_numpy(idx).to(sim.buf.ids.device)].cpu().numpy().view(np.uint32)
     g = orc.Grid(L, cur)
     ref = g.radius(r, queries=tuple(np.asarray(c)[rows] for c in cur))
+    counts = g.radius_counts(r)
     g.close()
+    orp = np.zeros(n + 1, np.int64)
+    orp[1:] = np.cumsum(counts)
+    assert sim.checksum() == orc.count_checksum(orp), "count checksum over all rows"
+    assert np.array_equal(rp, orp), "every row length"
     srp = np.zeros(len(rows) + 1, np.int64)
     srp[1:] = np.cumsum(rp[rows + 1] - rp[rows])
     assert np.array_equal(srp, ref.row_ptr), "row lengths"
