@@ -342,6 +342,28 @@ sphidx_status sphidx_write(const sphidx_lattice* lat, const sphidx_tables* tab, 
 sphidx_status sphidx_query(const sphidx_lattice* lat, const sphidx_tables* tab, const sphidx_queries* q,
                            sphidx_csr* csr, const sphidx_launch* launch, void* stream);
 
+/* For callers that cannot allocate device memory (work under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * as sphidx_query, with the query workspace taken from a fixed array of
+ * SPHIDX_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends.  The call allocates nothing and calls no
+ * allocating routine.
+ *   csr    outputs as for sphidx_query; workspace_dev must be NULL and
+ *          workspace_bytes 0 (INVALID_ARG otherwise)
+ *   q      at most SPHIDX_NOALLOC_MAX_QUERIES queries (CAPACITY otherwise,
+ *          nothing enqueued)
+ *   tab    must already be on the device (tables built or loaded on a host
+ *          with a device are); INVALID_ARG otherwise
+ * The array beyond the minimum workspace is the stash, so rows that do not
+ * fit it are walked again by the write pass (any batch is correct).  Every
+ * call on a GPU uses that GPU's one array and leaves its contents there:
+ * calls that overlap on one GPU (other streams, other host threads) race and
+ * must be serialised by the caller.  Device selection: the current device. */
+#define SPHIDX_NOALLOC_MAX_QUERIES 65536u
+#define SPHIDX_NOALLOC_SCRATCH_BYTES (32u << 20)
+sphidx_status sphidx_query_noalloc(const sphidx_lattice* lat, const sphidx_tables* tab, const sphidx_queries* q,
+                                   sphidx_csr* csr, const sphidx_launch* launch, void* stream);
+
 /* Pass 1 of a radius query with the default launch (mode forced to
  * RADIUS): the row sizes of Section II.A's neighbourhoods, scanned into
  * csr->row_ptr_dev (row_ptr[Q] = total pairs).  The workspace of `csr` is

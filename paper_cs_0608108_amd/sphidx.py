@@ -87,6 +87,8 @@ SIGNATURES = {
                                     ctypes.POINTER(LaunchDesc), P]),
     "sphidx_query": (ctypes.c_int, [P, P, ctypes.POINTER(Queries), ctypes.POINTER(CSRDesc),
                                     ctypes.POINTER(LaunchDesc), P]),
+    "sphidx_query_noalloc": (ctypes.c_int, [P, P, ctypes.POINTER(Queries), ctypes.POINTER(CSRDesc),
+                                            ctypes.POINTER(LaunchDesc), P]),
     "sphidx_radius_count": (ctypes.c_int, [P, P, ctypes.POINTER(Queries), ctypes.POINTER(CSRDesc), P]),
     "sphidx_radius_query": (ctypes.c_int, [P, P, ctypes.POINTER(Queries), ctypes.POINTER(CSRDesc), P]),
     "sphidx_knn_query": (ctypes.c_int, [P, P, ctypes.POINTER(Queries), ctypes.POINTER(CSRDesc), P]),
