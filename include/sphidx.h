@@ -260,6 +260,18 @@ size_t sphidx_query_stash_bytes(uint64_t pairs, int want_dist2);
                                    reversal distances below.  Needs tables. */
 #define SPHIDX_METHOD_LIST 3u   /* every query walks the non-empty cell list (needs an attached list;
                                    tables unused) */
+#define SPHIDX_METHOD_PAPER64 4u /* the paper's own table design (Section III.A): per cell entries
+                                   sorted by b^2 = sum max(|o|-1, 0)^2, the unshaved table below
+                                   floor(d)^2 and, up to floor(d^2), one of 64 tables specialised on
+                                   the six flags [frac(d) < zeta] (zeta = e - f up, f down), which leave
+                                   out ahead of time the cells the one-direction rule and Eq. 2
+                                   reject; the run-time test of Eq. 1 on the cells at or above d - 1;
+                                   every object of a kept cell tested.  One cell per lane, one query
+                                   per wavefront (grouped ignored, no LDS staging).  Needs tables whose
+                                   cap is at most 31 cells (RADIUS otherwise); queries the tables do
+                                   not serve take the cube scan, as with SPHERE.  For comparing the
+                                   designs: the row walk of SPHERE keeps exactly the same cells' objects
+                                   with fewer, longer rows */
 
 #define SPHIDX_SCHED_PLAIN 0u      /* one launch, each wave owns a fixed slice of queries */
 #define SPHIDX_SCHED_PERSISTENT 1u /* resident waves pull query tiles from per-XCD work queues */
@@ -272,7 +284,10 @@ typedef struct {
     uint32_t blocks_per_cu;   /* persistent residency; 0 = default */
     uint32_t sort_cap;        /* per-wave LDS row buffer (64, 128 or 256); longer rows take the
                                  windowed top-M path; 0 = 256 */
-    uint32_t table_in_lds;    /* 1: stage the whole row table in LDS (CAPACITY if it does not fit) */
+    uint32_t table_in_lds;    /* 1: stage the whole row table in LDS (CAPACITY if it does not fit);
+                                 2: stage in chunks: the first rows of every (y, z) class table, as
+                                 many as fit the LDS beside the passes' buffers (CAPACITY below 16),
+                                 the rest read from device memory */
     uint32_t interior;        /* count pass, sphere method: 0 = auto (on when objects per cell >= 1),
                                  1 = off, 2 = on: cells wholly inside the sphere are counted whole */
     uint32_t* stats_dev; /* optional uint32[4*Q]: per query walked entries, kept cells,
@@ -423,6 +438,28 @@ sphidx_status sphidx_move_agents_counted(const sphidx_lattice_desc* desc, uint64
  * scratch), SPHIDX_ERR_CAPACITY (scratch too small). */
 sphidx_status sphidx_move_resident(sphidx_lattice* lat, uint64_t seed, uint32_t step, uint32_t* step_dev,
                                    void* scratch_dev, size_t scratch_bytes, void* stream);
+
+/* Incremental maintenance restricted to the objects that change cell
+ * (Section I: the objects' cells are kept up to date as they move).  The
+ * lattice's records are moved by the displacement of sphidx_move_agents
+ * (keyed by object id); an object that stays in its cell keeps its rank
+ * among its cell's stayers, found by one scan of stay flags over the sorted
+ * records, and takes no atomic; only an object that changes cell takes one,
+ * for its rank among its new cell's arrivals, which follow the stayers.
+ *   lat, step, step_dev  as in sphidx_move_resident
+ *   scratch_dev  device buffer of at least
+ *                sphidx_move_incremental_scratch_bytes(lat) bytes (the moved
+ *                records, arrival ranks, the previous cell starts and the
+ *                new counts), 256-byte aligned, owned by the caller
+ * Cell starts and cell contents equal those of sphidx_move_agents followed
+ * by sphidx_build_lattice (the order inside a cell can differ: stayers keep
+ * their order, arrivals follow in any order).  Every object stays usable:
+ * clipped axes clamp to the region.
+ * Errors: SPHIDX_ERR_INVALID_ARG (null lattice, missing or misaligned
+ * scratch), SPHIDX_ERR_CAPACITY (scratch too small). */
+size_t sphidx_move_incremental_scratch_bytes(const sphidx_lattice* lat);
+sphidx_status sphidx_move_incremental(sphidx_lattice* lat, uint64_t seed, uint32_t step, uint32_t* step_dev,
+                                      void* scratch_dev, size_t scratch_bytes, void* stream);
 
 /* The lattice's objects as by-id coordinates: x_dev[id] = record x (normalised:
  * cyclic axes wrapped), and so on, for the n objects of the last build. */

@@ -82,6 +82,7 @@ def _load():
         "orc_move": (None, [D, U64, U32, U32, P, P, P]),
         "orc_count_checksum": (None, [P, U32, P]),
         "orc_num_threads": (ctypes.c_int, []),
+        "orc_set_num_threads": (None, [ctypes.c_int]),
         "orc_cube_cells": (I64, [D, P, U32]),
     }
     for name, (res, args) in sig.items():
@@ -323,3 +324,8 @@ def cube_cells(lat: Lattice, q, r_fx) -> int:
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on."""
+    _load().orc_set_num_threads(int(n))

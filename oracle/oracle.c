@@ -173,6 +173,15 @@ void orc_result_free(orc_result *r) {
     free(r);
 }
 
+/* Threads of the OpenMP loops from now on (1 = serial). */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

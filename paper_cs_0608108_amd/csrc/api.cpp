@@ -90,12 +90,17 @@ TabArgs tab_args(const sphidx_tables* t) {
     T.nr = t->nr;
     T.rmax = t->rmax_fx;
     T.total = (uint32_t)t->h_rows.size();
+    T.nrcls = t->nrclasses;
     T.has = 1;
+    T.p_off = t->d_poff;
+    T.p_b2 = t->d_pb2;
+    T.p_lo = t->d_plo;
+    T.p_nb2 = t->pnb2;
     return T;
 }
 
 struct Launch {
-    uint32_t method, persistent, waves, tile, bpc, cap, tab_lds, interior, no_stash, grouped;
+    uint32_t method, persistent, waves, tile, bpc, cap, tab_lds, lds_chunk, interior, no_stash, grouped;
     uint32_t weight, rev, knn_rev, model;
     uint32_t* stats;
     uint32_t* method_out;
@@ -110,6 +115,8 @@ sphidx_status resolve_launch(const sphidx_launch* in, const sphidx_tables* tab, 
     o.bpc = (in && in->blocks_per_cu) ? in->blocks_per_cu : 8u;
     o.cap = (in && in->sort_cap) ? in->sort_cap : 256u;
     o.tab_lds = in ? in->table_in_lds : 0u;
+    o.lds_chunk = 0;
+    if (o.tab_lds > 2) return SPHIDX_ERR_INVALID_ARG;
     o.interior = in ? in->interior : 0u;
     if (o.interior > 2) return SPHIDX_ERR_INVALID_ARG;
     o.no_stash = in ? in->no_stash : 0u;
@@ -127,14 +134,33 @@ sphidx_status resolve_launch(const sphidx_launch* in, const sphidx_tables* tab, 
     o.ev_begin = in ? (hipEvent_t)in->event_begin : nullptr;
     o.ev_end = in ? (hipEvent_t)in->event_end : nullptr;
     if (in && in->schedule > SPHIDX_SCHED_PERSISTENT) return SPHIDX_ERR_INVALID_ARG;
-    if (o.method > SPHIDX_METHOD_LIST) return SPHIDX_ERR_INVALID_ARG;
+    if (o.method > SPHIDX_METHOD_PAPER64) return SPHIDX_ERR_INVALID_ARG;
     if (!(o.waves == 1 || o.waves == 2 || o.waves == 4)) return SPHIDX_ERR_INVALID_ARG;
     if (o.cap < 64 || o.cap > 256 || (o.cap & (o.cap - 1))) return SPHIDX_ERR_INVALID_ARG;
     if (o.tile > 4096 || o.bpc > 64) return SPHIDX_ERR_INVALID_ARG;
-    const bool tables = o.method == SPHIDX_METHOD_SPHERE || o.method == SPHIDX_METHOD_AUTO;
+    const bool tables = o.method == SPHIDX_METHOD_SPHERE || o.method == SPHIDX_METHOD_AUTO ||
+                        o.method == SPHIDX_METHOD_PAPER64;
     if (tables && !tab) return SPHIDX_ERR_INVALID_ARG;
-    if (!tables) o.tab_lds = 0;
-    size_t tab_bytes = (o.tab_lds && tab) ? (tab->h_rows.size() * 4 + 15) / 16 * 16 : 0;
+    // the paper's tables exist only for offsets up to kPaperMaxOff cells
+    if (o.method == SPHIDX_METHOD_PAPER64 && !tab->pm) return SPHIDX_ERR_RADIUS;
+    // the row table is what LDS staging holds; the paper's cell tables and
+    // the other walks read device memory
+    if (o.method != SPHIDX_METHOD_SPHERE && o.method != SPHIDX_METHOD_AUTO) o.tab_lds = 0;
+    size_t tab_bytes = (o.tab_lds == 1 && tab) ? (tab->h_rows.size() * 4 + 15) / 16 * 16 : 0;
+    if (o.tab_lds == 2 && tab) {
+        // the first rows of every (y, z) class, as many as fit beside the
+        // largest per-block buffer of the passes
+        size_t worst = 0;
+        for (int pass = 1; pass <= 5; ++pass) worst = std::max(worst, query_lds_bytes(pass, o.cap, o.waves, 0));
+        const size_t room = kMaxBlockLds > worst ? kMaxBlockLds - worst : 0;
+        uint32_t longest = 0;
+        for (uint32_t c = 0; c < tab->nrclasses; ++c)
+            longest = std::max(longest, tab->h_rclass_start[c + 1] - tab->h_rclass_start[c]);
+        const uint32_t chunk = (uint32_t)std::min<size_t>(room / (4u * tab->nrclasses), longest) & ~3u;
+        if (chunk < 16) return SPHIDX_ERR_CAPACITY;
+        o.lds_chunk = chunk;
+        tab_bytes = ((size_t)tab->nrclasses * chunk * 4 + 15) / 16 * 16;
+    }
     for (int pass = 1; pass <= 5; ++pass) {
         if (query_lds_bytes(pass, o.cap, o.waves, 0) > kMaxBlockLds) return SPHIDX_ERR_INVALID_ARG;
         if (o.tab_lds && query_lds_bytes(pass, o.cap, o.waves, tab_bytes) > kMaxBlockLds) return SPHIDX_ERR_CAPACITY;
@@ -317,7 +343,8 @@ sphidx_status run_pass(int pass, const sphidx_lattice* lat, const sphidx_tables*
     if (s != SPHIDX_OK) return s;
     if (pass == 1 && csr->capacity > 0 && !csr->ids_dev) return SPHIDX_ERR_INVALID_ARG;
     if (tab && tab->F != lat->desc.frac_bits) return SPHIDX_ERR_INVALID_ARG;
-    const bool tables = ln.method == SPHIDX_METHOD_SPHERE || ln.method == SPHIDX_METHOD_AUTO;
+    const bool tables = ln.method == SPHIDX_METHOD_SPHERE || ln.method == SPHIDX_METHOD_AUTO ||
+                        ln.method == SPHIDX_METHOD_PAPER64;
     if (ln.method == SPHIDX_METHOD_LIST && !lat->cell_list) return SPHIDX_ERR_INVALID_ARG;
     if (tab && tables && !tab->d_rows) {
         s = tables_upload(const_cast<sphidx_tables*>(tab));
@@ -326,7 +353,9 @@ sphidx_status run_pass(int pass, const sphidx_lattice* lat, const sphidx_tables*
     note_stream(lat, (void*)st);
     LatArgs L = lat_args(lat);
     TabArgs T = tab_args(tables ? tab : nullptr);
-    T.lds = ln.tab_lds;
+    T.lds = ln.tab_lds ? 1u : 0u;
+    T.lds_chunk = ln.lds_chunk;
+    T.paper = ln.method == SPHIDX_METHOD_PAPER64 ? 1u : 0u;
     QArgs A = q_args(q, csr, ln);
     if (pass == 0) plan_stash(A, csr, ln, ln.interior == 2);
     // counting wholly-inside cells whole saves object reads but costs a
@@ -337,7 +366,8 @@ sphidx_status run_pass(int pass, const sphidx_lattice* lat, const sphidx_tables*
     // count pass: radius queries in groups of several per wavefront (the
     // persistent schedule; not with per-query statistics or the interior
     // shortcut, which the grouped kernel does not implement)
-    A.group = pass == 0 && ln.persistent && ln.grouped && !ln.stats && !A.interior;
+    // (the paper's cell tables are walked one query per wavefront)
+    A.group = pass == 0 && ln.persistent && ln.grouped && !ln.stats && !A.interior && !T.paper;
     if (pass == 0) {
         s = dev_err(launch_query_pass(0, L, T, A, ln.waves, ln.bpc, st, ln.ev_begin, ln.ev_end));
         if (s != SPHIDX_OK) return s;
@@ -654,6 +684,19 @@ sphidx_status sphidx_move_resident(sphidx_lattice* lat, uint64_t seed, uint32_t 
     }
     if (e == hipSuccess) e = launch_build_records(lat, moved, n, st);
     return dev_err(e);
+}
+
+size_t sphidx_move_incremental_scratch_bytes(const sphidx_lattice* lat) {
+    return lat ? move_incremental_scratch_bytes(lat) : 0;
+}
+
+sphidx_status sphidx_move_incremental(sphidx_lattice* lat, uint64_t seed, uint32_t step, uint32_t* step_dev,
+                                      void* scratch_dev, size_t scratch_bytes, void* stream) {
+    if (!lat) return SPHIDX_ERR_INVALID_ARG;
+    if (!scratch_dev || (uintptr_t)scratch_dev % kAlign) return SPHIDX_ERR_INVALID_ARG;
+    if (scratch_bytes < move_incremental_scratch_bytes(lat)) return SPHIDX_ERR_CAPACITY;
+    note_stream(lat, stream);
+    return dev_err(launch_move_incremental(lat, seed, step, step_dev, scratch_dev, (hipStream_t)stream));
 }
 
 sphidx_status sphidx_lattice_positions(const sphidx_lattice* lat, uint32_t* x_dev, uint32_t* y_dev, uint32_t* z_dev,

@@ -142,6 +142,32 @@ inline uint64_t paper_gap(int o, uint64_t f, uint64_t e) {
 
 }  // namespace
 
+// The paper's tables laid out for the device (Section III.A): the 64
+// specialised tables, then the unshaved table, each sorted by b^2, as
+// packed offsets (10 bits per axis, two's complement) with their b^2;
+// start[t] .. start[t + 1] is table t (t = 64: the unshaved table).
+void paper_tables_flat(int m, std::vector<uint32_t>& off, std::vector<uint32_t>& b2,
+                       std::vector<uint32_t>& start) {
+    const PaperTables pt = paper_tables(m);
+    off.clear();
+    b2.clear();
+    start.assign(66, 0);
+    auto put = [&](const std::vector<UnshavedEntry>& tab) {
+        for (const UnshavedEntry& en : tab) {
+            off.push_back(((uint32_t)en.o[0] & 0x3FFu) | (((uint32_t)en.o[1] & 0x3FFu) << 10) |
+                          (((uint32_t)en.o[2] & 0x3FFu) << 20));
+            b2.push_back(en.b2);
+        }
+    };
+    for (uint32_t t = 0; t < 64; ++t) {
+        start[t] = (uint32_t)off.size();
+        put(pt.spec[t]);
+    }
+    start[64] = (uint32_t)off.size();
+    put(pt.base);
+    start[65] = (uint32_t)off.size();
+}
+
 extern "C" {
 
 sphidx_status sphidx_table_census(const sphidx_tables* tab, uint32_t nq, const uint32_t* fx_host,

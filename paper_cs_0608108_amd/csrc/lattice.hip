@@ -337,6 +337,10 @@ hipError_t launch_scan_i64(int64_t* data, uint32_t n, void* tmp, hipStream_t st)
 
 size_t scan_u32_tmp_words(size_t n) { return (n + kScanBlock - 1) / kScanBlock + 2; }
 
+hipError_t launch_scan_u32(uint32_t* data, size_t n, uint32_t* tmp, hipStream_t st) {
+    return scan_exclusive<uint32_t>(data, n, tmp, st);
+}
+
 // Rebuild from records (incremental maintenance): the same counting sort over
 // `recs` (n records, not the lattice's own array) into the lattice's records.
 hipError_t launch_build_records(const sphidx_lattice* lat, const uint4* recs, uint32_t n, hipStream_t st) {

@@ -48,7 +48,8 @@ extern "C" sphidx_status sphidx_query_noalloc(const sphidx_lattice* lat, const s
     // tables are uploaded when they are built or loaded on a host with a
     // device; a query must not upload them here
     const uint32_t method = launch ? launch->method : SPHIDX_METHOD_SPHERE;
-    const bool tables = method == SPHIDX_METHOD_SPHERE || method == SPHIDX_METHOD_AUTO;
+    const bool tables = method == SPHIDX_METHOD_SPHERE || method == SPHIDX_METHOD_AUTO ||
+                        method == SPHIDX_METHOD_PAPER64;
     if (tables && tab && !tab->d_rows) return SPHIDX_ERR_INVALID_ARG;
     void* ws = nullptr;
     const sphidx_status s = scratch_address(&ws);

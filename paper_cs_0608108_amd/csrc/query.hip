@@ -42,8 +42,9 @@ namespace {
 
 constexpr uint32_t kMaxId = 0xFFFFFFFFu;
 constexpr uint64_t kMaxD2 = ~0ull;
-// Walk kinds: sphere rows only, cube rows only, or either (chosen per query).
-constexpr int kSphere = 0, kCube = 1, kEither = 2;
+// Walk kinds: sphere rows only, cube rows only, either (chosen per query),
+// or the paper's cell tables (cube rows for the queries they do not serve).
+constexpr int kSphere = 0, kCube = 1, kEither = 2, kPaper = 3;
 
 // ---------------------------------------------------------------------------
 // Wave primitives
@@ -263,7 +264,8 @@ __global__ __launch_bounds__(256) void setup_kernel(LatArgs L, TabArgs T, QArgs 
         }
         // the tables serve centres inside the region, radii up to their cap
         // and, on cyclic axes, up to the limit where no offset repeats a cell
-        const bool usable = METHOD == kSphere && inside && cyc_ok && r <= T.rmax;
+        const bool tables = METHOD == kSphere || METHOD == kPaper;
+        const bool usable = tables && inside && cyc_ok && r <= T.rmax;
         bool sphere = usable, list = false;
         const uint32_t j = (uint32_t)(((uint64_t)r + (1u << T.rshift) - 1u) >> T.rshift);
         if (A.select == 2u) {
@@ -317,11 +319,32 @@ __global__ __launch_bounds__(256) void setup_kernel(LatArgs L, TabArgs T, QArgs 
                 }
             }
         }
-        fallback = valid && METHOD == kSphere && !usable;
+        fallback = valid && tables && !usable;
         // (chosen per query: the main kernels take every walk themselves)
-        to_list = valid && METHOD == kSphere && !sphere && A.select != 1u;
+        to_list = valid && tables && !sphere && A.select != 1u;
         uint32_t tb = 0, tend = 0, kb = 0, kend = 0;
-        if (sphere && valid) {
+        if (METHOD == kPaper && sphere && valid) {
+            // the paper's tables (Section III.A): with d = r / e, the unshaved
+            // table below floor(d)^2, then, up to floor(d^2), the table chosen
+            // by the six flags [frac(d) < zeta] (zeta: e - f up, f down);
+            // tb = the specialised part's first entry, ncube = the unshaved
+            // entries before it, tend = all entries
+            const uint32_t D0 = r >> L.F, fu = r & (e - 1u);
+            uint32_t tsel = 0;
+            for (int a = 0; a < 3; ++a) {
+                const uint32_t f = q[a] & (e - 1u);
+                if (fu < e - f) tsel |= 1u << (2 * a);
+                if (fu < f) tsel |= 1u << (2 * a + 1);
+            }
+            const uint32_t lo2 = D0 * D0;
+            const uint32_t b2max = (uint32_t)(((uint64_t)r * r) >> (2 * L.F));
+            const uint32_t* base_lo = T.p_lo + (size_t)64 * T.p_nb2;
+            const uint32_t* spec_lo = T.p_lo + (size_t)tsel * T.p_nb2;
+            const uint32_t nbase = base_lo[lo2] - base_lo[0];
+            tb = spec_lo[lo2];
+            tend = nbase + (spec_lo[b2max + 1] - tb);
+            ncube = nbase;
+        } else if (sphere && valid) {
             // row tables are specialised on the (y, z) sub-cell position
             const uint32_t cls = ((q[1] & (e - 1u)) >> (L.F - T.s)) | (((q[2] & (e - 1u)) >> (L.F - T.s)) << T.s);
             tb = T.cstart[cls];
@@ -355,7 +378,7 @@ __global__ __launch_bounds__(256) void setup_kernel(LatArgs L, TabArgs T, QArgs 
         d[0] = make_uint4(q[0], q[1], q[2], row);
         d[1] = make_uint4(r, k, flags, tb);
         // (sphere K-NN queries walk no cube: its fields carry the first radius)
-        const bool kfirst = sphere && valid && knn;
+        const bool kfirst = METHOD != kPaper && sphere && valid && knn;
         d[2] = make_uint4(tend, kfirst ? kb : ncube, kfirst ? kend : nn[0], nn[1]);
         d[3] = make_uint4((uint32_t)lo3[0], (uint32_t)lo3[1], (uint32_t)lo3[2], nn[2]);
     }
@@ -428,6 +451,23 @@ __device__ __forceinline__ uint32_t cube_cells(const LatArgs& L, const Query& s)
         n *= hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
     }
     return n;
+}
+
+// Row j of the class table that starts at tb ((y, z) class cls): from the
+// staged copy when it holds it, else from device memory.
+template <bool TLDS>
+__device__ __forceinline__ uint32_t row_word(const TabArgs& T, const uint32_t* tab_lds, uint32_t tb, uint32_t cls,
+                                             uint32_t j) {
+    if (TLDS) {
+        if (T.lds_chunk == 0) return tab_lds[tb + j];
+        if (j < T.lds_chunk) return tab_lds[cls * T.lds_chunk + j];
+    }
+    return T.rows[tb + j];
+}
+
+// (y, z) sub-cell class of a query (the row table it walks).
+__device__ __forceinline__ uint32_t row_class(const LatArgs& L, const TabArgs& T, const uint32_t* f) {
+    return (f[1] >> (L.F - T.s)) | ((f[2] >> (L.F - T.s)) << T.s);
 }
 
 // ---------------------------------------------------------------------------
@@ -631,6 +671,50 @@ __device__ __forceinline__ RowRef list_row(const LatArgs& L, const Query& s, uin
     return r;
 }
 
+// Entry `ent` of the paper's tables (Section III.A), one cell: the unshaved
+// table's entries below floor(d)^2 come first (ent < s.ncube), then the
+// query's specialised table from s.tb.  Cells with b e >= thr -- b at or
+// above d - 1 when thr = (r - e)^2 -- take the run-time test of Eq. 1 with
+// the paper's per-axis distances (b_o cells plus the distance to the face,
+// e - f up and f down); objects of the kept cell are then tested one by one.
+__device__ __forceinline__ RowRef paper_row(const LatArgs& L, const TabArgs& T, const Query& s, uint32_t ent,
+                                            bool has, uint64_t bound2, uint64_t thr2) {
+    const uint32_t idx = ent < s.ncube ? T.p_lo[(size_t)64 * T.p_nb2] + ent : s.tb + (ent - s.ncube);
+    const uint32_t w = has ? T.p_off[idx] : 0u;
+    const uint64_t b2e = has ? (uint64_t)T.p_b2[idx] << (2 * L.F) : 0ull;
+    const int o[3] = {((int)(w << 22)) >> 22, ((int)(w << 12)) >> 22, ((int)(w << 2)) >> 22};
+    const uint32_t e = 1u << L.F;
+    bool live = has;
+    uint32_t t[3];
+    uint64_t g2 = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const uint32_t La = 1u << L.lg[a];
+        uint32_t v = (uint32_t)((int)s.c[a] + o[a]);
+        if ((L.cyc >> a) & 1u)
+            v &= La - 1u;
+        else
+            live = live && v < La;
+        t[a] = v;
+        const uint32_t ao = (uint32_t)(o[a] < 0 ? -o[a] : o[a]);
+        const uint64_t g = o[a] == 0 ? 0ull : ((uint64_t)(ao - 1u) << L.F) + (o[a] > 0 ? e - s.f[a] : s.f[a]);
+        g2 += g * g;
+    }
+    if (b2e >= thr2 && g2 > bound2) live = false;
+    if (!live) t[0] = t[1] = t[2] = 0u;
+    const uint32_t cell = pack_cell(L, t[0], t[1], t[2]);
+    const uint32_t st = L.cs[cell];
+    RowRef r;
+    r.st0 = st;
+    r.cnt0 = live ? L.cs[cell + 1] - st : 0u;
+    r.st1 = st;
+    r.cnt1 = 0u;
+    r.ist = st;
+    r.icnt = 0u;
+    r.kept = live ? 1u : 0u;
+    return r;
+}
+
 // Minimum-image squared distance of an object to the centre: on a cyclic
 // axis ((p - q + W/2) mod W) - W/2; on a clipped axis plain p - q (both below
 // 2^30, so the difference fits an int).
@@ -730,25 +814,40 @@ __device__ __forceinline__ void walk(const LatArgs& L, const TabArgs& T, const u
                                      bool interior, uint32_t& walked, B&& bound2_now, S&& on_step) {
     const uint32_t lane = lane_id();
     const uint32_t pre = (s.flags & F_OUTSIDE) ? 1u : 0u;
-    const bool sphere = METHOD == kSphere || (METHOD == kEither && (s.flags & F_SPHERE));
+    const bool sphere = METHOD == kSphere || ((METHOD == kEither || METHOD == kPaper) && (s.flags & F_SPHERE));
     const uint32_t nent = sphere ? s.tend : s.nn[1] * s.nn[2];
     const uint32_t total = nent + pre;
-    const uint32_t* rows = TLDS ? tab_lds + s.tb : T.rows + s.tb;
+    const uint32_t rcls = TLDS ? row_class(L, T, s.f) : 0u;
     // entry index of this lane's row in the current step (pseudo-row: ~0)
     uint32_t ent = lane - pre;
     uint32_t nxt = 0;
-    if (sphere && ent < nent) nxt = rows[ent];
+    if (METHOD != kPaper && sphere && ent < nent) nxt = row_word<TLDS>(T, tab_lds, s.tb, rcls, ent);
     const double inv_ny = (!sphere && s.nn[1]) ? 1.0 / (double)s.nn[1] : 0.0;
     for (uint32_t base = 0; base < total; base += 64, ent += 64) {
         const bool is_out = pre && base == 0 && lane == 0;
         RowRef r;
-        if (METHOD == kSphere || (METHOD == kEither && sphere)) {
+        if (METHOD == kPaper && sphere) {
+            const uint64_t bound2 = bound2_now();
+            // entries are sorted by b^2, and b e is below every cell's
+            // distance: once b^2 e^2 exceeds the bound nothing further can
+            // hold anything closer
+            if (KEY_STOP && base > 0) {
+                const uint32_t j = base - pre;
+                const uint32_t idx = j < s.ncube ? T.p_lo[(size_t)64 * T.p_nb2] + j : s.tb + (j - s.ncube);
+                if (((uint64_t)uni(T.p_b2[idx]) << (2 * L.F)) > bound2) break;
+            }
+            // the run-time test from b >= d - 1 on (every cell when d < 1)
+            const uint32_t e = 1u << L.F;
+            const uint32_t rt = uni(isqrt64(bound2));
+            const uint64_t thr2 = rt > e ? sq(rt - e) : 0ull;
+            r = paper_row(L, T, s, ent, ent < nent, bound2, thr2);
+        } else if (METHOD == kSphere || (METHOD == kEither && sphere)) {
             const uint64_t bound2 = bound2_now();
             // rows are sorted by key: once the key exceeds the bound no
             // further row can hold anything closer (the first row's key is 0)
             if (KEY_STOP && base > 0 && uni64((uint64_t)T.rkey[s.tb + base - pre]) > bound2) break;
             const uint32_t w = nxt;
-            if (ent + 64 < nent) nxt = rows[ent + 64];
+            if (ent + 64 < nent) nxt = row_word<TLDS>(T, tab_lds, s.tb, rcls, ent + 64);
             r = sphere_row(L, s, w, ent < nent, bound2, interior);
         } else if (s.flags & F_LIST) {
             r = list_row(L, s, ent, ent < nent, bound2_now());
@@ -835,20 +934,35 @@ __device__ __forceinline__ void for_each_query(uint32_t Q, const QArgs& A, uint3
     });
 }
 
-// Stage the whole row table in LDS (shared by the block's waves).
+// Stage the row table in LDS (shared by the block's waves): the whole table,
+// or, in chunks, the first lds_chunk rows of every (y, z) class -- the rows
+// nearest the centre, which every query of the class walks first.
 template <bool TLDS>
 __device__ __forceinline__ const uint32_t* stage_table(const TabArgs& T, char* smem) {
     if (!TLDS) return nullptr;
     uint32_t* t = (uint32_t*)smem;
-    for (uint32_t i = threadIdx.x; i < T.total; i += blockDim.x) t[i] = T.rows[i];
+    if (T.lds_chunk == 0) {
+        for (uint32_t i = threadIdx.x; i < T.total; i += blockDim.x) t[i] = T.rows[i];
+    } else {
+        const uint32_t n = T.nrcls * T.lds_chunk;
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const uint32_t c = i / T.lds_chunk, j = i - c * T.lds_chunk;
+            const uint32_t b = T.cstart[c];
+            t[i] = b + j < T.cstart[c + 1] ? T.rows[b + j] : 0u;
+        }
+    }
     __syncthreads();
     return t;
 }
 
 template <bool TLDS>
 __device__ __forceinline__ size_t table_lds_bytes(const TabArgs& T) {
-    return TLDS ? (((size_t)T.total * 4 + 15) & ~(size_t)15) : 0;
+    if (!TLDS) return 0;
+    const size_t words = T.lds_chunk ? (size_t)T.nrcls * T.lds_chunk : (size_t)T.total;
+    return (words * 4 + 15) & ~(size_t)15;
 }
+
+
 
 // ---------------------------------------------------------------------------
 // Ordering a row by (dist^2, id) in LDS.
@@ -1129,7 +1243,8 @@ __global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs 
     for_each_query(nq, A, queue_set(A, FROM_LIST ? (int)A.list_set : kQCount), [&](uint32_t ti_) {
         const uint32_t qi = FROM_LIST ? uni(A.list[ti_]) : ti_;
         const Query s = load_query(L, A, qi);
-        if (METHOD == kSphere && (s.flags & F_VALID) && !(s.flags & F_SPHERE)) return;  // fallback list
+        if ((METHOD == kSphere || METHOD == kPaper) && (s.flags & F_VALID) && !(s.flags & F_SPHERE))
+            return;  // fallback list
         const bool knn = s.flags & F_KNN;
         if (KSTASH && knn && (s.flags & F_VALID) && s.k <= 64u) {
             // the row itself: lane i ends with the i-th nearest
@@ -1436,8 +1551,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                     const bool live = act && !is_out;
                     RowRef r;
                     if (sph) {
-                        const uint32_t* rws = TLDS ? tab_lds : T.rows;
-                        const uint32_t w = live ? rws[sq.tb + ent] : 0u;
+                        const uint32_t w =
+                            live ? row_word<TLDS>(T, tab_lds, sq.tb, TLDS ? row_class(L, T, sq.f) : 0u, ent) : 0u;
                         r = sphere_row(L, sq, w, live, sq.r2, false);
                     } else {
                         const double inv_ny = sq.nn[1] ? 1.0 / (double)sq.nn[1] : 0.0;
@@ -1717,7 +1832,8 @@ __global__ __launch_bounds__(256) void write_kernel(LatArgs L, TabArgs T, QArgs 
         const uint32_t qi = FROM_LIST ? uni(A.list[ti_]) : (from_walk ? uni(A.walkq[ti_]) : ti_);
         if (FROM_LIST && stashed && uni(A.soff[qi]) != kMaxId) return;  // copied by the gather kernel
         const Query s = load_query(L, A, qi);
-        if (METHOD == kSphere && (s.flags & F_VALID) && !(s.flags & F_SPHERE)) return;  // fallback list
+        if ((METHOD == kSphere || METHOD == kPaper) && (s.flags & F_VALID) && !(s.flags & F_SPHERE))
+            return;  // fallback list
         const int64_t rb = A.row_ptr[s.row];
         const uint32_t rowlen = (uint32_t)(A.row_ptr[s.row + 1] - rb);
         if (rowlen == 0 || !(s.flags & F_VALID)) return;
@@ -2011,11 +2127,14 @@ __global__ __launch_bounds__(256) void gather_kernel(QArgs A, const uint4* pts, 
     }
 }
 
-// Kernel choice by variant: cube, sphere, sphere with the row table in LDS.
+// Kernel choice by variant: cube, sphere, sphere with the row table in LDS;
+// SPHIDX_PICKP adds variant 3, the paper's cell tables.
 #define SPHIDX_PICK(KERNEL, variant, SPH, ...)                                     \
     ((variant) == 0 ? (const void*)KERNEL<kCube, false __VA_ARGS__>                \
      : (variant) == 1 ? (const void*)KERNEL<SPH, false __VA_ARGS__>                \
                       : (const void*)KERNEL<SPH, true __VA_ARGS__>)
+#define SPHIDX_PICKP(KERNEL, variant, SPH, ...) \
+    ((variant) == 3 ? (const void*)KERNEL<kPaper, false __VA_ARGS__> : SPHIDX_PICK(KERNEL, variant, SPH, __VA_ARGS__))
 
 hipError_t launch_ptr(const void* fn, uint32_t nq, const QArgs& q, uint32_t waves, uint32_t bpc, size_t shmem,
                       hipStream_t st, const LatArgs& L, const TabArgs& T) {
@@ -2062,8 +2181,8 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
                              hipEvent_t ev_begin, hipEvent_t ev_end) {
     // optional timing events around the pass's main kernel(s)
     auto mark = [st](hipEvent_t ev) { return ev ? hipEventRecord(ev, st) : hipSuccess; };
-    const size_t tb = T.lds ? (((size_t)T.total * 4 + 15) & ~(size_t)15) : 0;
-    const int variant = !T.has ? 0 : (T.lds ? 2 : 1);
+    const size_t tb = tab_lds_bytes(T);
+    const int variant = !T.has ? 0 : T.paper ? 3 : (T.lds ? 2 : 1);
     const uint32_t lists = SPHIDX_NQSETS * SPHIDX_NQUEUE * SPHIDX_QSTRIDE;
     const uint32_t set_words = SPHIDX_NQUEUE * SPHIDX_QSTRIDE;
     hipError_t e;
@@ -2085,6 +2204,8 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
         // per-query descriptors (and, for the sphere method, the fallback list)
         if (variant == 0)
             setup_kernel<kCube><<<(q.Q + 255) / 256, 256, 0, st>>>(L, T, q);
+        else if (variant == 3)
+            setup_kernel<kPaper><<<(q.Q + 255) / 256, 256, 0, st>>>(L, T, q);
         else
             setup_kernel<kSphere><<<(q.Q + 255) / 256, 256, 0, st>>>(L, T, q);
         e = hipGetLastError();
@@ -2148,13 +2269,13 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
         const void* fn;
         if (ks)
             fn = either ? SPHIDX_PICK(count_kernel, variant, kEither, , false, true, true)
-                        : SPHIDX_PICK(count_kernel, variant, kSphere, , false, true, true);
+                        : SPHIDX_PICKP(count_kernel, variant, kSphere, , false, true, true);
         else if (q.stash)
             fn = either ? SPHIDX_PICK(count_kernel, variant, kEither, , false, true, false)
-                        : SPHIDX_PICK(count_kernel, variant, kSphere, , false, true, false);
+                        : SPHIDX_PICKP(count_kernel, variant, kSphere, , false, true, false);
         else
             fn = either ? SPHIDX_PICK(count_kernel, variant, kEither, , false, false, false)
-                        : SPHIDX_PICK(count_kernel, variant, kSphere, , false, false, false);
+                        : SPHIDX_PICKP(count_kernel, variant, kSphere, , false, false, false);
         e = launch_ptr(fn, q.Q, q, w, b, query_lds_bytes(lp, q.sort_cap, w, tb), st, L, T);
         if (e == hipSuccess) e = mark(ev_end);
         if (e != hipSuccess || variant == 0 || either) return e;
@@ -2174,7 +2295,7 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
         gather_kernel<<<(q.Q + 255) / 256, 256, 0, st>>>(q, L.pts, L.status);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         e = launch_ptr(either ? SPHIDX_PICK(write_kernel, variant, kEither, , false)
-                              : SPHIDX_PICK(write_kernel, variant, kSphere, , false),
+                              : SPHIDX_PICKP(write_kernel, variant, kSphere, , false),
                        q.Q, q, w, b, sh1, st, L, T);
         if (e == hipSuccess) e = mark(ev_end);
         if (e != hipSuccess) return e;
@@ -2190,12 +2311,12 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
         ql.list = q.longq;
         ql.list_count = q.long_count;
         ql.list_set = kQTopm;
-        return launch_ptr(SPHIDX_PICK(topm_kernel, variant, kEither, , true), 0, ql, w, b, sh2, st, L, T);
+        return launch_ptr(SPHIDX_PICKP(topm_kernel, variant, kEither, , true), 0, ql, w, b, sh2, st, L, T);
     }
     if ((e = mark(ev_begin)) != hipSuccess) return e;
     // rows kept by the count pass (does nothing otherwise), then the rest
     gather_kernel<<<(q.Q + 255) / 256, 256, 0, st>>>(q, L.pts, L.status);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    e = launch_ptr(SPHIDX_PICK(topm_kernel, variant, kEither, , false), q.Q, q, w, b, sh2, st, L, T);
+    e = launch_ptr(SPHIDX_PICKP(topm_kernel, variant, kEither, , false), q.Q, q, w, b, sh2, st, L, T);
     return e == hipSuccess ? mark(ev_end) : e;
 }

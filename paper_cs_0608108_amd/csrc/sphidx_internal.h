@@ -50,6 +50,16 @@ struct sphidx_tables {
     std::vector<int64_t> h_rkey;
     std::vector<uint32_t> h_rclass_start; // nrclasses + 1
     std::vector<uint32_t> h_rrindex;      // nrclasses * nr
+    // the paper's tables (Section III.A), built when the offsets stay within
+    // kPaperMaxOff cells: 64 specialised tables, then the unshaved table,
+    // each sorted by b^2 (packed offsets and b^2), and per table and value v
+    // the absolute index of its first entry with b^2 >= v
+    uint32_t pm = 0;    // offset bound m (0: not built)
+    uint32_t pnb2 = 0;  // values v per table in the index (3 m^2 + 2)
+    std::vector<uint32_t> h_poff, h_pb2, h_pstart, h_plo;
+    uint32_t* d_poff = nullptr;
+    uint32_t* d_pb2 = nullptr;
+    uint32_t* d_plo = nullptr;
     // device copies of the row table
     uint32_t* d_rows = nullptr;
     int64_t* d_rkey = nullptr;
@@ -88,6 +98,14 @@ struct TabArgs {
     uint32_t total;  // rows over all classes
     uint32_t has;    // 0: no tables (cube only)
     uint32_t lds;    // 1: stage the row table in LDS
+    uint32_t lds_chunk;  // with lds: rows staged per (y, z) class, the first of each (0: the whole table)
+    uint32_t nrcls;      // (y, z) classes of the row table
+    // the paper's tables (METHOD_PAPER64)
+    uint32_t paper;         // 1: walk them instead of the row table
+    const uint32_t* p_off;  // packed offsets, tables 0..63 then the unshaved table
+    const uint32_t* p_b2;   // b^2 of each entry
+    const uint32_t* p_lo;   // [65][p_nb2]: first entry of table t with b^2 >= v
+    uint32_t p_nb2;
 };
 
 struct QArgs {
@@ -154,6 +172,17 @@ enum : uint32_t { kHdrMode = 0, kHdrElems = 1, kHdrHasD2 = 2, kHdrD2Off = 3 };
     ((SPHIDX_NQSETS * SPHIDX_NQUEUE + SPHIDX_NLISTS + SPHIDX_NQUEUE) * SPHIDX_QSTRIDE)
 #define SPHIDX_MAX_LOG2_SUM 30
 
+constexpr uint32_t kPaperMaxOff = 32;
+
+// LDS bytes of the staged row table: the whole table, or the first
+// lds_chunk rows of every (y, z) class.
+inline size_t tab_lds_bytes(const TabArgs& T) {
+    if (!T.lds) return 0;
+    const size_t words = T.lds_chunk ? (size_t)T.nrcls * T.lds_chunk : (size_t)T.total;
+    return (words * 4 + 15) & ~(size_t)15;
+}
+void paper_tables_flat(int m, std::vector<uint32_t>& off, std::vector<uint32_t>& b2, std::vector<uint32_t>& start);
+
 // ---------------------------------------------------------------------------
 // Launchers (defined in the .hip files).
 
@@ -175,6 +204,10 @@ hipError_t launch_records_to_ids(const uint4* pts, uint32_t n, uint32_t* x, uint
                                  hipStream_t st);
 hipError_t launch_move_agents(const sphidx_lattice_desc& d, uint64_t seed, uint32_t step, uint32_t* step_dev,
                               uint32_t* x, uint32_t* y, uint32_t* z, uint32_t n, hipStream_t st);
+size_t move_incremental_scratch_bytes(const sphidx_lattice* lat);
+hipError_t launch_move_incremental(sphidx_lattice* lat, uint64_t seed, uint32_t step, uint32_t* step_dev,
+                                   void* scratch, hipStream_t st);
+hipError_t launch_scan_u32(uint32_t* data, size_t n, uint32_t* tmp, hipStream_t st);
 hipError_t launch_count_checksum(const int64_t* row_ptr, uint32_t Q, uint64_t* out, hipStream_t st);
 int device_cu_count();
 size_t query_lds_bytes(int pass, uint32_t cap, uint32_t waves, size_t table_bytes);

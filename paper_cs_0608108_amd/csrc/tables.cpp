@@ -62,6 +62,10 @@ sphidx_status tables_upload(sphidx_tables* t) {
               put((void**)&t->d_rclass_start, t->h_rclass_start.data(), t->h_rclass_start.size() * 4) &&
               put((void**)&t->d_rrindex, t->h_rrindex.data(), t->h_rrindex.size() * 4) &&
               put((void**)&t->d_vcount, t->h_rindex.data(), t->h_rindex.size() * 4);
+    if (ok && t->pm)
+        ok = put((void**)&t->d_poff, t->h_poff.data(), t->h_poff.size() * 4) &&
+             put((void**)&t->d_pb2, t->h_pb2.data(), t->h_pb2.size() * 4) &&
+             put((void**)&t->d_plo, t->h_plo.data(), t->h_plo.size() * 4);
     return ok ? SPHIDX_OK : SPHIDX_ERR_OUT_OF_MEMORY;
 }
 
@@ -73,6 +77,10 @@ void free_device(sphidx_tables* t) {
     if (t->d_rclass_start) (void)hipFree(t->d_rclass_start);
     if (t->d_rrindex) (void)hipFree(t->d_rrindex);
     if (t->d_vcount) (void)hipFree(t->d_vcount);
+    if (t->d_poff) (void)hipFree(t->d_poff);
+    if (t->d_pb2) (void)hipFree(t->d_pb2);
+    if (t->d_plo) (void)hipFree(t->d_plo);
+    t->d_poff = t->d_pb2 = t->d_plo = nullptr;
     t->d_vcount = nullptr;
     t->d_rows = nullptr;
     t->d_rkey = nullptr;
@@ -136,6 +144,32 @@ void tables_build_rows(sphidx_tables* t) {
         }
     }
     t->h_rclass_start[t->nrclasses] = (uint32_t)t->h_rows.size();
+}
+
+// The paper's 64 specialised tables and the unshaved table (Section III.A)
+// for offsets up to m = ceil(rmax / e) + 1 cells, with the per-table b^2
+// index the query set-up reads; left unbuilt (pm = 0) beyond kPaperMaxOff.
+void tables_build_paper(sphidx_tables* t) {
+    const uint64_t e = 1ull << t->F;
+    const uint64_t m = ((uint64_t)t->rmax_fx + e - 1) / e + 1;
+    t->pm = 0;
+    t->h_poff.clear();
+    t->h_pb2.clear();
+    t->h_pstart.clear();
+    t->h_plo.clear();
+    if (m > kPaperMaxOff) return;
+    paper_tables_flat((int)m, t->h_poff, t->h_pb2, t->h_pstart);
+    t->pm = (uint32_t)m;
+    t->pnb2 = 3u * (uint32_t)(m * m) + 2u;
+    t->h_plo.assign((size_t)65 * t->pnb2, 0);
+    for (uint32_t tb = 0; tb < 65; ++tb) {
+        uint32_t p = t->h_pstart[tb];
+        const uint32_t end = t->h_pstart[tb + 1];
+        for (uint32_t v = 0; v < t->pnb2; ++v) {
+            while (p < end && t->h_pb2[p] < v) ++p;
+            t->h_plo[(size_t)tb * t->pnb2 + v] = p;
+        }
+    }
 }
 
 // Build on the host (validation of s / F / rmax is done by the caller).
@@ -214,6 +248,7 @@ sphidx_status tables_build_host(uint32_t F, uint32_t s, uint32_t rmax_fx, sphidx
     t->h_class_start[ncls] = (uint32_t)t->h_off.size();
     t->total = t->h_off.size();
     tables_build_rows(t);
+    tables_build_paper(t);
     return SPHIDX_OK;
 }
 
@@ -298,5 +333,6 @@ sphidx_status tables_load_file(const char* path, sphidx_tables* t) {
     }
     if (t->s > t->F || t->F > 30) return SPHIDX_ERR_IO;
     tables_build_rows(t);
+    tables_build_paper(t);
     return SPHIDX_OK;
 }

@@ -1,5 +1,7 @@
 // Moving agents (dynamic objects whose positions change every step,
 // Section I) and the order-independent checksum of per-row neighbour counts.
+#include <algorithm>
+
 #include "sphidx_internal.h"
 
 namespace {
@@ -105,6 +107,92 @@ __global__ __launch_bounds__(256) void checksum_kernel(const int64_t* __restrict
     }
 }
 
+// ---------------------------------------------------------------------------
+// Incremental lattice update (Section I: the objects' cells are kept up to
+// date as they move).  Objects that stay in their cell keep their order and
+// take no atomic; only the movers count themselves into their new cells.
+//   move     record p moved; stay flag = (new cell == old cell); a mover
+//            takes its rank among its new cell's arrivals (one atomic)
+//   scan     exclusive scan of the stay flags: S
+//   count    new count of cell c = stayers S[ocs[c+1]] - S[ocs[c]] + arrivals
+//   scan     the new counts -> new cell starts
+//   place    a stayer keeps its rank among its cell's stayers,
+//            S[p] - S[ocs[c]]; a mover goes after its new cell's stayers,
+//            at its arrival rank
+// (ocs: the cell starts before the step.)
+
+struct IncArgs {
+    uint32_t lg[3];
+    uint32_t F;
+    uint32_t cyc;
+    uint32_t ncells;
+    uint32_t n;
+    const uint4* old_pts;  // the lattice's records before the step (sorted)
+    uint4* moved;          // the same records moved, in the old order
+    uint4* new_pts;        // the lattice's records after the step
+    const uint32_t* ocs;   // cell starts before the step (ncells + 3)
+    uint32_t* cnt;         // arrivals per cell, then new counts, then new starts
+    uint32_t* stay;        // n + 1: stay flags, then their exclusive scan
+    uint32_t* arank;       // per mover: rank among its new cell's arrivals
+};
+
+// Cell of a normalised record: region cells packed z-major, ncells for a
+// clipped coordinate at or beyond the world width (the outside cell),
+// ncells + 1 for a clipped coordinate >= 2^30 (left out of queries).
+__device__ __forceinline__ uint32_t inc_cell(const IncArgs& a, const uint4& P) {
+    const uint32_t v[3] = {P.x, P.y, P.z};
+    bool out = false, bad = false;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (!((a.cyc >> k) & 1u)) {
+            bad |= v[k] >= (1u << 30);
+            out |= (v[k] >> (a.lg[k] + a.F)) != 0u;
+        }
+    }
+    if (bad) return a.ncells + 1u;
+    if (out) return a.ncells;
+    return ((v[2] >> a.F) << (a.lg[0] + a.lg[1])) | ((v[1] >> a.F) << a.lg[0]) | (v[0] >> a.F);
+}
+
+__global__ __launch_bounds__(256) void inc_move_kernel(MoveArgs m, IncArgs a) {
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    const uint32_t step = m.step_dev ? *m.step_dev : m.step;
+    const uint4 P = a.old_pts[p];
+    const uint4 N = make_uint4(moved(m, step, 0, P.w, P.x), moved(m, step, 1, P.w, P.y), moved(m, step, 2, P.w, P.z),
+                               P.w);
+    a.moved[p] = N;
+    const uint32_t c = inc_cell(a, P), c2 = inc_cell(a, N);
+    const bool st = c == c2;
+    a.stay[p] = st ? 1u : 0u;
+    if (!st) a.arank[p] = atomicAdd(&a.cnt[c2], 1u);
+}
+
+__global__ __launch_bounds__(256) void inc_count_kernel(IncArgs a) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.ncells + 2u) return;
+    a.cnt[c] += a.stay[a.ocs[c + 1]] - a.stay[a.ocs[c]];
+}
+
+__global__ __launch_bounds__(256) void inc_place_kernel(IncArgs a) {
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    const uint4 N = a.moved[p];
+    const uint32_t c = inc_cell(a, N);
+    const uint32_t s0 = a.stay[p];
+    uint32_t pos;
+    if (a.stay[p + 1] != s0)
+        pos = a.cnt[c] + (s0 - a.stay[a.ocs[c]]);  // stayer: rank among its cell's stayers
+    else
+        pos = a.cnt[c] + (a.stay[a.ocs[c + 1]] - a.stay[a.ocs[c]]) + a.arank[p];
+    a.new_pts[pos] = N;
+}
+
+__global__ __launch_bounds__(256) void copy_u32_kernel(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst,
+                                                       uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
 }  // namespace
 
 namespace {
@@ -172,4 +260,52 @@ hipError_t launch_count_checksum(const int64_t* row_ptr, uint32_t Q, uint64_t* o
     if (blocks == 0) blocks = 1;
     checksum_kernel<<<blocks, 256, 0, st>>>(row_ptr, Q, (unsigned long long*)out);
     return hipGetLastError();
+}
+
+// Incremental update of a lattice of moving objects: scratch holds the moved
+// records (16 B per object), the movers' arrival ranks (4 B per object), the
+// old cell starts and the per-cell counts (4 B per cell each); the lattice's
+// rank array holds the stay flags and their scan.
+size_t move_incremental_scratch_bytes(const sphidx_lattice* lat) {
+    const size_t n = lat->max_points, nc = (size_t)lat->ncells + 4;
+    return 16 * n + 4 * n + 4 * nc + 4 * nc + 1024;
+}
+
+hipError_t launch_move_incremental(sphidx_lattice* lat, uint64_t seed, uint32_t step, uint32_t* step_dev,
+                                   void* scratch, hipStream_t st) {
+    const uint32_t n = lat->n;
+    const size_t nc = (size_t)lat->ncells + 4;
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    char* b = (char*)scratch;
+    IncArgs a;
+    for (int k = 0; k < 3; ++k) a.lg[k] = lat->desc.log2_cells[k];
+    a.F = lat->desc.frac_bits;
+    a.cyc = lat->desc.cyclic_mask;
+    a.ncells = lat->ncells;
+    a.n = n;
+    a.old_pts = lat->pts;
+    a.new_pts = lat->pts;
+    a.moved = (uint4*)b;
+    a.arank = (uint32_t*)(b + al(16 * (size_t)n));
+    uint32_t* ocs = (uint32_t*)(b + al(16 * (size_t)n) + al(4 * (size_t)n));
+    a.ocs = ocs;
+    a.cnt = (uint32_t*)((char*)ocs + al(4 * nc));
+    a.stay = lat->rank;
+    const MoveArgs m = move_args(lat->desc, seed, step, step_dev, n);
+    const uint32_t ncs = lat->ncells + 3u;  // cell starts: region cells, outside, left out, end
+    const uint32_t cb = (uint32_t)std::min<size_t>((ncs + 255) / 256, 65536);
+    copy_u32_kernel<<<cb, 256, 0, st>>>(lat->cell_start, ocs, ncs);
+    hipError_t e = launch_fill_u32(a.cnt, 0u, ncs, st);
+    if (e != hipSuccess) return e;
+    const uint32_t blocks = (n + 255) / 256;
+    if (n > 0) inc_move_kernel<<<blocks, 256, 0, st>>>(m, a);
+    if (step_dev) advance_step_kernel<<<1, 1, 0, st>>>(step_dev);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_scan_u32(a.stay, n, lat->scan_tmp, st)) != hipSuccess) return e;
+    inc_count_kernel<<<(lat->ncells + 2u + 255u) / 256u, 256, 0, st>>>(a);
+    if ((e = launch_scan_u32(a.cnt, (size_t)lat->ncells + 2, lat->scan_tmp, st)) != hipSuccess) return e;
+    if (n > 0) inc_place_kernel<<<blocks, 256, 0, st>>>(a);
+    copy_u32_kernel<<<cb, 256, 0, st>>>(a.cnt, lat->cell_start, ncs);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_cell_list(lat, st);
 }

@@ -21,7 +21,7 @@ OK, ERR_INVALID_ARG, ERR_RANGE, ERR_RADIUS, ERR_CAPACITY, ERR_OOM, ERR_DEVICE, E
 FLAG_RANGE, FLAG_CAPACITY, FLAG_FALLBACK = 1, 2, 4
 MODE_RADIUS, MODE_KNN, MODE_MIXED = 0, 1, 2
 EXCLUDE_SELF = 1
-METHOD_SPHERE, METHOD_CUBE, METHOD_AUTO, METHOD_LIST = 0, 1, 2, 3
+METHOD_SPHERE, METHOD_CUBE, METHOD_AUTO, METHOD_LIST, METHOD_PAPER64 = 0, 1, 2, 3, 4
 SCHED_PLAIN, SCHED_PERSISTENT = 0, 1
 
 U32, I32, U64, I64, SZ, P = (ctypes.c_uint32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64,
@@ -97,6 +97,8 @@ SIGNATURES = {
     "sphidx_move_agents": (ctypes.c_int, [ctypes.POINTER(LatticeDesc), U64, U32, P, P, P, U32, P]),
     "sphidx_move_agents_counted": (ctypes.c_int, [ctypes.POINTER(LatticeDesc), U64, P, P, P, P, U32, P]),
     "sphidx_move_resident": (ctypes.c_int, [P, U64, U32, P, P, ctypes.c_size_t, P]),
+    "sphidx_move_incremental_scratch_bytes": (SZ, [P]),
+    "sphidx_move_incremental": (ctypes.c_int, [P, U64, U32, P, P, ctypes.c_size_t, P]),
     "sphidx_lattice_positions": (ctypes.c_int, [P, P, P, P, P]),
     "sphidx_count_checksum": (ctypes.c_int, [P, U32, P, P]),
     "sphidx_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -501,6 +503,20 @@ def move_resident(lat, seed, scratch, step=0, step_dev=None, stream=None):
     check(load().sphidx_move_resident(lat.handle, int(seed), int(step), None if step_dev is None else _ptr(step_dev),
                                       _ptr(scratch), int(scratch.numel() * scratch.element_size()), _stream(stream)),
           "move_resident")
+
+
+def move_incremental_scratch_bytes(lat):
+    return int(load().sphidx_move_incremental_scratch_bytes(lat.handle))
+
+
+def move_incremental(lat, seed, scratch, step=0, step_dev=None, stream=None):
+    """Move the lattice's records and update the lattice incrementally (only
+    objects that change cell take an atomic); `scratch` is a device tensor of
+    at least move_incremental_scratch_bytes(lat) bytes, 256-byte aligned."""
+    check(load().sphidx_move_incremental(lat.handle, int(seed), int(step),
+                                         None if step_dev is None else _ptr(step_dev), _ptr(scratch),
+                                         int(scratch.numel() * scratch.element_size()), _stream(stream)),
+          "move_incremental")
 
 
 def lattice_positions(lat, x, y, z, stream=None):

@@ -149,6 +149,72 @@ def test_resident_move_equals_move_then_build(sx, mask):
         sx.move_resident(lat_b, seed, scratch[1:])
 
 
+@pytest.mark.parametrize("mask", [7, 0, 5])
+def test_incremental_move_equals_move_then_build(sx, mask):
+    """Incremental maintenance restricted to the objects that change cell:
+    cell starts, cell contents and positions equal those of moving the by-id
+    arrays and building again, step after step (objects outside a clipped
+    region and unusable coordinates included); inside every cell the objects
+    that stayed keep their previous order and come first."""
+    import torch
+
+    from gpu_util import tiny_points
+    rng = np.random.default_rng(190 + mask)
+    log2, F, seed = (5, 4, 5), 10, 29
+    pts = tiny_points(rng, log2, F, mask, 6000, outside=(mask != 7), invalid=(mask == 0))
+    n = len(pts[0])
+    desc = sx.desc_of(log2, F, mask)
+    dev_a = [sx.to_dev_u32(a) for a in pts]
+    dev_b = [sx.to_dev_u32(a) for a in pts]
+    lat_a = sx.Lattice(log2, F, mask, n)
+    lat_b = sx.Lattice(log2, F, mask, n)
+    lat_a.build(*dev_a)
+    lat_b.build(*dev_b)
+    step_a = torch.zeros(1, dtype=torch.int32, device="cuda")
+    step_b = torch.zeros(1, dtype=torch.int32, device="cuda")
+    scratch = torch.empty(sx.move_incremental_scratch_bytes(lat_b) // 4 + 1, dtype=torch.int32, device="cuda")
+    out = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in range(3)]
+    for step in range(5):
+        say(f"incremental mask={mask} step={step}")
+        before = lat_b.host_arrays()
+        if step < 4:
+            sx.move_agents_counted(desc, seed, step_a, *dev_a)
+            sx.move_incremental(lat_b, seed, scratch, step_dev=step_b)
+        else:  # the host-step form
+            sx.move_agents(desc, seed, 40, *dev_a)
+            sx.move_incremental(lat_b, seed, scratch, step=40)
+        lat_a.build(*dev_a)
+        ha, hb = lat_a.host_arrays(), lat_b.host_arrays()
+        assert np.array_equal(ha["cell_start"], hb["cell_start"]), step
+        for u, v in zip(_cells_sorted(ha), _cells_sorted(hb)):
+            assert np.array_equal(u, v), step
+        sx.lattice_positions(lat_b, *out)
+        for a in range(3):
+            assert np.array_equal(sx.to_host_u32(out[a]), sx.to_host_u32(dev_a[a])), (step, a)
+        # stayers first, in their previous order
+        cs0, cs1 = before["cell_start"], hb["cell_start"]
+        ncell = len(cs1) - 1
+        old_cell = np.empty(n, np.int64)
+        old_rank = np.empty(n, np.int64)
+        pos = np.arange(n)
+        oc = np.searchsorted(cs0, pos, side="right") - 1
+        old_cell[before["ids"]] = oc
+        old_rank[before["ids"]] = pos
+        nc = np.searchsorted(cs1, pos, side="right") - 1
+        ids1 = hb["ids"]
+        stay = old_cell[ids1] == nc
+        for c in np.unique(nc[stay])[:200]:
+            sel = np.nonzero(nc == c)[0]
+            st = stay[sel]
+            k = int(st.sum())
+            assert st[:k].all(), (step, c)
+            assert np.all(np.diff(old_rank[ids1[sel[:k]]]) > 0), (step, c)
+        assert ncell > 0
+    assert int(step_b.item()) == 4
+    with pytest.raises(sx.SphidxError):
+        sx.move_incremental(lat_b, seed, scratch[:16])
+
+
 def test_resident_move_on_an_empty_lattice(sx):
     import torch
     lat = sx.Lattice((4, 4, 4), 8, 7, 16)
@@ -157,14 +223,53 @@ def test_resident_move_on_an_empty_lattice(sx):
     step = torch.zeros(1, dtype=torch.int32, device="cuda")
     sx.move_resident(lat, 5, e, step_dev=step)
     sx.lattice_positions(lat, e, e, e)
+    inc = torch.empty(sx.move_incremental_scratch_bytes(lat) // 4 + 1, dtype=torch.int32, device="cuda")
+    sx.move_incremental(lat, 5, inc, step_dev=step)
     h = lat.host_arrays()
     assert len(h["ids"]) == 0 and (h["cell_start"] == 0).all()
-    assert int(step.item()) == 1
+    assert int(step.item()) == 2
     code, flags = lat.status()
     assert code == sx.OK and flags == 0
 
 
-@pytest.mark.parametrize("resident", [False, True])
+def test_capacity_overflow_grows_the_buffers_and_redoes_the_query(sx, orc):
+    """Output buffers sized below the first step's pairs: the step sets the
+    capacity flag and writes no ids; ensure_capacity() grows the buffers,
+    runs the step's query again without moving the agents a second time and
+    captures the graph again, and the rows then equal the oracle's."""
+    import torch
+
+    from paper_cs_0608108_amd import synth, timestep
+    spec = synth.LatticeSpec((5, 5, 5), 16, 7)
+    n, seed, r = 20000, 23, 2 << 16
+    pts = synth.uniform_points(spec, n, seed)
+    sim = timestep.AgentSim(spec.log2_cells, spec.frac_bits, spec.cyclic_mask, pts, r, seed, headroom=0.5)
+    L = orc.Lattice(spec.log2_cells, spec.frac_bits, spec.cyclic_mask)
+    sim.step()
+    grew, flags = sim.ensure_capacity()
+    assert grew and flags & sx.FLAG_CAPACITY
+    assert sim.ensure_capacity() == (False, 0)
+    cur = pts
+    for t in range(sim.steps_done):
+        cur = orc.move(L, seed, t, cur)
+    ref = orc.Grid(L, cur).radius(r)
+    rp, ids, _ = sim.csr()
+    assert np.array_equal(rp, ref.row_ptr) and np.array_equal(ids, ref.ids), "after the eager step"
+    sim.capture()
+    for _ in range(3):
+        sim.replay()
+        sim.ensure_capacity()
+    torch.cuda.synchronize()
+    cur = pts
+    for t in range(sim.steps_done):
+        cur = orc.move(L, seed, t, cur)
+    ref = orc.Grid(L, cur).radius(r)
+    rp, ids, _ = sim.csr()
+    assert np.array_equal(rp, ref.row_ptr) and np.array_equal(ids, ref.ids), "after the replays"
+    assert sim.checksum() == orc.count_checksum(ref.row_ptr)
+
+
+@pytest.mark.parametrize("resident", [False, True, "incremental"])
 def test_full_size_timestep_in_the_benchmark_launch(sx, orc, resident):
     """The moving-agent workload at full size (8,388,608 agents in a cyclic
     256^3 lattice, r = 3 cells) in the launch the benchmark times (groups of
@@ -181,7 +286,7 @@ def test_full_size_timestep_in_the_benchmark_launch(sx, orc, resident):
     ln = sx.LaunchConfig(method=sx.METHOD_SPHERE, schedule=sx.SCHED_PERSISTENT, grouped=1, interior=1,
                          sort_cap=256, waves_per_block=4, tile=64, blocks_per_cu=8)
     sim = timestep.AgentSim(w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask, w.pts, r, seed, launch=ln,
-                            resident=resident)
+                            resident=resident is True, incremental=resident == "incremental")
     say(f"C4 full size resident={resident}")
     sim.step()
     torch.cuda.synchronize()
