@@ -332,6 +332,10 @@ typedef struct {
     uint32_t* method_dev;     /* optional uint32[Q], written by the count pass: the walk each query
                                  used (SPHIDX_METHOD_SPHERE, _CUBE or _LIST), or 0xFFFFFFFF for a
                                  query with an empty row by definition (invalid centre, K = 0) */
+    uint32_t long_row_waves;  /* write pass, radius rows longer than sort_cap and at most 2048 pairs:
+                                 the wavefronts that walk and order one such row together, as one
+                                 block (2, 4 or 8; 0 = 4); 1 = one wavefront per row, which takes
+                                 the row in windows of sort_cap, walking it once per window */
 } sphidx_launch;
 
 /* Bytes of device scratch a query call on Q queries needs. */

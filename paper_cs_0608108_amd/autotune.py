@@ -4,7 +4,9 @@ For one workload shape it times a small grid of launch configurations
 (waves per block, queries per work-queue grab, resident blocks per CU, LDS
 row buffer, row table staged in LDS whole, in per-class chunks or not at
 all, the interior shortcut, queries grouped per wavefront) on the device
-with HIP events and keeps the fastest.  Results
+with HIP events and keeps the fastest; then, with that launch, the waves
+that take one long radius row together, and the sub-cell bits of the
+tables when the caller can build them.  Results
 are cached as JSON keyed by the device architecture and the workload shape,
 so a later process reuses them without searching again.
 """
@@ -122,6 +124,23 @@ def tune(shape: dict, make_runner, method=sphidx.METHOD_SPHERE, schedule=sphidx.
         if log:
             log(f"tune {shape}: no candidate ran; using the default launch")
         return {}
+    # waves per long radius row (one block per row in the write pass; 1:
+    # one wave per row, windowed), with the launch found above
+    best_lw = None
+    for lw in (1, 2, 4, 8):
+        cfg = dict(best[1], long_row_waves=lw)
+        try:
+            ms = time_config(make_runner(sphidx.LaunchConfig(method=method, schedule=schedule, **cfg)))
+        except sphidx.SphidxError as err:
+            if log:
+                log(f"tune long_row_waves={lw} -> skipped ({err})")
+            continue
+        if log:
+            log(f"tune long_row_waves={lw} -> {ms:.3f} ms")
+        if best_lw is None or ms < best_lw[0]:
+            best_lw = (ms, cfg)
+    if best_lw is not None:
+        best = best_lw
     if subcell_runner is not None:
         ln = sphidx.LaunchConfig(method=method, schedule=schedule, **best[1])
         best_s = None

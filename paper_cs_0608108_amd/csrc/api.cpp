@@ -100,7 +100,7 @@ TabArgs tab_args(const sphidx_tables* t) {
 }
 
 struct Launch {
-    uint32_t method, persistent, waves, tile, bpc, cap, tab_lds, lds_chunk, interior, no_stash, grouped;
+    uint32_t method, persistent, waves, tile, bpc, cap, tab_lds, lds_chunk, interior, no_stash, grouped, long_waves;
     uint32_t weight, rev, knn_rev, model;
     uint32_t* stats;
     uint32_t* method_out;
@@ -123,6 +123,9 @@ sphidx_status resolve_launch(const sphidx_launch* in, const sphidx_tables* tab, 
     if (o.no_stash > 1) return SPHIDX_ERR_INVALID_ARG;
     o.grouped = in ? in->grouped : 0u;
     if (o.grouped > 1) return SPHIDX_ERR_INVALID_ARG;
+    o.long_waves = (in && in->long_row_waves) ? in->long_row_waves : 4u;
+    if (!(o.long_waves == 1 || o.long_waves == 2 || o.long_waves == 4 || o.long_waves == 8))
+        return SPHIDX_ERR_INVALID_ARG;
     o.stats = in ? in->stats_dev : nullptr;
     o.method_out = in ? in->method_dev : nullptr;
     o.weight = (in && in->select_weight) ? in->select_weight : 256u;
@@ -255,6 +258,7 @@ QArgs q_args(const sphidx_queries* q, sphidx_csr* csr, const Launch& ln) {
     A.knn_rev = ln.knn_rev;
     A.model = ln.model;
     A.method_out = ln.method_out;
+    A.long_waves = ln.long_waves;
     return A;
 }
 

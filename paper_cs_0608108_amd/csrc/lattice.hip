@@ -205,10 +205,11 @@ __global__ __launch_bounds__(kScanThreads) void scan_partials_kernel(T* __restri
     if (threadIdx.x == 0) partial[nb] = tot;
 }
 
-// Each thread scans its own run of kScanItems elements; with VEC (data
-// 16-byte aligned) a whole run is moved with 16-byte loads and stores.
+// Each thread scans its own run of kScanItems elements of `in` into `out`
+// (the same array for an in-place scan); with VEC (both 16-byte aligned) a
+// whole run is moved with 16-byte loads and stores.
 template <typename T, bool VEC>
-__global__ __launch_bounds__(kScanThreads) void scan_down_kernel(T* __restrict__ data, size_t n,
+__global__ __launch_bounds__(kScanThreads) void scan_down_kernel(const T* in, T* out, size_t n,
                                                                  const T* __restrict__ partial, uint32_t nb) {
     __shared__ T sh[kScanThreads / 64 + 1];
     constexpr int kVec = kScanItems * (int)sizeof(T) / 16;
@@ -216,14 +217,14 @@ __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(T* __restrict__
     const bool whole = VEC && base + kScanItems <= n;
     T v[kScanItems];
     if (whole) {
-        const uint4* p = (const uint4*)(data + base);
+        const uint4* p = (const uint4*)(in + base);
         uint4 w[kVec];
 #pragma unroll
         for (int k = 0; k < kVec; ++k) w[k] = p[k];
         __builtin_memcpy(v, w, sizeof(v));
     } else {
 #pragma unroll
-        for (int k = 0; k < kScanItems; ++k) v[k] = (base + k < n) ? data[base + k] : (T)0;
+        for (int k = 0; k < kScanItems; ++k) v[k] = (base + k < n) ? in[base + k] : (T)0;
     }
     T s = 0;
 #pragma unroll
@@ -239,30 +240,36 @@ __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(T* __restrict__
     if (whole) {
         uint4 w[kVec];
         __builtin_memcpy(w, o, sizeof(o));
-        uint4* p = (uint4*)(data + base);
+        uint4* p = (uint4*)(out + base);
 #pragma unroll
         for (int k = 0; k < kVec; ++k) p[k] = w[k];
     } else {
 #pragma unroll
         for (int k = 0; k < kScanItems; ++k)
-            if (base + k < n) data[base + k] = o[k];
+            if (base + k < n) out[base + k] = o[k];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) data[n] = partial[nb];
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = partial[nb];
 }
 
-// In-place exclusive scan of data[0..n); data[n] receives the total.
-// `partial` needs ceil(n / kScanBlock) + 1 elements.
+// Exclusive scan of in[0..n) into out[0..n) (in place when in == out);
+// out[n] receives the total.  `partial` needs ceil(n / kScanBlock) + 1
+// elements.
 template <typename T>
-hipError_t scan_exclusive(T* data, size_t n, T* partial, hipStream_t st) {
+hipError_t scan_exclusive_to(const T* in, T* out, size_t n, T* partial, hipStream_t st) {
     uint32_t nb = (uint32_t)((n + kScanBlock - 1) / kScanBlock);
     if (nb == 0) nb = 1;
-    scan_reduce_kernel<T><<<nb, kScanThreads, 0, st>>>(data, n, partial);
+    scan_reduce_kernel<T><<<nb, kScanThreads, 0, st>>>(in, n, partial);
     scan_partials_kernel<T><<<1, kScanThreads, 0, st>>>(partial, nb);
-    if (((uintptr_t)data & 15u) == 0)
-        scan_down_kernel<T, true><<<nb, kScanThreads, 0, st>>>(data, n, partial, nb);
+    if ((((uintptr_t)in | (uintptr_t)out) & 15u) == 0)
+        scan_down_kernel<T, true><<<nb, kScanThreads, 0, st>>>(in, out, n, partial, nb);
     else
-        scan_down_kernel<T, false><<<nb, kScanThreads, 0, st>>>(data, n, partial, nb);
+        scan_down_kernel<T, false><<<nb, kScanThreads, 0, st>>>(in, out, n, partial, nb);
     return hipGetLastError();
+}
+
+template <typename T>
+hipError_t scan_exclusive(T* data, size_t n, T* partial, hipStream_t st) {
+    return scan_exclusive_to<T>(data, data, n, partial, st);
 }
 
 }  // namespace
@@ -339,6 +346,10 @@ size_t scan_u32_tmp_words(size_t n) { return (n + kScanBlock - 1) / kScanBlock +
 
 hipError_t launch_scan_u32(uint32_t* data, size_t n, uint32_t* tmp, hipStream_t st) {
     return scan_exclusive<uint32_t>(data, n, tmp, st);
+}
+
+hipError_t launch_scan_u32_to(const uint32_t* in, uint32_t* out, size_t n, uint32_t* tmp, hipStream_t st) {
+    return scan_exclusive_to<uint32_t>(in, out, n, tmp, st);
 }
 
 // Rebuild from records (incremental maintenance): the same counting sort over

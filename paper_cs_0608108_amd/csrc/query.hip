@@ -36,6 +36,8 @@
 // non-empty cell list, whichever the comparison of their cells (Section
 // III.B, III.C) or of their estimated work finds smallest; a list entry is
 // one more kind of row.
+#include <algorithm>
+
 #include "sphidx_internal.h"
 
 namespace {
@@ -809,9 +811,13 @@ __device__ __forceinline__ bool for_candidates(const LatArgs& L, uint32_t st0, u
 // bound2_now() is re-read before every step (top-M shrinks it); KEY_STOP
 // enables the cut-off on sorted row keys; `interior` marks the cells wholly
 // inside the sphere (count pass).
+// The steps of 64 entries a wavefront takes start at `first` and follow
+// every `stride` entries (a block of W waves walks one row with first =
+// 64 w, stride = 64 W; a lone wave takes them all).
 template <int METHOD, bool TLDS, bool KEY_STOP, typename B, typename S>
 __device__ __forceinline__ void walk(const LatArgs& L, const TabArgs& T, const uint32_t* tab_lds, const Query& s,
-                                     bool interior, uint32_t& walked, B&& bound2_now, S&& on_step) {
+                                     bool interior, uint32_t& walked, B&& bound2_now, S&& on_step,
+                                     uint32_t first = 0, uint32_t stride = 64) {
     const uint32_t lane = lane_id();
     const uint32_t pre = (s.flags & F_OUTSIDE) ? 1u : 0u;
     const bool sphere = METHOD == kSphere || ((METHOD == kEither || METHOD == kPaper) && (s.flags & F_SPHERE));
@@ -819,11 +825,11 @@ __device__ __forceinline__ void walk(const LatArgs& L, const TabArgs& T, const u
     const uint32_t total = nent + pre;
     const uint32_t rcls = TLDS ? row_class(L, T, s.f) : 0u;
     // entry index of this lane's row in the current step (pseudo-row: ~0)
-    uint32_t ent = lane - pre;
+    uint32_t ent = lane - pre + first;
     uint32_t nxt = 0;
     if (METHOD != kPaper && sphere && ent < nent) nxt = row_word<TLDS>(T, tab_lds, s.tb, rcls, ent);
     const double inv_ny = (!sphere && s.nn[1]) ? 1.0 / (double)s.nn[1] : 0.0;
-    for (uint32_t base = 0; base < total; base += 64, ent += 64) {
+    for (uint32_t base = first; base < total; base += stride, ent += stride) {
         const bool is_out = pre && base == 0 && lane == 0;
         RowRef r;
         if (METHOD == kPaper && sphere) {
@@ -847,7 +853,7 @@ __device__ __forceinline__ void walk(const LatArgs& L, const TabArgs& T, const u
             // further row can hold anything closer (the first row's key is 0)
             if (KEY_STOP && base > 0 && uni64((uint64_t)T.rkey[s.tb + base - pre]) > bound2) break;
             const uint32_t w = nxt;
-            if (ent + 64 < nent) nxt = row_word<TLDS>(T, tab_lds, s.tb, rcls, ent + 64);
+            if (ent + stride < nent) nxt = row_word<TLDS>(T, tab_lds, s.tb, rcls, ent + stride);
             r = sphere_row(L, s, w, ent < nent, bound2, interior);
         } else if (s.flags & F_LIST) {
             r = list_row(L, s, ent, ent < nent, bound2_now());
@@ -1151,6 +1157,8 @@ __device__ __forceinline__ uint32_t topm_registers(const LatArgs& L, const TabAr
 
 // Queue sets of the work counters.
 constexpr int kQCount = 0, kQWrite = 1, kQTopm = 2, kQFbCount = 3, kQFbWrite = 4, kQWalk = 5, kQExtra = 6;
+// Longest radius row the block-per-row kernel orders in LDS (28 bytes per pair).
+constexpr uint32_t kLongCap = 2048;
 
 __device__ __forceinline__ uint32_t* queue_set(const QArgs& A, int set) {
     return A.queues + (size_t)set * SPHIDX_NQUEUE * SPHIDX_QSTRIDE;
@@ -1906,6 +1914,8 @@ __global__ __launch_bounds__(256) void topm_kernel(LatArgs L, TabArgs T, QArgs A
         const int64_t rb = A.row_ptr[s.row];
         const uint32_t rowlen = (uint32_t)(A.row_ptr[s.row + 1] - rb);
         if (rowlen == 0 || !(s.flags & F_VALID)) return;
+        // long radius rows the block-per-row kernel takes
+        if (FROM_LIST && A.long_waves > 1 && !(s.flags & F_KNN) && rowlen <= kLongCap) return;
         uint64_t* td = tdA;
         uint64_t* ud = tdB;
         uint32_t* tix = tiA;
@@ -2025,6 +2035,131 @@ __global__ __launch_bounds__(256) void topm_kernel(LatArgs L, TabArgs T, QArgs A
             wave_sync();
         }
     });
+}
+
+// ---------------------------------------------------------------------------
+// Pass 1, radius rows longer than a wavefront's LDS row buffer and at most
+// kLongCap pairs: one block of W waves per row.  Wave w walks the row's
+// table entries in 64-entry steps w, w + W, ..., tests their candidates and
+// appends its hits to a block-wide LDS buffer (one LDS atomic per wave
+// step).  The block then orders the row by (dist^2, id) with one bucket
+// sort -- bucket floor(n d^2 / r^2), capped at n - 1, is monotone in d^2 --
+// and an exact rank inside each bucket, and stores it.  Rows come from the
+// long-row list one per block; the top-M kernel leaves them alone.
+
+// Exclusive scan over the block of one value per thread; `wsum` holds one
+// word per wavefront.
+__device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t* wsum) {
+    const uint32_t wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint32_t incl = scan_add(v);
+    if (lane_id() == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t off = 0;
+    for (uint32_t w = 0; w < nw; ++w) off += w < wave ? wsum[w] : 0u;
+    __syncthreads();
+    return off + incl - v;
+}
+
+// Sort the block's n <= kLongCap pairs (td, ti) by (dist^2, id) and store
+// them at dst; every pair has dist^2 <= r2.
+__device__ void block_sort_store(const uint64_t* td, const uint32_t* ti, uint64_t* sd, uint32_t* si, uint32_t* hist,
+                                 uint32_t* wsum, uint32_t n, uint64_t r2, uint32_t* dst_ids, int64_t* dst_d2) {
+    const uint32_t tid = threadIdx.x, nt = blockDim.x;
+    const float scale = r2 > 0 ? (float)n / (float)r2 : 0.0f;
+    for (uint32_t t = tid; t < n; t += nt) hist[t] = 0u;
+    __syncthreads();
+    for (uint32_t t = tid; t < n; t += nt) atomicAdd(&hist[sort_bucket(td[t], scale, n)], 1u);
+    __syncthreads();
+    // bucket starts: each thread owns a run of buckets
+    const uint32_t per = (n + nt - 1) / nt, b0 = tid * per;
+    uint32_t sum = 0;
+    for (uint32_t k = 0; k < per; ++k)
+        if (b0 + k < n) sum += hist[b0 + k];
+    uint32_t run = block_scan_excl(sum, wsum);
+    for (uint32_t k = 0; k < per; ++k)
+        if (b0 + k < n) {
+            const uint32_t c = hist[b0 + k];
+            hist[b0 + k] = run;
+            run += c;
+        }
+    __syncthreads();
+    // scatter by bucket: each bucket's cursor ends at the next one's start
+    for (uint32_t t = tid; t < n; t += nt) {
+        const uint32_t pos = atomicAdd(&hist[sort_bucket(td[t], scale, n)], 1u);
+        sd[pos] = td[t];
+        si[pos] = ti[t];
+    }
+    __syncthreads();
+    for (uint32_t t = tid; t < n; t += nt) {
+        const uint64_t d = sd[t];
+        const uint32_t id = si[t];
+        const uint32_t b = sort_bucket(d, scale, n);
+        const uint32_t lo = b ? hist[b - 1] : 0u, hi = hist[b];
+        uint32_t rank = lo;
+        for (uint32_t j = lo; j < hi; ++j) rank += key_less(sd[j], si[j], d, id) ? 1u : 0u;
+        dst_ids[rank] = id;
+        if (dst_d2) dst_d2[rank] = (int64_t)d;
+    }
+}
+
+template <int METHOD>
+__global__ __launch_bounds__(512) void long_kernel(LatArgs L, TabArgs T, QArgs A) {
+    extern __shared__ __align__(16) char smem[];
+    uint64_t* td = (uint64_t*)smem;  // hits in arrival order
+    uint64_t* sd = td + kLongCap;    // by bucket
+    uint32_t* ti = (uint32_t*)(sd + kLongCap);
+    uint32_t* si = ti + kLongCap;
+    uint32_t* hist = si + kLongCap;
+    uint32_t* ctl = hist + kLongCap;  // [0] hits so far, [1] list entry taken, [4, 12) wave sums
+    const uint32_t wave = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = lane_id();
+    uint32_t* own = ctl + 16 + wave * 64;
+    if (A.row_ptr[A.Q] > A.capacity) return;  // (the write kernel sets the flag)
+    const AxisWrap aw = axis_wrap(L);
+    const uint32_t nq = uni(*A.list_count);
+    uint32_t* qc = queue_set(A, kQExtra);
+    for (;;) {
+        if (threadIdx.x == 0) {
+            ctl[1] = atomicAdd(qc, 1u);
+            ctl[0] = 0u;
+        }
+        __syncthreads();
+        const uint32_t t = uni(ctl[1]);
+        if (t >= nq) break;
+        const uint32_t qi = uni(A.list[t]);
+        const Query s = load_query(L, A, qi);
+        const int64_t rb = A.row_ptr[s.row];
+        const uint32_t rowlen = (uint32_t)(A.row_ptr[s.row + 1] - rb);
+        // the same for every wave of the block
+        const bool mine = (s.flags & F_VALID) && !(s.flags & F_KNN) && rowlen > 0 && rowlen <= kLongCap;
+        if (mine) {
+            uint32_t cand = 0, walked = 0;
+            auto visit = [&](bool act, uint32_t p, const uint4& P) -> bool {
+                const uint64_t d2 = obj_dist2(aw, s, P);
+                const bool hit = act && d2 <= s.r2 && p != s.self;
+                const uint64_t hm = __ballot(hit);
+                if (hm) {
+                    uint32_t base = 0;
+                    if (lane == 0) base = atomicAdd(&ctl[0], (uint32_t)__popcll(hm));
+                    base = uni(base);
+                    const uint32_t slot = base + lanes_below(hm);
+                    if (hit && slot < kLongCap) {
+                        td[slot] = d2;
+                        ti[slot] = P.w;
+                    }
+                }
+                return false;
+            };
+            walk<METHOD, false, false>(L, T, nullptr, s, false, walked, [&]() { return s.r2; },
+                                       [&](const RowRef& r) -> bool {
+                return for_candidates(L, r.st0, r.cnt0, r.st1, r.cnt1, own, cand, visit);
+            }, 64u * wave, 64u * nw);
+        }
+        __syncthreads();
+        if (mine)
+            block_sort_store(td, ti, sd, si, hist, ctl + 4, min(ctl[0], rowlen), s.r2, A.out_ids + rb,
+                             A.out_d2 ? A.out_d2 + rb : nullptr);
+        __syncthreads();
+    }
 }
 
 // Zero counter words [begin, end); the count pass also writes the stash
@@ -2165,6 +2300,8 @@ int device_cu_count() {
     cached = cus;
     return cus;
 }
+
+size_t long_lds_bytes(uint32_t waves) { return (size_t)kLongCap * 28 + 64 + (size_t)waves * 256; }
 
 // LDS bytes per block: pass 0 count (3 with the stash), 1 write, 2 top-M,
 // 4 grouped count (5 with the stash).
@@ -2307,9 +2444,24 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
                            query_lds_bytes(1, q.sort_cap, w, 0), st, L, T);
             if (e != hipSuccess) return e;
         }
-        // K-NN rows of a mixed batch and long radius rows, from the list
+        // K-NN rows of a mixed batch and long radius rows, from the list:
+        // radius rows up to kLongCap pairs one block per row, the others
+        // one wavefront per row (windowed top-M)
         ql.list = q.longq;
         ql.list_count = q.long_count;
+        if (q.long_waves > 1) {
+            const void* lf = variant == 0   ? (const void*)long_kernel<kCube>
+                             : variant == 3 ? (const void*)long_kernel<kPaper>
+                                            : (const void*)long_kernel<kEither>;
+            const size_t lds = long_lds_bytes(q.long_waves);
+            const uint32_t per_cu = (uint32_t)std::max<size_t>(1, (160u * 1024u) / lds);
+            LatArgs l = L;
+            TabArgs t = T;
+            QArgs a = ql;
+            void* args[] = {&l, &t, &a};
+            e = hipLaunchKernel(lf, dim3((uint32_t)device_cu_count() * per_cu), dim3(64u * q.long_waves), args, lds, st);
+            if (e != hipSuccess) return e;
+        }
         ql.list_set = kQTopm;
         return launch_ptr(SPHIDX_PICKP(topm_kernel, variant, kEither, , true), 0, ql, w, b, sh2, st, L, T);
     }

@@ -158,6 +158,7 @@ struct QArgs {
     uint32_t knn_rev;   // volume choice: K-NN queries below this take the cube
     uint32_t model;     // volume choice: 0 = cells, 1 = estimated lane work
     uint32_t* method_out;  // optional per query row: the walk used
+    uint32_t long_waves;   // write pass: waves per long radius row (one block each); <= 1: one wave, windowed
 };
 
 // Stash header words (in the counter block): written by the count pass,
@@ -208,6 +209,8 @@ size_t move_incremental_scratch_bytes(const sphidx_lattice* lat);
 hipError_t launch_move_incremental(sphidx_lattice* lat, uint64_t seed, uint32_t step, uint32_t* step_dev,
                                    void* scratch, hipStream_t st);
 hipError_t launch_scan_u32(uint32_t* data, size_t n, uint32_t* tmp, hipStream_t st);
+hipError_t launch_scan_u32_to(const uint32_t* in, uint32_t* out, size_t n, uint32_t* tmp, hipStream_t st);
 hipError_t launch_count_checksum(const int64_t* row_ptr, uint32_t Q, uint64_t* out, hipStream_t st);
 int device_cu_count();
 size_t query_lds_bytes(int pass, uint32_t cap, uint32_t waves, size_t table_bytes);
+size_t long_lds_bytes(uint32_t waves);

@@ -114,12 +114,11 @@ __global__ __launch_bounds__(256) void checksum_kernel(const int64_t* __restrict
 //   move     record p moved; stay flag = (new cell == old cell); a mover
 //            takes its rank among its new cell's arrivals (one atomic)
 //   scan     exclusive scan of the stay flags: S
-//   count    new count of cell c = stayers S[ocs[c+1]] - S[ocs[c]] + arrivals
-//   scan     the new counts -> new cell starts
-//   place    a stayer keeps its rank among its cell's stayers,
-//            S[p] - S[ocs[c]]; a mover goes after its new cell's stayers,
-//            at its arrival rank
-// (ocs: the cell starts before the step.)
+//   count    per cell c: its stayers' base SB[c] = S[cs[c]] (old starts),
+//            new count = S[cs[c+1]] - S[cs[c]] + arrivals
+//   scan     the new counts -> the lattice's new cell starts
+//   place    a stayer keeps its rank among its cell's stayers, S[p] - SB[c];
+//            a mover goes after its new cell's stayers, at its arrival rank
 
 struct IncArgs {
     uint32_t lg[3];
@@ -130,8 +129,9 @@ struct IncArgs {
     const uint4* old_pts;  // the lattice's records before the step (sorted)
     uint4* moved;          // the same records moved, in the old order
     uint4* new_pts;        // the lattice's records after the step
-    const uint32_t* ocs;   // cell starts before the step (ncells + 3)
-    uint32_t* cnt;         // arrivals per cell, then new counts, then new starts
+    uint32_t* cs;          // the lattice's cell starts: old ones, then new ones (ncells + 3)
+    uint32_t* sb;          // per cell: stayers before its first object (ncells + 3)
+    uint32_t* cnt;         // arrivals per cell, then new counts
     uint32_t* stay;        // n + 1: stay flags, then their exclusive scan
     uint32_t* arank;       // per mover: rank among its new cell's arrivals
 };
@@ -171,7 +171,10 @@ __global__ __launch_bounds__(256) void inc_move_kernel(MoveArgs m, IncArgs a) {
 __global__ __launch_bounds__(256) void inc_count_kernel(IncArgs a) {
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.ncells + 2u) return;
-    a.cnt[c] += a.stay[a.ocs[c + 1]] - a.stay[a.ocs[c]];
+    const uint32_t b = a.stay[a.cs[c]], e = a.stay[a.cs[c + 1]];
+    a.sb[c] = b;
+    if (c == a.ncells + 1u) a.sb[c + 1] = e;
+    a.cnt[c] += e - b;
 }
 
 __global__ __launch_bounds__(256) void inc_place_kernel(IncArgs a) {
@@ -182,15 +185,10 @@ __global__ __launch_bounds__(256) void inc_place_kernel(IncArgs a) {
     const uint32_t s0 = a.stay[p];
     uint32_t pos;
     if (a.stay[p + 1] != s0)
-        pos = a.cnt[c] + (s0 - a.stay[a.ocs[c]]);  // stayer: rank among its cell's stayers
+        pos = a.cs[c] + (s0 - a.sb[c]);  // stayer: rank among its cell's stayers
     else
-        pos = a.cnt[c] + (a.stay[a.ocs[c + 1]] - a.stay[a.ocs[c]]) + a.arank[p];
+        pos = a.cs[c] + (a.sb[c + 1] - a.sb[c]) + a.arank[p];
     a.new_pts[pos] = N;
-}
-
-__global__ __launch_bounds__(256) void copy_u32_kernel(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst,
-                                                       uint32_t n) {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
 }
 
 }  // namespace
@@ -264,8 +262,8 @@ hipError_t launch_count_checksum(const int64_t* row_ptr, uint32_t Q, uint64_t* o
 
 // Incremental update of a lattice of moving objects: scratch holds the moved
 // records (16 B per object), the movers' arrival ranks (4 B per object), the
-// old cell starts and the per-cell counts (4 B per cell each); the lattice's
-// rank array holds the stay flags and their scan.
+// per-cell stayer bases and counts (4 B per cell each); the lattice's rank
+// array holds the stay flags and their scan.
 size_t move_incremental_scratch_bytes(const sphidx_lattice* lat) {
     const size_t n = lat->max_points, nc = (size_t)lat->ncells + 4;
     return 16 * n + 4 * n + 4 * nc + 4 * nc + 1024;
@@ -287,15 +285,12 @@ hipError_t launch_move_incremental(sphidx_lattice* lat, uint64_t seed, uint32_t 
     a.new_pts = lat->pts;
     a.moved = (uint4*)b;
     a.arank = (uint32_t*)(b + al(16 * (size_t)n));
-    uint32_t* ocs = (uint32_t*)(b + al(16 * (size_t)n) + al(4 * (size_t)n));
-    a.ocs = ocs;
-    a.cnt = (uint32_t*)((char*)ocs + al(4 * nc));
+    a.sb = (uint32_t*)(b + al(16 * (size_t)n) + al(4 * (size_t)n));
+    a.cnt = (uint32_t*)((char*)a.sb + al(4 * nc));
+    a.cs = lat->cell_start;
     a.stay = lat->rank;
     const MoveArgs m = move_args(lat->desc, seed, step, step_dev, n);
-    const uint32_t ncs = lat->ncells + 3u;  // cell starts: region cells, outside, left out, end
-    const uint32_t cb = (uint32_t)std::min<size_t>((ncs + 255) / 256, 65536);
-    copy_u32_kernel<<<cb, 256, 0, st>>>(lat->cell_start, ocs, ncs);
-    hipError_t e = launch_fill_u32(a.cnt, 0u, ncs, st);
+    hipError_t e = launch_fill_u32(a.cnt, 0u, (size_t)lat->ncells + 3, st);
     if (e != hipSuccess) return e;
     const uint32_t blocks = (n + 255) / 256;
     if (n > 0) inc_move_kernel<<<blocks, 256, 0, st>>>(m, a);
@@ -303,9 +298,11 @@ hipError_t launch_move_incremental(sphidx_lattice* lat, uint64_t seed, uint32_t 
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_scan_u32(a.stay, n, lat->scan_tmp, st)) != hipSuccess) return e;
     inc_count_kernel<<<(lat->ncells + 2u + 255u) / 256u, 256, 0, st>>>(a);
-    if ((e = launch_scan_u32(a.cnt, (size_t)lat->ncells + 2, lat->scan_tmp, st)) != hipSuccess) return e;
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // the new counts' scan is written straight into the lattice's cell starts
+    if ((e = launch_scan_u32_to(a.cnt, lat->cell_start, (size_t)lat->ncells + 2, lat->scan_tmp, st)) != hipSuccess)
+        return e;
     if (n > 0) inc_place_kernel<<<blocks, 256, 0, st>>>(a);
-    copy_u32_kernel<<<cb, 256, 0, st>>>(a.cnt, lat->cell_start, ncs);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return launch_cell_list(lat, st);
 }

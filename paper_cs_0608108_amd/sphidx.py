@@ -56,7 +56,7 @@ class LaunchDesc(ctypes.Structure):
                 ("blocks_per_cu", U32), ("sort_cap", U32), ("table_in_lds", U32), ("interior", U32),
                 ("stats_dev", P), ("event_begin", P), ("event_end", P), ("no_stash", U32),
                 ("grouped", U32), ("select_weight", U32), ("reversal_fx", U32), ("knn_reversal_fx", U32),
-                ("select_model", U32), ("method_dev", P)]
+                ("select_model", U32), ("method_dev", P), ("long_row_waves", U32)]
 
 
 # Every symbol include/sphidx.h declares, with its ctypes signature.
@@ -342,6 +342,7 @@ class LaunchConfig:
     knn_reversal_fx: int = 0
     select_model: int = 0  # 0: compare cells (the paper); 1: compare estimated lane work
     method_out: torch.Tensor | None = None  # int32[Q]: the walk each query used
+    long_row_waves: int = 0  # waves per long radius row in the write pass (0 = 4, 1 = one wave, windowed)
 
     def c(self) -> LaunchDesc:
         d = LaunchDesc()
@@ -353,6 +354,7 @@ class LaunchConfig:
         d.grouped = self.grouped
         d.select_weight, d.reversal_fx, d.knn_reversal_fx = self.select_weight, self.reversal_fx, self.knn_reversal_fx
         d.select_model = self.select_model
+        d.long_row_waves = self.long_row_waves
         d.method_dev = None if self.method_out is None else self.method_out.data_ptr()
         d.stats_dev = None if self.stats is None else self.stats.data_ptr()
         if self.events is not None:
