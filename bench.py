@@ -805,6 +805,25 @@ def leg_knn(args, out):
     tabs.clear()
     ln = sphidx.LaunchConfig(**cfg)
     log(f"knn launch config: {cfg}, sub-cell bits {sbits}")
+    # the order of the objects inside a cell: the counting sort's, or by x
+    # (rows over dense cells then narrowed to the sphere's x-slab); the
+    # faster of the two, each over a few steps
+    order_ms = {}
+    for order in (sphidx.ORDER_ANY, sphidx.ORDER_X):
+        lat.set_cell_order(order)
+        for _ in range(2):
+            step_with(ln)()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            step_with(ln)()
+        e1.record()
+        torch.cuda.synchronize()
+        order_ms["x" if order == sphidx.ORDER_X else "any"] = round(e0.elapsed_time(e1) / 5, 4)
+    order = sphidx.ORDER_X if order_ms["x"] < order_ms["any"] else sphidx.ORDER_ANY
+    lat.set_cell_order(order)
+    log(f"knn cell order: {order_ms} ms/step -> {'x' if order else 'any'}")
     for _ in range(2):
         step_with(ln)()
     torch.cuda.synchronize()
@@ -868,6 +887,7 @@ def leg_knn(args, out):
     alg = query_bytes(n, lat.ncells, n, pairs)
     res.update({"workload": w.name, "ms_per_step": round(ms, 4), "queries_per_s": round(n / (ms * 1e-3), 1),
                 "launch": dict(cfg, schedule="persistent"), "subcell_bits": sbits,
+                "cell_order": "x" if order else "any", "ms_per_step_by_cell_order": order_ms,
                 "step": "rebuild + K-NN count + scan + write (top-K rows, sorted by (dist2, id))",
                 "pairs_per_step": pairs,
                 "sampled_rows_bit_exact_vs_oracle": exact,

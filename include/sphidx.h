@@ -121,6 +121,22 @@ sphidx_status sphidx_lattice_get_view(const sphidx_lattice* lat, sphidx_lattice_
 size_t sphidx_cell_list_bytes(const sphidx_lattice* lat);
 sphidx_status sphidx_lattice_attach_cell_list(sphidx_lattice* lat, void* list_dev, size_t bytes, void* stream);
 
+/* Order of the objects inside each cell after a build.  ANY: the order the
+ * counting sort's atomics give (the default).  X: by x coordinate, then id,
+ * for every cell of at most 4,096 objects; queries then narrow a row of
+ * cells with many objects to those whose x lies within the sphere's x-slab
+ * on that row, by a search on the sorted x values, instead of testing every
+ * object of the row's cells (results are the same; the order costs one more
+ * pass of the build, quadratic in a cell's objects).  A build that finds a
+ * larger cell keeps it in the counting sort's order and queries then test
+ * whole rows.  Applies to sphidx_build_lattice; sphidx_move_resident and
+ * sphidx_move_incremental leave cells unordered.  INVALID_ARG for another
+ * value.  Host only; the order is made by the next build, and queries narrow
+ * rows only while the order set is X and the last build ordered every cell. */
+#define SPHIDX_ORDER_ANY 0u
+#define SPHIDX_ORDER_X 1u
+sphidx_status sphidx_lattice_set_cell_order(sphidx_lattice* lat, uint32_t order);
+
 /* Synchronise `stream`, return the device status word in *flags_out (may be
  * NULL) and clear it.  Returns RANGE or CAPACITY when those bits were set. */
 sphidx_status sphidx_lattice_status(sphidx_lattice* lat, void* stream, uint32_t* flags_out);

@@ -73,6 +73,9 @@ LatArgs lat_args(const sphidx_lattice* lat) {
     L.status = lat->status;
     L.cells = lat->cell_list ? (const uint2*)(lat->cell_list + 16) : nullptr;
     L.ncl = lat->cell_list ? (const uint32_t*)lat->cell_list : nullptr;
+    // queries look at the x-order word only on lattices built to keep it, so
+    // that the others pay one uniform branch per row
+    L.xsorted = lat->cell_order == SPHIDX_ORDER_X ? lat->status + 1 : nullptr;
     return L;
 }
 
@@ -410,6 +413,7 @@ sphidx_status sphidx_lattice_create(const sphidx_lattice_desc* desc, uint32_t ma
     lat->scan_tmp = (uint32_t*)(b + ly.scan_tmp);
     lat->status = (uint32_t*)(b + ly.status);
     lat->bytes = ly.total;
+    lat->cell_order = SPHIDX_ORDER_ANY;
     (void)hipGetDevice(&lat->device);
     // an empty lattice until the first build: every cell empty, status clear
     // (skipped on a host without a device, where only validation can run)
@@ -466,6 +470,12 @@ sphidx_status sphidx_lattice_get_view(const sphidx_lattice* lat, sphidx_lattice_
     out->points = (const uint32_t*)lat->pts;
     out->n = lat->n;
     out->ncells = lat->ncells;
+    return SPHIDX_OK;
+}
+
+sphidx_status sphidx_lattice_set_cell_order(sphidx_lattice* lat, uint32_t order) {
+    if (!lat || order > SPHIDX_ORDER_X) return SPHIDX_ERR_INVALID_ARG;
+    lat->cell_order = order;
     return SPHIDX_OK;
 }
 

@@ -110,6 +110,34 @@ __global__ __launch_bounds__(256) void scatter_records_kernel(BuildArgs a) {
     a.pts[a.count[cell] + a.rank[i]] = make_uint4(vx, vy, vz, P.w);
 }
 
+// Objects inside a cell in x order (then id), for cells of at most
+// kXSortCap objects: after the scatter, every object counts the objects of
+// its cell that come before it and keeps that rank by id; a second scatter
+// from the inputs then places it.  In a larger cell an object keeps its
+// place and the lattice's x-order word is cleared.
+constexpr uint32_t kXSortCap = 4096;
+
+__global__ __launch_bounds__(256) void xrank_kernel(BuildArgs a) {
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    const uint4 P = a.pts[p];
+    uint32_t vx = P.x, vy = P.y, vz = P.z;
+    bool bad;
+    const uint32_t cell = object_cell(a, vx, vy, vz, bad);
+    const uint32_t lo = a.count[cell], hi = a.count[cell + 1];
+    uint32_t r = p - lo;
+    if (hi - lo > kXSortCap) {
+        if (p == lo) a.status[1] = 0u;
+    } else {
+        r = 0;
+        for (uint32_t q = lo; q < hi; ++q) {
+            const uint4 Q = a.pts[q];
+            r += (Q.x < P.x || (Q.x == P.x && Q.w < P.w)) ? 1u : 0u;
+        }
+    }
+    a.rank[P.w] = r;
+}
+
 // Packed region cell of a sorted record (normalised, inside the region).
 __device__ __forceinline__ uint32_t record_cell(const BuildArgs& a, const uint4& P) {
     return ((P.z >> a.F) << (a.lg[0] + a.lg[1])) | ((P.y >> a.F) << a.lg[0]) | (P.x >> a.F);
@@ -324,11 +352,18 @@ hipError_t launch_build(const sphidx_lattice* lat, const uint32_t* x, const uint
     size_t ncount = (size_t)lat->ncells + 2;
     hipError_t e = launch_fill_u32(lat->cell_start, 0u, ncount + 1, st);
     if (e != hipSuccess) return e;
+    const bool xo = lat->cell_order == SPHIDX_ORDER_X;
+    // the x-order word: set here, cleared by a cell too large to order
+    if ((e = launch_fill_u32(lat->status + 1, xo ? 1u : 0u, 1, st)) != hipSuccess) return e;
     uint32_t blocks = (n + 255) / 256;
     if (n > 0) hist_kernel<<<blocks, 256, 0, st>>>(a);
     e = scan_exclusive<uint32_t>(lat->cell_start, ncount, lat->scan_tmp, st);
     if (e != hipSuccess) return e;
     if (n > 0) scatter_kernel<<<blocks, 256, 0, st>>>(a);
+    if (n > 0 && xo) {
+        xrank_kernel<<<blocks, 256, 0, st>>>(a);
+        scatter_kernel<<<blocks, 256, 0, st>>>(a);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return launch_cell_list(lat, st);
 }
@@ -360,6 +395,8 @@ hipError_t launch_build_records(const sphidx_lattice* lat, const uint4* recs, ui
     size_t ncount = (size_t)lat->ncells + 2;
     hipError_t e = launch_fill_u32(lat->cell_start, 0u, ncount + 1, st);
     if (e != hipSuccess) return e;
+    // cells in the counting sort's order
+    if ((e = launch_fill_u32(lat->status + 1, 0u, 1, st)) != hipSuccess) return e;
     uint32_t blocks = (n + 255) / 256;
     if (n > 0) hist_records_kernel<<<blocks, 256, 0, st>>>(a);
     e = scan_exclusive<uint32_t>(lat->cell_start, ncount, lat->scan_tmp, st);

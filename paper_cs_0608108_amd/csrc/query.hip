@@ -483,6 +483,7 @@ struct RowRef {
     uint32_t st0, cnt0, st1, cnt1;
     uint32_t ist, icnt;
     uint32_t kept;
+    bool plain;  // one range (st1, cnt1): the run neither wraps nor has a wholly-inside part
 };
 
 // Per-axis distance from a position f inside the home cell to the farthest
@@ -565,7 +566,44 @@ __device__ __forceinline__ RowRef row_ranges(const LatArgs& L, uint32_t base, in
     r.ist = v1;
     r.icnt = has_int ? v2 - v1 : 0u;
     r.kept = (uint32_t)(wrap ? (p1 - p0) + (p3 - p2) : (p3 - p0));
+    r.plain = !wrap && !has_int;
     return r;
+}
+
+// Cells in x order (objects inside each cell by x, cells of a row in x
+// order): the objects of a plain run have increasing x, and those within the
+// sphere's x-slab [qx - X, qx + X] on this row are one sub-range, found by
+// two binary searches on x (interleaved, so that their loads overlap).  Only
+// for rows with many objects, where the searches cost less than testing the
+// objects outside the slab.
+constexpr uint32_t kNarrowMin = 24;
+
+__device__ __forceinline__ void narrow_x(const LatArgs& L, RowRef& r, uint32_t qx, uint32_t X) {
+    const uint32_t* xs = (const uint32_t*)L.pts;  // x of sorted position p at xs[4 p]
+    const uint32_t lo_t = qx > X ? qx - X : 0u, hi_t = qx + X;
+    uint32_t a = r.st1, na = r.cnt1, b = r.st1, nb = r.cnt1;
+    while (na | nb) {
+        if (na) {
+            const uint32_t h = na >> 1;
+            if (xs[4 * (a + h)] < lo_t) {
+                a += h + 1;
+                na -= h + 1;
+            } else {
+                na = h;
+            }
+        }
+        if (nb) {
+            const uint32_t h = nb >> 1;
+            if (xs[4 * (b + h)] <= hi_t) {
+                b += h + 1;
+                nb -= h + 1;
+            } else {
+                nb = h;
+            }
+        }
+    }
+    r.st1 = a;
+    r.cnt1 = b - a;
 }
 
 // Squared distance along one axis from the query to the nearest position of
@@ -616,7 +654,9 @@ __device__ __forceinline__ RowRef sphere_row(const LatArgs& L, const Query& s, u
         tz = 0;
     }
     const uint32_t base = (tz << (L.lg[0] + L.lg[1])) | (ty << L.lg[0]);
-    return row_ranges(L, base, (int)s.c[0] - nneg, (int)s.c[0] + npos, ia, ib, live);
+    RowRef rr = row_ranges(L, base, (int)s.c[0] - nneg, (int)s.c[0] + npos, ia, ib, live);
+    if (L.xsorted && rr.plain && rr.cnt1 >= kNarrowMin && *L.xsorted) narrow_x(L, rr, s.q[0], X);
+    return rr;
 }
 
 // Row e of the bounding cube (no test: the bin-lattice scans every cell).
@@ -670,6 +710,7 @@ __device__ __forceinline__ RowRef list_row(const LatArgs& L, const Query& s, uin
     r.ist = c.y;
     r.icnt = 0u;
     r.kept = keep ? 1u : 0u;
+    r.plain = false;
     return r;
 }
 
@@ -714,6 +755,7 @@ __device__ __forceinline__ RowRef paper_row(const LatArgs& L, const TabArgs& T, 
     r.ist = st;
     r.icnt = 0u;
     r.kept = live ? 1u : 0u;
+    r.plain = false;
     return r;
 }
 
@@ -1703,11 +1745,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
             }
             if (mine) A.row_ptr[row] = (int64_t)nrow;
             if (STASH) {
+                // pairs kept per slot: a K-NN row keeps its first K, so the
+                // stash takes those only (K-NN variant); a radius row, all
+                const uint32_t ko = KNN ? (mine ? nrow : 0u) : nq;
+                const uint32_t kincl = scan_add(ko);
+                const uint32_t qo0 = kincl - ko;
+                const uint32_t tout = KNN ? lane_val(kincl, 63) : total;
                 bool ok = total <= hitcap;
-                if (ok && total > 0 && cur + total > lim) {
+                if (ok && tout > 0 && cur + tout > lim) {
                     ok = false;
                     if (!dry) {
-                        const uint32_t grab = max(A.stash_chunk, total);
+                        const uint32_t grab = max(A.stash_chunk, tout);
                         uint32_t t = 0;
                         if (lane == 0) t = atomicAdd(A.stash_ctr + region * SPHIDX_QSTRIDE, grab);
                         t = uni(t);
@@ -1721,7 +1769,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                     }
                 }
                 const uint32_t qs0 = scan_add(nq) - nq;
-                if (ok && total > 0) {
+                if (ok && tout > 0) {
                     // every hit's dist^2 is at most its slot's r^2: shifted
                     // right by gsh, the largest r^2 of the group fits 24 bits,
                     // so a bucket needs one 32-bit conversion
@@ -1737,6 +1785,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                         qst[lane] = qs0;
                         qn[lane] = nq;
                         qsc[lane] = r2 > 0 ? (float)nq / (float)((uint32_t)(r2 >> gsh) + 1u) : 0.0f;
+                        // (the owner map is free until the next group)
+                        own[lane] = qo0;
+                        own[kGroup + lane] = ko;
                     }
                     for (uint32_t t = lane; t < total; t += 64) hh[t] = 0u;
                     wave_sync();
@@ -1785,12 +1836,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                         const uint32_t lo = hh[bi], hi = bi + 1 < total ? hh[bi + 1] : total;
                         uint32_t rank = lo;
                         for (uint32_t j = lo; j < hi; ++j) rank += hs[j] < key ? 1u : 0u;
-                        A.stash_ids[cur + rank] = (uint32_t)(key & idmask);
-                        if (A.stash_d2) A.stash_d2[cur + rank] = (int64_t)key_d2(key, idbits, d2bits);
+                        uint32_t o = cur + rank;
+                        bool keep = true;
+                        if (KNN) {
+                            // its rank inside its slot's row, kept when below K
+                            const uint32_t sl = (uint32_t)(key >> (64u - kGroupBits));
+                            const uint32_t wr = rank - qst[sl];
+                            keep = wr < own[kGroup + sl];
+                            o = cur + own[sl] + wr;
+                        }
+                        if (keep) {
+                            A.stash_ids[o] = (uint32_t)(key & idmask);
+                            if (A.stash_d2) A.stash_d2[o] = (int64_t)key_d2(key, idbits, d2bits);
+                        }
                     }
                     wave_sync();
-                    if (mine) A.soff[qi] = cur + qs0;
-                    cur += total;
+                    if (mine) A.soff[qi] = cur + (KNN ? qo0 : qs0);
+                    cur += tout;
                 } else {
                     // not kept: the write pass walks these rows again
                     const bool walk_again = mine && nq > 0;

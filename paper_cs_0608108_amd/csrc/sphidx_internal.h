@@ -20,7 +20,8 @@ struct sphidx_lattice {
     uint4* pts;         // by sorted position: normalised x, y, z and the object id
     uint32_t* rank;     // per input object: its slot inside its cell (build scratch)
     uint32_t* scan_tmp; // scan partial sums
-    uint32_t* status;   // device status word
+    uint32_t* status;   // device status word; status[1]: 1 while every cell's objects are in x order
+    uint32_t cell_order; // SPHIDX_ORDER_*: the order builds give the objects inside a cell
     size_t bytes;
     int device;
     // attached non-empty cell list (caller-owned): count word, then entries
@@ -83,6 +84,7 @@ struct LatArgs {
     uint32_t* status;
     const uint2* cells;   // non-empty cell list {cell, first} (NULL: none kept)
     const uint32_t* ncl;  // its length (device)
+    const uint32_t* xsorted;  // device word: 1 when the objects inside every cell are in x order (NULL: not kept)
 };
 
 struct TabArgs {

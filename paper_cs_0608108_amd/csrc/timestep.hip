@@ -292,6 +292,8 @@ hipError_t launch_move_incremental(sphidx_lattice* lat, uint64_t seed, uint32_t 
     const MoveArgs m = move_args(lat->desc, seed, step, step_dev, n);
     hipError_t e = launch_fill_u32(a.cnt, 0u, (size_t)lat->ncells + 3, st);
     if (e != hipSuccess) return e;
+    // arrivals follow the stayers: cells in no particular order
+    if ((e = launch_fill_u32(lat->status + 1, 0u, 1, st)) != hipSuccess) return e;
     const uint32_t blocks = (n + 255) / 256;
     if (n > 0) inc_move_kernel<<<blocks, 256, 0, st>>>(m, a);
     if (step_dev) advance_step_kernel<<<1, 1, 0, st>>>(step_dev);

@@ -23,6 +23,7 @@ MODE_RADIUS, MODE_KNN, MODE_MIXED = 0, 1, 2
 EXCLUDE_SELF = 1
 METHOD_SPHERE, METHOD_CUBE, METHOD_AUTO, METHOD_LIST, METHOD_PAPER64 = 0, 1, 2, 3, 4
 SCHED_PLAIN, SCHED_PERSISTENT = 0, 1
+ORDER_ANY, ORDER_X = 0, 1
 
 U32, I32, U64, I64, SZ, P = (ctypes.c_uint32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64,
                              ctypes.c_size_t, ctypes.c_void_p)
@@ -67,6 +68,7 @@ SIGNATURES = {
     "sphidx_build_lattice": (ctypes.c_int, [P, P, P, P, U32, P]),
     "sphidx_lattice_get_view": (ctypes.c_int, [P, ctypes.POINTER(LatticeView)]),
     "sphidx_lattice_status": (ctypes.c_int, [P, P, ctypes.POINTER(U32)]),
+    "sphidx_lattice_set_cell_order": (ctypes.c_int, [P, U32]),
     "sphidx_stream_status": (ctypes.c_int, [P, ctypes.POINTER(U32)]),
     "sphidx_cell_list_bytes": (SZ, [P]),
     "sphidx_lattice_attach_cell_list": (ctypes.c_int, [P, P, SZ, P]),
@@ -230,6 +232,10 @@ class Lattice:
         raw = self.cell_list.view(torch.int32).cpu().numpy().view(np.uint32)
         cnt = int(raw[0])
         return cnt, raw[4:4 + 2 * (cnt + 1)].reshape(cnt + 1, 2).copy()
+
+    def set_cell_order(self, order):
+        """ORDER_ANY or ORDER_X (objects inside each cell by x) for later builds."""
+        check(load().sphidx_lattice_set_cell_order(self.handle, int(order)), "set_cell_order")
 
     def status(self, stream=None):
         """(status code, flags); synchronises the stream and clears the word."""

@@ -245,8 +245,9 @@ def test_knn_clustered_full_size_every_row(sx, orc):
     """The clustered K-NN workload at full size (4,194,304 points in 64
     clusters, K = 16, search cap 8 cells) in the launches the benchmark
     times: groups of queries searched as radius rows at a first radius,
-    rows kept in the count pass.  Every row (ids and squared distances) is
-    checked against the oracle's K nearest of all points."""
+    rows kept in the count pass, with the objects inside each cell in the
+    counting sort's order and in x order.  Every row (ids and squared
+    distances) is checked against the oracle's K nearest of all points."""
     import torch
 
     from paper_cs_0608108_amd import synth
@@ -260,14 +261,16 @@ def test_knn_clustered_full_size_every_row(sx, orc):
     ref = g.knn(K, cap)
     g.close()
     assert int(ref.row_ptr[-1]) == n * K
-    for tile, bpc in ((64, 6), (256, 8)):
+    for order, tile, bpc in ((sx.ORDER_ANY, 64, 6), (sx.ORDER_ANY, 256, 8), (sx.ORDER_X, 64, 8)):
+        lat.set_cell_order(order)
+        lat.build(*lat._pts_dev)
         ln = sx.LaunchConfig(method=sx.METHOD_SPHERE, schedule=sx.SCHED_PERSISTENT, grouped=1, interior=1,
                              sort_cap=256, waves_per_block=4, tile=tile, blocks_per_cu=bpc)
-        say("C3 grouped with the stash", tile, bpc)
+        say("C3 grouped with the stash", order, tile, bpc)
         buf = sx.QueryBuffers(n, n * K, want_dist2=True, stash_pairs=3 * n * K)
         sx.query(lat, tab, q, buf, ln)
         torch.cuda.synchronize()
-        assert_same(buf.host(), ref, f"C3 every row, tile {tile}")
+        assert_same(buf.host(), ref, f"C3 every row, order {order}, tile {tile}")
         del buf
     code, flags = lat.status()
     assert code == sx.OK and flags == 0
@@ -507,3 +510,58 @@ def test_runs_are_deterministic(sx):
     b = run(sx, lat, tab, w.r_fx)
     for x, y in zip(a, b):
         np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("mask", [7, 0])
+def test_cells_in_x_order_match_oracle(sx, orc, mask):
+    """Objects ordered by x inside each cell (SPHIDX_ORDER_X): the build sorts
+    every cell of at most 4,096 objects by (x, id), rows of many objects are
+    narrowed to the sphere's x-slab by search, and every query result stays
+    equal to the oracle's; a cell of more objects stays in the counting
+    sort's order and its rows are tested whole."""
+    import torch
+    from paper_cs_0608108_amd import synth
+    rng = np.random.default_rng(700 + mask)
+    log2, F = (5, 5, 5), 12
+    spec = synth.LatticeSpec(log2, F, mask)
+    E = 1 << F
+    dense = synth.gaussian_cluster_points(spec, 60000, 91, 8, 1.5 * E)
+    W = 32 << F
+    flat = [rng.integers(0, W, 8000).astype(np.uint32) for _ in range(3)]
+    big = [np.full(5000, (3 << F) + 17 if a else (9 << F) + 5, np.uint32) for a in range(3)]
+    big[0] = (9 << F) + rng.integers(0, E, 5000).astype(np.uint32)  # one cell of 5,000 objects
+    pts = tuple(np.concatenate([dense[a], flat[a], big[a]]).astype(np.uint32) for a in range(3))
+    n = len(pts[0])
+    lat = sx.Lattice(log2, F, mask, n)
+    lat.set_cell_order(sx.ORDER_X)
+    dev = [sx.to_dev_u32(a) for a in pts]
+    lat.build(*dev)
+    h = lat.host_arrays()
+    cs = h["cell_start"]
+    sizes = np.diff(cs[: (1 << 15) + 1])
+    assert sizes.max() == 5000 and (sizes > 24).sum() > 100
+    for c in np.nonzero((sizes > 1) & (sizes <= 4096))[0]:
+        xs, ids = h["xs"][cs[c]:cs[c + 1]].astype(np.int64), h["ids"][cs[c]:cs[c + 1]].astype(np.int64)
+        key = (xs << 32) | ids
+        assert np.all(np.diff(key) > 0), c
+    tab = sx.Tables(lat, 2, 3 * E)
+    g = orc.Grid(orc.Lattice(log2, F, mask), pts)
+    r = rng.integers(0, 3 * E, n).astype(np.uint32)
+    ref = g.radius(r)
+    K = 12
+    refk = g.knn(np.full(n, K, np.uint32), np.full(n, 3 * E, np.uint32))
+    for launch, stash in ((sx.LaunchConfig(), True), (sx.LaunchConfig(grouped=1), True),
+                          (sx.LaunchConfig(grouped=1, interior=2), False), (sx.LaunchConfig(), False)):
+        say(f"x order mask={mask} grouped={launch.grouped} stash={stash}")
+        assert_same(run(sx, lat, tab, r, launch=launch, stash=stash), ref, "radius, cells in x order")
+        assert_same(run(sx, lat, tab, 3 * E, k=K, mode=sx.MODE_KNN, launch=launch, stash=stash), refk,
+                    "K-NN, cells in x order")
+    g.close()
+    # a records update leaves cells unordered: results still exact
+    scratch = torch.empty(4 * n, dtype=torch.int32, device="cuda")
+    sx.move_resident(lat, 5, scratch, step=0)
+    cur = orc.move(orc.Lattice(log2, F, mask), 5, 0, pts)
+    ref2 = orc.Grid(orc.Lattice(log2, F, mask), cur).radius(r)
+    assert_same(run(sx, lat, tab, r, launch=sx.LaunchConfig(grouped=1), stash=True), ref2, "after a records update")
+    code, flags = lat.status()
+    assert code == sx.OK, (code, flags)
