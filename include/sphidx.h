@@ -306,8 +306,12 @@ typedef struct {
                                  the rest read from device memory */
     uint32_t interior;        /* count pass, sphere method: 0 = auto (on when objects per cell >= 1),
                                  1 = off, 2 = on: cells wholly inside the sphere are counted whole */
-    uint32_t* stats_dev; /* optional uint32[4*Q]: per query walked entries, kept cells,
-                            candidate objects tested, cube cells (count pass) */
+    uint32_t* stats_dev; /* optional uint32[4*Q], zeroed by the caller: per query, the count
+                            pass adds the table entries (rows) walked, the cells kept and the
+                            candidate objects tested, over every walk the query took (a grouped
+                            K-NN row searched again, a K-NN search restarted at a larger bound),
+                            and stores the bounding cube's cells.  Costs atomics: for
+                            measurement, not for timed runs */
     void* event_begin;   /* optional hipEvent_t, recorded on the stream just before the pass's main
                             kernel (count pass: the count kernel; write pass: the stash copy and
                             the write kernel, or the top-K kernel when every row is K-NN) */

@@ -279,15 +279,15 @@ void plan_stash(QArgs& A, const sphidx_csr* csr, const Launch& ln, bool interior
     const bool d2 = csr->dist2_dev != nullptr;
     uint64_t elems = d2 ? room / 12 : room / 4;
     elems = std::min<uint64_t>(elems, 0xFFFFFF00ull);
-    const uint64_t region = elems / SPHIDX_NQUEUE;
+    const uint64_t region = elems / SPHIDX_NREGION;
     if (region < 4096) return;
     A.stash = 1;
     A.stash_region = (uint32_t)region;
     A.stash_ids = (uint32_t*)A.stash_base;
-    A.stash_d2 = d2 ? (int64_t*)(A.stash_base + align_up(region * SPHIDX_NQUEUE * 4)) : nullptr;
+    A.stash_d2 = d2 ? (int64_t*)(A.stash_base + align_up(region * SPHIDX_NREGION * 4)) : nullptr;
     // about 8 grabs per resident wave and region: little tail left unused
     const uint64_t waves = (uint64_t)device_cu_count() * ln.bpc * ln.waves;
-    const uint64_t per = std::max<uint64_t>(1, waves / SPHIDX_NQUEUE);
+    const uint64_t per = std::max<uint64_t>(1, waves / SPHIDX_NREGION);
     A.stash_chunk = (uint32_t)std::min<uint64_t>(8192, std::max<uint64_t>(ln.cap, region / (per * 8)));
 }
 
@@ -374,7 +374,7 @@ sphidx_status run_pass(int pass, const sphidx_lattice* lat, const sphidx_tables*
     // persistent schedule; not with per-query statistics or the interior
     // shortcut, which the grouped kernel does not implement)
     // (the paper's cell tables are walked one query per wavefront)
-    A.group = pass == 0 && ln.persistent && ln.grouped && !ln.stats && !A.interior && !T.paper;
+    A.group = pass == 0 && ln.persistent && ln.grouped && !A.interior && !T.paper;
     if (pass == 0) {
         s = dev_err(launch_query_pass(0, L, T, A, ln.waves, ln.bpc, st, ln.ev_begin, ln.ev_end));
         if (s != SPHIDX_OK) return s;
@@ -601,7 +601,7 @@ size_t sphidx_query_stash_bytes(uint64_t pairs, int want_dist2) {
     // chunk is at most an eighth of a region per resident wave, at least
     // 256 objects) and the alignment slack
     const uint64_t waves = (uint64_t)device_cu_count() * 64u;
-    const uint64_t elems = pairs + pairs / 4 + waves * 256u + 4096u * SPHIDX_NQUEUE;
+    const uint64_t elems = pairs + pairs / 4 + waves * 256u + 4096u * SPHIDX_NREGION;
     return (size_t)(elems * (want_dist2 ? 12u : 4u) + 1024u);
 }
 

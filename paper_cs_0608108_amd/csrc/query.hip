@@ -197,11 +197,13 @@ __device__ __forceinline__ uint32_t pack_cell(const LatArgs& L, uint32_t x, uint
 
 // One thread per query: centre, radius, K, method and walk extent.
 // K-NN first search radius in the grouped count, as a multiple of the radius
-// of the ball that holds K objects at the home cell's density (about 1.7K
-// expected inside).  Smaller leaves more rows short of K (searched again),
-// larger overflows more hit buffers; on clustered K = 16 the step took 5.93,
-// 5.29, 5.23, 5.24, 5.34, 5.53, 6.50 and 8.45 ms at 1.1, 1.15, 1.18, 1.2,
-// 1.22, 1.25, 1.35 and 1.5.
+// of the ball that holds K objects at the density around the home cell
+// (about 1.7K expected inside).  Smaller leaves more rows short of K
+// (searched again), larger overflows more hit buffers; on clustered K = 16
+// the step took 5.93, 5.29, 5.23, 5.24, 5.34, 5.53, 6.50 and 8.45 ms at 1.1,
+// 1.15, 1.18, 1.2, 1.22, 1.25, 1.35 and 1.5 (home cell density, cells in
+// counting-sort order); with cells in x order and the three-cell density,
+// 3.98, 3.82 and 4.30 ms at 1.15, 1.2 and 1.3.
 constexpr float kFirstRadius = 1.2f;
 
 template <int METHOD>
@@ -353,11 +355,17 @@ __global__ __launch_bounds__(256) void setup_kernel(LatArgs L, TabArgs T, QArgs 
             tend = T.rindex[(size_t)cls * T.nr + j];
             if (knn) {
                 // K-NN: a first search radius expected to hold about 1.7K
-                // objects at the home cell's density (the lattice mean as a
-                // floor), and its table prefix; the grouped count searches
-                // it as a radius row and keeps the first K when it holds K
+                // objects at the density of the home cell and its two
+                // neighbours along x (one contiguous range of counts; the
+                // lattice mean as a floor), and its table prefix; the grouped
+                // count searches it as a radius row and keeps the first K
+                // when it holds K.  (The home cell alone sent 3.4 % of the
+                // clustered K = 16 rows to the one-query-per-wave kernel,
+                // the three cells 2.0 %: 4.04 -> 3.82 ms per step.)
                 const uint32_t home = pack_cell(L, q[0] >> L.F, q[1] >> L.F, q[2] >> L.F);
-                const float dens = fmaxf((float)L.n / (float)L.ncells, (float)(L.cs[home + 1] - L.cs[home]));
+                const uint32_t hl = home > 0u ? home - 1u : 0u, hr = min(home + 2u, L.ncells);
+                const float dens =
+                    fmaxf((float)L.n / (float)L.ncells, (float)(L.cs[hr] - L.cs[hl]) / (float)(hr - hl));
                 const float rho = kFirstRadius * (float)e * cbrtf(0.2387f * (float)k / fmaxf(dens, 1e-6f));
                 kb = rho >= (float)r ? r : max(1u, (uint32_t)rho);
                 const uint32_t jb = (uint32_t)(((uint64_t)kb + (1u << T.rshift) - 1u) >> T.rshift);
@@ -495,19 +503,41 @@ __device__ __forceinline__ uint32_t axis_far(int o, uint32_t f, uint32_t F) {
     return max(f, e - 1u - f);
 }
 
-// floor(sqrt(v)) for v < 2^62.  The hardware reciprocal square root
-// (relative error about 2^-23) and one Newton step give sqrt(v) to about
-// 2^-45 relative, well within one unit below 2^31; exact integer steps then
-// settle the floor.  (v = 0 makes the estimate NaN: it is not used.)
+// s^2 for s < 2^24: two 24-bit multiplies (low and high word) instead of a
+// 64-bit multiply-add.
+__device__ __forceinline__ uint64_t sq24(uint32_t s) {
+    const uint32_t t = s & 0xFFFFFFu;
+    return (uint64_t)t * t;
+}
+
+// floor(sqrt(v)) for v < 2^62.
+// Below 2^41 (roots below 2^20.5): v in single precision (the high word is
+// exact, the low word and the sum round once each: relative error at most
+// 1.5 x 2^-24) and the hardware square root (within 1 ulp) give the root to
+// within 0.25, so its truncation is the floor or one either side of it; two
+// exact steps with 24-bit products settle it.
+// Above: the hardware reciprocal square root in double precision (relative
+// error about 2^-23) and one Newton step give the root to about 2^-45
+// relative, well within one unit below 2^31; exact integer steps settle the
+// floor.  (v = 0 takes the first branch.)
 __device__ __forceinline__ uint32_t isqrt64(uint64_t v) {
-    const double d = (double)v;
-    const double y = __builtin_amdgcn_rsq(d);
-    double x = d * y;
-    x = __builtin_fma(x, __builtin_fma(-x, 0.5 * y, 0.5), x);
-    uint32_t s = v ? (uint32_t)x : 0u;
-    if ((uint64_t)s * s > v) --s;
-    if ((uint64_t)s * s > v) --s;
-    if ((uint64_t)(s + 1u) * (s + 1u) <= v) ++s;
+    const uint32_t hi = (uint32_t)(v >> 32);
+    uint32_t s;
+    if (hi < (1u << 9)) {
+        const float fv = __builtin_fmaf((float)hi, 4294967296.0f, (float)(uint32_t)v);
+        s = (uint32_t)__builtin_amdgcn_sqrtf(fv);
+        if (sq24(s) > v) --s;
+        if (sq24(s + 1u) <= v) ++s;
+    } else {
+        const double d = (double)v;
+        const double y = __builtin_amdgcn_rsq(d);
+        double x = d * y;
+        x = __builtin_fma(x, __builtin_fma(-x, 0.5 * y, 0.5), x);
+        s = (uint32_t)x;
+        if ((uint64_t)s * s > v) --s;
+        if ((uint64_t)s * s > v) --s;
+        if ((uint64_t)(s + 1u) * (s + 1u) <= v) ++s;
+    }
     return s;
 }
 
@@ -608,11 +638,14 @@ __device__ __forceinline__ void narrow_x(const LatArgs& L, RowRef& r, uint32_t q
 
 // Squared distance along one axis from the query to the nearest position of
 // the cell at offset o: 0 for o = 0, else (|o| - 1) cells plus the distance
-// to the shared face (up = e - f above, dn = f + 1 below).
+// to the shared face (up = e - f above, dn = f + 1 below).  A lower bound
+// only (the callers keep a cell or a row when it is within the bound, and
+// test its objects exactly): a distance of 2^24 units or more is taken as
+// 2^24 - 1, so that the square takes 24-bit products.
 __device__ __forceinline__ uint64_t axis_gap2(int o, uint32_t up, uint32_t dn, uint32_t F) {
     const uint32_t ao = (uint32_t)(o < 0 ? -o : o);
     const uint32_t g = o == 0 ? 0u : ((ao - 1u) << F) + (o > 0 ? up : dn);
-    return sq(g);
+    return sq24(min(g, 0xFFFFFFu));
 }
 
 // Row (oy, oz) of the sphere table: the cells it meets are those whose
@@ -933,24 +966,24 @@ __device__ __forceinline__ void for_each_range(uint32_t Q, const QArgs& A, uint3
         A.persistent ? max(tmin, min(tmax, (uint32_t)((uint64_t)Q / ((uint64_t)gridDim.x * nw * 2u)))) : A.tile;
     // plain: consecutive block ids go round-robin over the 8 XCDs; give each
     // XCD a contiguous range of slices so neighbouring queries share its L2.
-    // persistent: one queue per XCD over a contiguous range of queries; drain
-    // the own queue, then take from the others; a queue found empty stays
-    // empty, so every wave stops after one empty round.
-    uint32_t x = blockIdx.x % SPHIDX_NQUEUE;
-    uint32_t misses = 0;
+    // persistent: SPHIDX_NQUEUE queues, each over a contiguous range of
+    // queries and served by blocks of one XCD (several queues per XCD, so
+    // that fewer waves share each counter); a wave drains its own queue, then
+    // looks at all the others at once and moves to the first with work left,
+    // and stops when none has any.  Queues only drain, so every wave stops.
+    uint32_t x = blockIdx.x % (A.persistent ? SPHIDX_NQUEUE : SPHIDX_NXCD);
     bool first = true;
     for (;;) {
         uint32_t b = 0, e = 0;
         if (!A.persistent) {
             if (!first) break;
             const uint32_t G = gridDim.x, bi = blockIdx.x;
-            const uint32_t full = G / SPHIDX_NQUEUE, rem = G % SPHIDX_NQUEUE;
-            const uint32_t lb = x * full + min(x, rem) + bi / SPHIDX_NQUEUE;
+            const uint32_t full = G / SPHIDX_NXCD, rem = G % SPHIDX_NXCD;
+            const uint32_t lb = x * full + min(x, rem) + bi / SPHIDX_NXCD;
             const uint64_t q0 = ((uint64_t)lb * nw + wave) * tile;
             b = (uint32_t)min(q0, (uint64_t)Q);
             e = (uint32_t)min(q0 + tile, (uint64_t)Q);
         } else {
-            if (misses >= SPHIDX_NQUEUE) break;
             const uint32_t qs = (uint32_t)(((uint64_t)x * Q) / SPHIDX_NQUEUE);
             const uint32_t qe = (uint32_t)(((uint64_t)(x + 1) * Q) / SPHIDX_NQUEUE);
             uint32_t* qc = queues + x * SPHIDX_QSTRIDE;
@@ -962,11 +995,21 @@ __device__ __forceinline__ void for_each_range(uint32_t Q, const QArgs& A, uint3
             }
             t = uni(t);
             if ((uint64_t)qs + t >= qe) {
-                x = (x + 1) % SPHIDX_NQUEUE;
-                ++misses;
+                // lane l reads queue x + 1 + l
+                bool left = false;
+                if (lane + 1u < SPHIDX_NQUEUE) {
+                    const uint32_t y = (x + 1u + lane) % SPHIDX_NQUEUE;
+                    const uint32_t ys = (uint32_t)(((uint64_t)y * Q) / SPHIDX_NQUEUE);
+                    const uint32_t ye = (uint32_t)(((uint64_t)(y + 1) * Q) / SPHIDX_NQUEUE);
+                    const uint32_t ty =
+                        __hip_atomic_load(queues + y * SPHIDX_QSTRIDE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    left = (uint64_t)ys + ty < ye;
+                }
+                const uint64_t m = __ballot(left);
+                if (m == 0) break;
+                x = (x + 1u + (uint32_t)__builtin_ctzll(m)) % SPHIDX_NQUEUE;
                 continue;
             }
-            misses = 0;
             b = qs + t;
             e = (uint32_t)min((uint64_t)qe, (uint64_t)qs + t + tile);
         }
@@ -1120,12 +1163,12 @@ template <int METHOD, bool TLDS>
 __device__ __forceinline__ uint32_t topm_registers(const LatArgs& L, const TabArgs& T, const uint32_t* tab_lds,
                                                    const Query& s, const AxisWrap& aw, uint32_t* own, uint32_t M,
                                                    uint64_t B, bool has_lower, uint64_t ld, uint32_t li, uint64_t& rd,
-                                                   uint32_t& ri) {
+                                                   uint32_t& ri, uint32_t* stat = nullptr) {
     const uint32_t lane = lane_id();
     rd = kMaxD2;
     ri = kMaxId;
     uint64_t kd = kMaxD2;
-    uint32_t kid = kMaxId, held = 0, cand2 = 0, walked2 = 0;
+    uint32_t kid = kMaxId, held = 0, cand2 = 0, walked2 = 0, kept2 = 0;
     auto visit_r = [&](bool act, uint32_t p, const uint4& P) -> bool {
         const uint64_t d2 = obj_dist2(aw, s, P);
         const uint32_t id = P.w;
@@ -1181,6 +1224,7 @@ __device__ __forceinline__ uint32_t topm_registers(const LatArgs& L, const TabAr
     for (;;) {
         walk<METHOD, TLDS, true>(L, T, tab_lds, s, false, walked2, [&]() { return held >= M ? kd : B; },
                                  [&](const RowRef& r) -> bool {
+            kept2 += r.kept;
             return for_candidates(L, r.st0, r.cnt0, r.st1, r.cnt1, own, cand2, visit_r);
         });
         if (held >= M || B >= s.r2) break;
@@ -1190,6 +1234,15 @@ __device__ __forceinline__ uint32_t topm_registers(const LatArgs& L, const TabAr
         ri = kMaxId;
         kd = kMaxD2;
         kid = kMaxId;
+    }
+    if (stat) {
+        // per-query statistics, every walk of the search included
+        const uint32_t k2 = wave_sum(kept2);
+        if (lane == 0) {
+            stat[0] += walked2;
+            stat[1] += k2;
+            stat[2] += cand2;
+        }
     }
     return min(held, M);
 }
@@ -1269,7 +1322,7 @@ __global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs 
     const uint32_t nq = FROM_LIST ? uni(*A.list_count) : A.Q;
     // this wave's stash chunk [cur, lim) in its region; `dry` once the
     // region is used up
-    const uint32_t region = blockIdx.x % SPHIDX_NQUEUE;
+    const uint32_t region = blockIdx.x % SPHIDX_NREGION;
     uint32_t cur = 0, lim = 0;
     bool dry = false;
     const uint32_t idbits = L.n > 1 ? 32u - (uint32_t)__builtin_clz(L.n - 1u) : 0u;  // ids are below n
@@ -1300,8 +1353,14 @@ __global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs 
             // the row itself: lane i ends with the i-th nearest
             uint64_t rd;
             uint32_t ri;
+            uint32_t* stp = A.stats ? A.stats + 4 * (size_t)s.row : nullptr;
             const uint32_t got = topm_registers<METHOD, TLDS>(L, T, tab_lds, s, aw, own, s.k,
-                                                               first_bound(L, s, s.k, 0u), false, 0ull, 0u, rd, ri);
+                                                               first_bound(L, s, s.k, 0u), false, 0ull, 0u, rd, ri,
+                                                               stp);
+            if (stp) {
+                const uint32_t nc = cube_cells(L, s);
+                if (lane == 0) stp[3] = nc;
+            }
             if (lane == 0) A.row_ptr[s.row] = (int64_t)got;
             uint32_t off = 0u;  // empty rows: nothing to copy
             if (got > 0) {
@@ -1375,10 +1434,11 @@ __global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs 
             const uint32_t kept_all = wave_sum(kept);
             const uint32_t ncube = (s.flags & F_VALID) ? cube_cells(L, s) : 0u;
             if (lane == 0) {
+                // (added to: a grouped count may have walked the query first)
                 uint32_t* stp = A.stats + 4 * (size_t)s.row;
-                stp[0] = walked;
-                stp[1] = kept_all;
-                stp[2] = cand;
+                stp[0] += walked;
+                stp[1] += kept_all;
+                stp[2] += cand;
                 stp[3] = ncube;
             }
         }
@@ -1452,7 +1512,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
     const uint32_t hitcap = group_hitcap(A.sort_cap), grows = group_rows(A.sort_cap);  // hitcap <= kMaxHitCap
     uint32_t rlim = grows;  // rows per group (shrinks where hits overflow the buffer)
     char* wb = smem + table_lds_bytes<TLDS>(T) + (size_t)wave * group_lds_per_wave(STASH, A.sort_cap);
-    uint4* qp = (uint4*)wb;                    // per slot: centre + table start, r^2 + self + rows,
+    uint4* qp = (uint4*)wb;                    // five records of kGroup slots each (slot s of record k
+                                               // at qp[k * kGroup + s]): centre + table start, r^2 + self + rows,
                                                // cube extent, flags + row, W/2 - centre + self
     uint32_t* cnt = (uint32_t*)(wb + 640);     // [0, 8) hits, [8, 16) row start, [16, 24) hits,
     uint32_t* qst = cnt + 8;                   // [24, 32) bucket scale (float)
@@ -1469,7 +1530,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
     const uint32_t idbits = L.n > 1 ? 32u - (uint32_t)__builtin_clz(L.n - 1u) : 0u;
     const uint32_t d2bits = 64u - kGroupBits - idbits;
     const uint64_t idmask = idbits ? (~0ull >> (64u - idbits)) : 0ull;
-    const uint32_t region = blockIdx.x % SPHIDX_NQUEUE;
+    const uint32_t region = blockIdx.x % SPHIDX_NREGION;
     uint32_t cur = 0, lim = 0;
     bool dry = false;
     const uint32_t nq = FROM_LIST ? uni(*A.list_count) : A.Q;
@@ -1531,16 +1592,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
             if (mine) {
                 const uint64_t r2 = (KNN && knn) ? (uint64_t)d2.y * d2.y : (uint64_t)d1.x * d1.x;
                 const uint32_t self = (A.qx == nullptr && (A.flags & SPHIDX_EXCLUDE_SELF)) ? qi : kMaxId;
-                uint4* p = qp + 5 * lane;
+                uint4* p = qp + lane;
                 p[0] = make_uint4(d0.x, d0.y, d0.z, d1.w);
-                p[1] = make_uint4((uint32_t)r2, (uint32_t)(r2 >> 32), self, rows);
+                p[kGroup] = make_uint4((uint32_t)r2, (uint32_t)(r2 >> 32), self, rows);
                 // (a K-NN slot walks no cube: K and whether its search radius
                 // covers the cap take the cube fields)
-                p[2] = make_uint4(d3.x, d3.y, d3.z, (KNN && knn) ? d1.y : d2.z);
-                p[3] = make_uint4(d2.w, (KNN && knn) ? (d2.y >= d1.x ? 1u : 0u) : d3.w, d1.z, row);
+                p[2 * kGroup] = make_uint4(d3.x, d3.y, d3.z, (KNN && knn) ? d1.y : d2.z);
+                p[3 * kGroup] = make_uint4(d2.w, (KNN && knn) ? (d2.y >= d1.x ? 1u : 0u) : d3.w, d1.z, row);
                 // the candidate test's form of the centre: the minimum-image
                 // offset is ((p + (W/2 - c)) mod W) - W/2
-                p[4] = make_uint4(aw.half[0] - d0.x, aw.half[1] - d0.y, aw.half[2] - d0.z, self);
+                p[4 * kGroup] = make_uint4(aw.half[0] - d0.x, aw.half[1] - d0.y, aw.half[2] - d0.z, self);
             }
             if (lane < kGroup) cnt[lane] = 0u;
             wave_sync();
@@ -1573,8 +1634,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                     const uint32_t gmax = scan_max(own[lane]);
                     const uint32_t gs = act ? gmax - 1u : 0u;
                     const uint32_t ent = fr - bperm(excl, gs);
-                    const uint4* p = qp + 5 * gs;
-                    const uint4 pa = p[0], pb = p[1], pc = p[2], pd = p[3];
+                    const uint4* p = qp + gs;
+                    const uint4 pa = p[0], pb = p[kGroup], pc = p[2 * kGroup], pd = p[3 * kGroup];
                     Query sq;
                     sq.q[0] = pa.x;
                     sq.q[1] = pa.y;
@@ -1614,6 +1675,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                         r.cnt0 = L.cs[L.ncells + 1] - r.st0;
                         r.cnt1 = 0u;
                     }
+                    if (A.stats && live) {
+                        // per-query statistics, the outside cell's pseudo-row
+                        // left out (rows walked again are counted again)
+                        uint32_t* stp = A.stats + 4 * (size_t)pd.w;
+                        atomicAdd(stp, 1u);
+                        atomicAdd(stp + 1, r.kept);
+                    }
                     const uint32_t tl = act ? r.cnt0 + r.cnt1 : 0u;
                     const uint32_t ci = scan_add(tl);
                     const uint32_t ce = carry + ci - tl;
@@ -1649,8 +1717,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                     return g < CT;
                 };
                 auto test = [&](const uint4& P, uint32_t pos, uint32_t sl, bool cact, uint32_t cb) {
-                    const uint4 ch = qp[5 * sl + 4];
-                    const uint2 cr = *(const uint2*)(qp + 5 * sl + 1);
+                    const uint4 ch = qp[4 * kGroup + sl];
+                    const uint2 cr = *(const uint2*)(qp + kGroup + sl);
                     const uint32_t pv[3] = {P.x, P.y, P.z}, hv[3] = {ch.x, ch.y, ch.z};
                     uint64_t d2 = 0;
 #pragma unroll
@@ -1660,6 +1728,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                     }
                     const uint64_t r2 = (uint64_t)cr.x | ((uint64_t)cr.y << 32);
                     const bool hit = cact && d2 <= r2 && pos != ch.w;
+                    if (A.stats && cact) atomicAdd(A.stats + 4 * (size_t)qp[3 * kGroup + sl].w + 2, 1u);
                     const uint64_t H = __ballot(hit);
                     const uint32_t hp = hcount + lanes_below(H);
                     // hits per slot: a slot's candidates take contiguous lanes
@@ -1723,10 +1792,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
             // is searched again by the one-query-per-wave kernel
             uint32_t nrow = nq;
             if (KNN && knn) {
-                const uint32_t kk = qp[5 * lane + 2].w;
+                const uint32_t kk = qp[2 * kGroup + lane].w;
                 if (nq >= kk) {
                     nrow = kk;
-                } else if (qp[5 * lane + 3].y == 0u) {
+                } else if (qp[3 * kGroup + lane].y == 0u) {
                     mine = false;
                     extra = true;
                 }
@@ -1775,7 +1844,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                     // so a bucket needs one 32-bit conversion
                     uint64_t r2 = 0;
                     if (lane < kGroup) {
-                        const uint4 pb = qp[5 * lane + 1];
+                        const uint4 pb = qp[kGroup + lane];
                         r2 = nq > 0 ? (uint64_t)pb.x | ((uint64_t)pb.y << 32) : 0ull;
                     }
                     const uint32_t rbits = lane_val(scan_max(r2 ? 64u - (uint32_t)__builtin_clzll(r2) : 0u), 63);
@@ -2226,8 +2295,12 @@ __global__ __launch_bounds__(512) void long_kernel(LatArgs L, TabArgs T, QArgs A
 
 // Zero counter words [begin, end); the count pass also writes the stash
 // header (hdr != NULL: four words) after clearing.
+// Counters sit SPHIDX_QSTRIDE words apart and only those words are read:
+// the others are left as they are.  One block; the stash header, inside the
+// cleared range, is written after every clear.
 __global__ void clear_counters_kernel(uint32_t* c, uint32_t begin, uint32_t end, uint32_t* hdr, uint4 hv) {
-    for (uint32_t i = begin + threadIdx.x; i < end; i += blockDim.x) c[i] = 0u;
+    for (uint32_t i = begin + threadIdx.x * SPHIDX_QSTRIDE; i < end; i += blockDim.x * SPHIDX_QSTRIDE) c[i] = 0u;
+    __syncthreads();
     if (hdr && threadIdx.x == 0) {
         hdr[kHdrMode] = hv.x;
         hdr[kHdrElems] = hv.y;
@@ -2387,7 +2460,7 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
     hipError_t e;
     if (pass == 0) {
         // everything, then the stash header for the write pass
-        const uint4 hv = make_uint4(q.stash, q.stash ? q.stash_region * SPHIDX_NQUEUE : 0u, q.stash_d2 ? 1u : 0u,
+        const uint4 hv = make_uint4(q.stash, q.stash ? q.stash_region * SPHIDX_NREGION : 0u, q.stash_d2 ? 1u : 0u,
                                     q.stash_d2 ? (uint32_t)(((char*)q.stash_d2 - q.stash_base) / 256) : 0u);
         clear_counters_kernel<<<1, 256, 0, st>>>(q.queues, 0u, SPHIDX_COUNTER_WORDS, q.stash_hdr, hv);
     } else {
@@ -2418,9 +2491,8 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
     ql.persistent = 1;
     if (pass == 0) {
         const int lp = q.stash ? 3 : 0;
-        // K-NN rows searched and kept by the count pass (not with per-query
-        // statistics, which that path does not gather)
-        const bool ks = q.stash && q.mode != SPHIDX_MODE_RADIUS && !q.stats;
+        // K-NN rows searched and kept by the count pass
+        const bool ks = q.stash && q.mode != SPHIDX_MODE_RADIUS;
         if ((e = mark(ev_begin)) != hipSuccess) return e;
         if (q.group) {
             // radius queries in groups: all queries (those of the tables),

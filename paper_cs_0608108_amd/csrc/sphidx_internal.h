@@ -167,13 +167,16 @@ struct QArgs {
 // read by the write pass, which therefore needs no host-side state.
 enum : uint32_t { kHdrMode = 0, kHdrElems = 1, kHdrHasD2 = 2, kHdrD2Off = 3 };
 
-#define SPHIDX_NQUEUE 8         // one work queue per XCD of the MI355X
+#define SPHIDX_NXCD 8           // XCDs of the MI355X: blocks are dispatched to them in turn
+#define SPHIDX_NQUEUE 64        // work queues per set, 8 per XCD: queue q is served by the blocks of XCD q mod 8
+#define SPHIDX_NREGION SPHIDX_NXCD  // stash regions, one per XCD
 #define SPHIDX_QSTRIDE 32       // counters 128 bytes apart: one L2 line each
 #define SPHIDX_NQSETS 7         // count, write, top-M, fallback count, fallback write, walk list, extra list
 #define SPHIDX_NLISTS 5         // long_count, fb_count, walk_count, stash header, xq_count
 #define SPHIDX_COUNTER_WORDS \
-    ((SPHIDX_NQSETS * SPHIDX_NQUEUE + SPHIDX_NLISTS + SPHIDX_NQUEUE) * SPHIDX_QSTRIDE)
+    ((SPHIDX_NQSETS * SPHIDX_NQUEUE + SPHIDX_NLISTS + SPHIDX_NREGION) * SPHIDX_QSTRIDE)
 #define SPHIDX_MAX_LOG2_SUM 30
+static_assert(SPHIDX_NQUEUE <= 64 && SPHIDX_NQUEUE % SPHIDX_NXCD == 0, "a wave looks at every queue at once");
 
 constexpr uint32_t kPaperMaxOff = 32;
 
