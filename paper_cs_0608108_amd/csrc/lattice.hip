@@ -114,20 +114,51 @@ __global__ __launch_bounds__(256) void scatter_records_kernel(BuildArgs a) {
 // kXSortCap objects: after the scatter, every object counts the objects of
 // its cell that come before it and keeps that rank by id; a second scatter
 // from the inputs then places it.  In a larger cell an object keeps its
-// place and the lattice's x-order word is cleared.
+// place and the lattice's x-order word is cleared.  A block's 256 positions
+// cover a run of whole or partial cells; when the cells' objects number at
+// most kXStage they are staged in LDS as (x, id) keys and counted there,
+// else every thread reads its cell from device memory.
 constexpr uint32_t kXSortCap = 4096;
+constexpr uint32_t kXStage = 2048;
 
 __global__ __launch_bounds__(256) void xrank_kernel(BuildArgs a) {
-    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.n) return;
-    const uint4 P = a.pts[p];
-    uint32_t vx = P.x, vy = P.y, vz = P.z;
-    bool bad;
-    const uint32_t cell = object_cell(a, vx, vy, vz, bad);
-    const uint32_t lo = a.count[cell], hi = a.count[cell + 1];
+    __shared__ uint64_t keys[kXStage];
+    __shared__ uint32_t span[2];
+    const uint32_t p0 = blockIdx.x * blockDim.x, p = p0 + threadIdx.x;
+    const uint32_t last = min(a.n, p0 + blockDim.x) - 1u;
+    const bool act = p < a.n;
+    uint4 P = make_uint4(0, 0, 0, 0);
+    uint32_t lo = 0, hi = 0;
+    if (act) {
+        P = a.pts[p];
+        uint32_t vx = P.x, vy = P.y, vz = P.z;
+        bool bad;
+        const uint32_t cell = object_cell(a, vx, vy, vz, bad);
+        lo = a.count[cell];
+        hi = a.count[cell + 1];
+    }
+    // positions are in cell order: the block's cells span [lo of its first
+    // position, hi of its last)
+    if (p == p0) span[0] = lo;
+    if (p == last) span[1] = hi;
+    __syncthreads();
+    const uint32_t s0 = span[0], s1 = span[1];
+    const bool staged = s1 - s0 <= kXStage;
+    if (staged) {
+        for (uint32_t q = s0 + threadIdx.x; q < s1; q += blockDim.x) {
+            const uint4 Q = a.pts[q];
+            keys[q - s0] = ((uint64_t)Q.x << 32) | Q.w;
+        }
+    }
+    __syncthreads();
+    if (!act) return;
     uint32_t r = p - lo;
     if (hi - lo > kXSortCap) {
         if (p == lo) a.status[1] = 0u;
+    } else if (staged) {
+        const uint64_t mine = ((uint64_t)P.x << 32) | P.w;
+        r = 0;
+        for (uint32_t q = lo - s0; q < hi - s0; ++q) r += keys[q] < mine ? 1u : 0u;
     } else {
         r = 0;
         for (uint32_t q = lo; q < hi; ++q) {

@@ -1252,6 +1252,9 @@ __device__ __forceinline__ uint32_t topm_registers(const LatArgs& L, const TabAr
 
 // Queue sets of the work counters.
 constexpr int kQCount = 0, kQWrite = 1, kQTopm = 2, kQFbCount = 3, kQFbWrite = 4, kQWalk = 5, kQExtra = 6;
+// the count pass's last list (rows the second grouped round left) takes the
+// fallback write set, which only the write pass uses and clears
+constexpr int kQExtra2 = kQFbWrite;
 // Longest radius row the block-per-row kernel orders in LDS (28 bytes per pair).
 constexpr uint32_t kLongCap = 2048;
 
@@ -1456,7 +1459,10 @@ __global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs 
 // search radius and keep the first K.  Queries it does not take (K-NN of
 // large K or off the sphere tables, keys that would not fit 64 bits, rows
 // short of K inside the first radius) go to the extra list for the
-// one-query-per-wave kernel.
+// one-query-per-wave kernel.  The list-driven K-NN variant is the second
+// round over that list: a K-NN row short of K inside its first radius is
+// searched again in groups at half as large a radius again (the cap at most);
+// what that round does not take goes on to the one-query-per-wave kernel.
 
 constexpr uint32_t kGroup = 8, kGroupBits = 3;
 // hit buffer keys and rows per group, in eighths of sort_cap
@@ -1551,11 +1557,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                 d3 = A.desc[4 * (size_t)qi + 3];
                 row = d0.w;
                 const uint32_t flags = d1.z;
+                if (KNN && FROM_LIST && (flags & F_KNN) && (flags & F_SPHERE) && d2.y < d1.x) {
+                    // second round: the first radius held fewer than K, so
+                    // the radius grows by half (to the cap) and its table
+                    // prefix follows from the radius index of the row class
+                    const uint32_t e1 = 1u << L.F, sh = L.F - T.s;
+                    const uint32_t cls = ((d0.y & (e1 - 1u)) >> sh) | (((d0.z & (e1 - 1u)) >> sh) << T.s);
+                    const uint32_t kb = (uint32_t)min((uint64_t)d1.x, (uint64_t)d2.y + (d2.y >> 1) + 1u);
+                    const uint32_t jb = (uint32_t)(((uint64_t)kb + (1u << T.rshift) - 1u) >> T.rshift);
+                    d2.y = kb;
+                    d2.z = T.rindex[(size_t)cls * T.nr + jb];
+                }
                 const uint64_t r2 = (uint64_t)d1.x * d1.x;
                 const uint32_t r2bits = r2 ? 64u - (uint32_t)__builtin_clzll(r2) : 0u;
                 const bool valid = flags & F_VALID, sph = flags & F_SPHERE;
                 if (!valid) {
                     invalid = true;
+                } else if (KNN && FROM_LIST && !((flags & F_KNN) && sph)) {
+                    // the second round takes sphere-table K-NN rows only;
+                    // everything else on its list goes on
+                    extra = true;
                 } else if (METHOD == kSphere && !sph) {
                     // counted by the fallback list's kernel
                 } else if (KNN && (flags & F_KNN)) {
@@ -2528,6 +2549,24 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
             ql.list = q.xq;
             ql.list_count = q.xq_count;
             ql.list_set = kQExtra;
+            if (gk && variant != 0) {
+                // K-NN rows short of K inside their first radius: a second
+                // grouped round at a larger radius; what it leaves goes on
+                // the long-row list (free until the write pass) to the
+                // one-query-per-wave kernel
+                QArgs qr = ql;
+                qr.xq = q.longq;
+                qr.xq_count = q.long_count;
+                e = launch_ptr(q.stash ? (either ? SPHIDX_PICK(group_count_kernel, variant, kEither, , true, true, true)
+                                                 : SPHIDX_PICK(group_count_kernel, variant, kSphere, , true, true, true))
+                                       : (either ? SPHIDX_PICK(group_count_kernel, variant, kEither, , false, true, true)
+                                                 : SPHIDX_PICK(group_count_kernel, variant, kSphere, , false, true, true)),
+                               0, qr, w, b, gl, st, L, T);
+                if (e != hipSuccess) return e;
+                ql.list = q.longq;
+                ql.list_count = q.long_count;
+                ql.list_set = kQExtra2;
+            }
             if (ks)
                 return launch_ptr(SPHIDX_PICK(count_kernel, variant, kEither, , true, true, true), 0, ql, w, b,
                                   query_lds_bytes(lp, q.sort_cap, w, tb), st, L, T);
