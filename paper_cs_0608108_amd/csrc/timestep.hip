@@ -79,10 +79,20 @@ __global__ __launch_bounds__(256) void checksum_kernel(const int64_t* __restrict
                                                        unsigned long long* out) {
     __shared__ uint64_t part[2][4];
     uint64_t s = 0, h = 0;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < Q; i += gridDim.x * blockDim.x) {
-        uint64_t c = (uint64_t)(row_ptr[i + 1] - row_ptr[i]);
-        s += c;
-        h += mix64(((uint64_t)i << 32) | (c & 0xffffffffull));
+    // four consecutive rows per thread and step: five row_ptr loads in flight
+    const uint64_t stride = 4ull * gridDim.x * blockDim.x;
+    for (uint64_t i0 = 4ull * (blockIdx.x * blockDim.x + threadIdx.x); i0 < Q; i0 += stride) {
+        int64_t v[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) v[k] = i0 + k <= Q ? row_ptr[i0 + k] : 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (i0 + k < Q) {
+                const uint64_t c = (uint64_t)(v[k + 1] - v[k]);
+                s += c;
+                h += mix64(((i0 + k) << 32) | (c & 0xffffffffull));
+            }
+        }
     }
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) {

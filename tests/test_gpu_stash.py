@@ -242,15 +242,24 @@ def test_grouped_rows_beyond_one_chunk(sx, orc, mask, method):
 def test_grouped_knn_radius_rows_match_oracle(sx, orc, mask):
     """K-NN rows searched in groups as radius rows at a first search radius:
     dense clusters (rows kept from a radius that holds K), sparse regions and
-    small caps (fewer than K inside: searched again one query per wavefront,
-    or every object when the radius covers the cap), K above a quarter of
-    the hit buffer (one query per wavefront), buffers that overflow."""
+    small caps (fewer than K inside: searched again in groups at a larger
+    radius, then one query per wavefront, or every object when the radius
+    covers the cap), K above a quarter of the hit buffer (one query per
+    wavefront), buffers that overflow.  Cells holding a tight clump in one
+    corner and a lone object in the opposite corner make the home-cell
+    density far too high for the lone object's rows, so that they fail both
+    grouped rounds."""
     from paper_cs_0608108_amd import synth
     log2, F = (5, 5, 5), 12
+    E = 1 << F
     spec = synth.LatticeSpec(log2, F, mask)
-    dense = synth.gaussian_cluster_points(spec, 24000, 41 + mask, 8, 1.5 * (1 << F))
+    dense = synth.gaussian_cluster_points(spec, 24000, 41 + mask, 8, 1.5 * E)
     sparse = synth.uniform_points(spec, 6000, 43 + mask)
-    pts = tuple(np.concatenate([dense[a], sparse[a]]).astype(np.uint32) for a in range(3))
+    crng = np.random.default_rng(900 + mask)
+    cells = crng.integers(2, 30, (20, 3))
+    clump = [np.concatenate([(c[a] << F) + crng.integers(0, E // 16, 300) for c in cells]) for a in range(3)]
+    lone = [(cells[:, a] << F) + E - 1 - crng.integers(0, E // 16, 20) for a in range(3)]
+    pts = tuple(np.concatenate([dense[a], sparse[a], clump[a], lone[a]]).astype(np.uint32) for a in range(3))
     lat = _world(sx, log2, F, mask, pts)
     tab = sx.Tables(lat, 2, 4 << F)
     n = len(pts[0])
