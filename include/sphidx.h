@@ -320,10 +320,11 @@ typedef struct {
     uint32_t no_stash;   /* 1: never keep rows in the workspace stash (see sphidx_csr) */
     uint32_t grouped;    /* 1: the count pass takes radius queries in groups of several per
                             wavefront (persistent schedule), and K-NN queries of the sphere
-                            tables with 4K <= sort_cap as radius rows at a first search
-                            radius (expected to hold about 1.7K objects), keeping the first
-                            K when it holds K (rows short of K are searched again one query
-                            per wavefront; the stash then needs about 2K pairs per query);
+                            tables with 2K <= sort_cap as radius rows at a first search
+                            radius (expected to hold min(1.7K, K + 3 sqrt(K) + 3) objects),
+                            keeping the first K when it holds K (rows short of K are searched
+                            again in groups at a larger radius, then one query per
+                            wavefront; the stash needs K pairs per such row);
                             0: one query per wavefront */
     /* METHOD_AUTO (Appendix: weighting factor and reversal distances).  A radius query takes
      * the sphere when select_weight/256 * (sphere cells) <= (cube cells), else the cube; then
@@ -352,7 +353,7 @@ typedef struct {
     uint32_t* method_dev;     /* optional uint32[Q], written by the count pass: the walk each query
                                  used (SPHIDX_METHOD_SPHERE, _CUBE or _LIST), or 0xFFFFFFFF for a
                                  query with an empty row by definition (invalid centre, K = 0) */
-    uint32_t long_row_waves;  /* write pass, radius rows longer than sort_cap and at most 2048 pairs:
+    uint32_t long_row_waves;  /* write pass, radius rows longer than sort_cap and at most 3072 pairs:
                                  the wavefronts that walk and order one such row together, as one
                                  block (2, 4 or 8; 0 = 4); 1 = one wavefront per row, which takes
                                  the row in windows of sort_cap, walking it once per window */

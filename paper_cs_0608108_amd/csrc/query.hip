@@ -196,15 +196,20 @@ __device__ __forceinline__ uint32_t pack_cell(const LatArgs& L, uint32_t x, uint
 }
 
 // One thread per query: centre, radius, K, method and walk extent.
-// K-NN first search radius in the grouped count, as a multiple of the radius
-// of the ball that holds K objects at the density around the home cell
-// (about 1.7K expected inside).  Smaller leaves more rows short of K
-// (searched again), larger overflows more hit buffers; on clustered K = 16
-// the step took 5.93, 5.29, 5.23, 5.24, 5.34, 5.53, 6.50 and 8.45 ms at 1.1,
-// 1.15, 1.18, 1.2, 1.22, 1.25, 1.35 and 1.5 (home cell density, cells in
-// counting-sort order); with cells in x order and the three-cell density,
-// 3.98, 3.82 and 4.30 ms at 1.15, 1.2 and 1.3.
-constexpr float kFirstRadius = 1.2f;
+// K-NN first search radius in the grouped count: the radius of the ball
+// expected to hold knn_target(K) objects at the density around the home cell.
+// For small K that is 1.2^3 K (about 1.7K): smaller leaves more rows short of
+// K (searched again), larger overflows more hit buffers; on clustered K = 16
+// the step took 5.93, 5.29, 5.23, 5.24, 5.34, 5.53, 6.50 and 8.45 ms at radius
+// factors 1.1, 1.15, 1.18, 1.2, 1.22, 1.25, 1.35 and 1.5 (home cell density,
+// cells in counting-sort order); with cells in x order and the three-cell
+// density, 3.98, 3.82 and 4.30 ms at 1.15, 1.2 and 1.3.  For large K the count
+// inside a ball varies relatively less (about sqrt(K)), so K + 3 sqrt(K) + 3
+// is enough, and a row of K up to half the hit buffer fits it.
+__host__ __device__ inline float knn_target(float k) {
+    const float a = 1.728f * k, b = k + 3.0f * __builtin_sqrtf(k) + 3.0f;
+    return a < b ? a : b;
+}
 
 template <int METHOD>
 __global__ __launch_bounds__(256) void setup_kernel(LatArgs L, TabArgs T, QArgs A) {
@@ -354,7 +359,7 @@ __global__ __launch_bounds__(256) void setup_kernel(LatArgs L, TabArgs T, QArgs 
             tb = T.cstart[cls];
             tend = T.rindex[(size_t)cls * T.nr + j];
             if (knn) {
-                // K-NN: a first search radius expected to hold about 1.7K
+                // K-NN: a first search radius expected to hold knn_target(K)
                 // objects at the density of the home cell and its two
                 // neighbours along x (one contiguous range of counts; the
                 // lattice mean as a floor), and its table prefix; the grouped
@@ -366,7 +371,7 @@ __global__ __launch_bounds__(256) void setup_kernel(LatArgs L, TabArgs T, QArgs 
                 const uint32_t hl = home > 0u ? home - 1u : 0u, hr = min(home + 2u, L.ncells);
                 const float dens =
                     fmaxf((float)L.n / (float)L.ncells, (float)(L.cs[hr] - L.cs[hl]) / (float)(hr - hl));
-                const float rho = kFirstRadius * (float)e * cbrtf(0.2387f * (float)k / fmaxf(dens, 1e-6f));
+                const float rho = (float)e * cbrtf(0.2387f * knn_target((float)k) / fmaxf(dens, 1e-6f));
                 kb = rho >= (float)r ? r : max(1u, (uint32_t)rho);
                 const uint32_t jb = (uint32_t)(((uint64_t)kb + (1u << T.rshift) - 1u) >> T.rshift);
                 kend = T.rindex[(size_t)cls * T.nr + jb];
@@ -1256,7 +1261,7 @@ constexpr int kQCount = 0, kQWrite = 1, kQTopm = 2, kQFbCount = 3, kQFbWrite = 4
 // fallback write set, which only the write pass uses and clears
 constexpr int kQExtra2 = kQFbWrite;
 // Longest radius row the block-per-row kernel orders in LDS (28 bytes per pair).
-constexpr uint32_t kLongCap = 2048;
+constexpr uint32_t kLongCap = 3072;
 
 __device__ __forceinline__ uint32_t* queue_set(const QArgs& A, int set) {
     return A.queues + (size_t)set * SPHIDX_NQUEUE * SPHIDX_QSTRIDE;
@@ -1461,8 +1466,9 @@ __global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs 
 // short of K inside the first radius) go to the extra list for the
 // one-query-per-wave kernel.  The list-driven K-NN variant is the second
 // round over that list: a K-NN row short of K inside its first radius is
-// searched again in groups at half as large a radius again (the cap at most);
-// what that round does not take goes on to the one-query-per-wave kernel.
+// searched again in groups at the larger radius the first round wrote into
+// its descriptor from the count it saw (the cap at most); what that round
+// does not take goes on to the one-query-per-wave kernel.
 
 constexpr uint32_t kGroup = 8, kGroupBits = 3;
 // hit buffer keys and rows per group, in eighths of sort_cap
@@ -1557,17 +1563,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                 d3 = A.desc[4 * (size_t)qi + 3];
                 row = d0.w;
                 const uint32_t flags = d1.z;
-                if (KNN && FROM_LIST && (flags & F_KNN) && (flags & F_SPHERE) && d2.y < d1.x) {
-                    // second round: the first radius held fewer than K, so
-                    // the radius grows by half (to the cap) and its table
-                    // prefix follows from the radius index of the row class
-                    const uint32_t e1 = 1u << L.F, sh = L.F - T.s;
-                    const uint32_t cls = ((d0.y & (e1 - 1u)) >> sh) | (((d0.z & (e1 - 1u)) >> sh) << T.s);
-                    const uint32_t kb = (uint32_t)min((uint64_t)d1.x, (uint64_t)d2.y + (d2.y >> 1) + 1u);
-                    const uint32_t jb = (uint32_t)(((uint64_t)kb + (1u << T.rshift) - 1u) >> T.rshift);
-                    d2.y = kb;
-                    d2.z = T.rindex[(size_t)cls * T.nr + jb];
-                }
                 const uint64_t r2 = (uint64_t)d1.x * d1.x;
                 const uint32_t r2bits = r2 ? 64u - (uint32_t)__builtin_clzll(r2) : 0u;
                 const bool valid = flags & F_VALID, sph = flags & F_SPHERE;
@@ -1580,14 +1575,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                 } else if (METHOD == kSphere && !sph) {
                     // counted by the fallback list's kernel
                 } else if (KNN && (flags & F_KNN)) {
-                    // K-NN (sphere tables, K up to a quarter of the buffer):
+                    // K-NN (sphere tables, K up to half the buffer):
                     // a radius row at the first search radius d2.y, the
                     // table prefix d2.z; its first K are the K nearest when
                     // it holds K (Section II.A: beyond the radius every
                     // object is farther)
                     const uint64_t b2 = (uint64_t)d2.y * d2.y;
                     const uint32_t b2bits = b2 ? 64u - (uint32_t)__builtin_clzll(b2) : 0u;
-                    if (!sph || (flags & F_LIST) || b2bits > d2bits || 4u * d1.y > hitcap) {
+                    if (!sph || (flags & F_LIST) || b2bits > d2bits || 2u * d1.y > hitcap) {
                         extra = true;
                     } else {
                         mine = true;
@@ -1819,6 +1814,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                 } else if (qp[3 * kGroup + lane].y == 0u) {
                     mine = false;
                     extra = true;
+                    if (!FROM_LIST) {
+                        // for the second round: the radius expected to hold
+                        // knn_target(K) at the density the first ball showed
+                        // (grown by 1.15 to 2 times, the cap at most), and its
+                        // table prefix from the radius index of the row class
+                        const float sc =
+                            fminf(2.0f, fmaxf(1.15f, cbrtf(knn_target((float)kk) / fmaxf((float)nq, 0.5f))));
+                        const uint32_t kb = (uint32_t)min((uint64_t)d1.x, (uint64_t)((float)d2.y * sc) + 1u);
+                        const uint32_t e1 = 1u << L.F, sh = L.F - T.s;
+                        const uint32_t cls = ((d0.y & (e1 - 1u)) >> sh) | (((d0.z & (e1 - 1u)) >> sh) << T.s);
+                        const uint32_t jb = (uint32_t)(((uint64_t)kb + (1u << T.rshift) - 1u) >> T.rshift);
+                        A.desc[4 * (size_t)qi + 2] = make_uint4(d2.x, kb, T.rindex[(size_t)cls * T.nr + jb], d2.w);
+                    }
                 }
             }
             if (invalid) {
@@ -2213,8 +2221,9 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t* wsum) 
 }
 
 // Sort the block's n <= kLongCap pairs (td, ti) by (dist^2, id) and store
-// them at dst; every pair has dist^2 <= r2.
-__device__ void block_sort_store(const uint64_t* td, const uint32_t* ti, uint64_t* sd, uint32_t* si, uint32_t* hist,
+// them at dst; every pair has dist^2 <= r2.  The pairs stay where they are:
+// the bucket pass orders their indices (sx), which the rank pass follows.
+__device__ void block_sort_store(const uint64_t* td, const uint32_t* ti, uint32_t* sx, uint32_t* hist,
                                  uint32_t* wsum, uint32_t n, uint64_t r2, uint32_t* dst_ids, int64_t* dst_d2) {
     const uint32_t tid = threadIdx.x, nt = blockDim.x;
     const float scale = r2 > 0 ? (float)n / (float)r2 : 0.0f;
@@ -2235,20 +2244,21 @@ __device__ void block_sort_store(const uint64_t* td, const uint32_t* ti, uint64_
             run += c;
         }
     __syncthreads();
-    // scatter by bucket: each bucket's cursor ends at the next one's start
-    for (uint32_t t = tid; t < n; t += nt) {
-        const uint32_t pos = atomicAdd(&hist[sort_bucket(td[t], scale, n)], 1u);
-        sd[pos] = td[t];
-        si[pos] = ti[t];
-    }
+    // scatter the indices by bucket: each bucket's cursor ends at the next
+    // one's start
+    for (uint32_t t = tid; t < n; t += nt) sx[atomicAdd(&hist[sort_bucket(td[t], scale, n)], 1u)] = t;
     __syncthreads();
     for (uint32_t t = tid; t < n; t += nt) {
-        const uint64_t d = sd[t];
-        const uint32_t id = si[t];
+        const uint32_t i = sx[t];
+        const uint64_t d = td[i];
+        const uint32_t id = ti[i];
         const uint32_t b = sort_bucket(d, scale, n);
         const uint32_t lo = b ? hist[b - 1] : 0u, hi = hist[b];
         uint32_t rank = lo;
-        for (uint32_t j = lo; j < hi; ++j) rank += key_less(sd[j], si[j], d, id) ? 1u : 0u;
+        for (uint32_t j = lo; j < hi; ++j) {
+            const uint32_t o = sx[j];
+            rank += key_less(td[o], ti[o], d, id) ? 1u : 0u;
+        }
         dst_ids[rank] = id;
         if (dst_d2) dst_d2[rank] = (int64_t)d;
     }
@@ -2258,10 +2268,9 @@ template <int METHOD>
 __global__ __launch_bounds__(512) void long_kernel(LatArgs L, TabArgs T, QArgs A) {
     extern __shared__ __align__(16) char smem[];
     uint64_t* td = (uint64_t*)smem;  // hits in arrival order
-    uint64_t* sd = td + kLongCap;    // by bucket
-    uint32_t* ti = (uint32_t*)(sd + kLongCap);
-    uint32_t* si = ti + kLongCap;
-    uint32_t* hist = si + kLongCap;
+    uint32_t* ti = (uint32_t*)(td + kLongCap);
+    uint32_t* sx = ti + kLongCap;    // their indices by bucket
+    uint32_t* hist = sx + kLongCap;
     uint32_t* ctl = hist + kLongCap;  // [0] hits so far, [1] list entry taken, [4, 12) wave sums
     const uint32_t wave = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = lane_id();
     uint32_t* own = ctl + 16 + wave * 64;
@@ -2308,7 +2317,7 @@ __global__ __launch_bounds__(512) void long_kernel(LatArgs L, TabArgs T, QArgs A
         }
         __syncthreads();
         if (mine)
-            block_sort_store(td, ti, sd, si, hist, ctl + 4, min(ctl[0], rowlen), s.r2, A.out_ids + rb,
+            block_sort_store(td, ti, sx, hist, ctl + 4, min(ctl[0], rowlen), s.r2, A.out_ids + rb,
                              A.out_d2 ? A.out_d2 + rb : nullptr);
         __syncthreads();
     }
@@ -2457,7 +2466,7 @@ int device_cu_count() {
     return cus;
 }
 
-size_t long_lds_bytes(uint32_t waves) { return (size_t)kLongCap * 28 + 64 + (size_t)waves * 256; }
+size_t long_lds_bytes(uint32_t waves) { return (size_t)kLongCap * 20 + 64 + (size_t)waves * 256; }
 
 // LDS bytes per block: pass 0 count (3 with the stash), 1 write, 2 top-M,
 // 4 grouped count (5 with the stash).

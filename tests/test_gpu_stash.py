@@ -244,7 +244,7 @@ def test_grouped_knn_radius_rows_match_oracle(sx, orc, mask):
     dense clusters (rows kept from a radius that holds K), sparse regions and
     small caps (fewer than K inside: searched again in groups at a larger
     radius, then one query per wavefront, or every object when the radius
-    covers the cap), K above a quarter of the hit buffer (one query per
+    covers the cap), K above half the hit buffer (one query per
     wavefront), buffers that overflow.  Cells holding a tight clump in one
     corner and a lone object in the opposite corner make the home-cell
     density far too high for the lone object's rows, so that they fail both
