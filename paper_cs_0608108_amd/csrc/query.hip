@@ -170,7 +170,10 @@ __device__ __forceinline__ uint64_t sq(uint32_t g) { return (uint64_t)g * (uint6
 
 // F_LIST: the query walks the non-empty cell list (neither F_SPHERE nor
 // F_LIST: the bounding cube).
-enum : uint32_t { F_VALID = 1u, F_KNN = 2u, F_SPHERE = 4u, F_OUTSIDE = 8u, F_LIST = 16u };
+// F_KBOUND: a K-NN row whose count pass found K objects within the radius
+// stored in descriptor word 12 (an upper bound of its K-th distance; sphere
+// walks only, which leave that word unused)
+enum : uint32_t { F_VALID = 1u, F_KNN = 2u, F_SPHERE = 4u, F_OUTSIDE = 8u, F_LIST = 16u, F_KBOUND = 32u };
 
 struct Query {
     uint32_t q[3];  // normalised centre
@@ -184,6 +187,7 @@ struct Query {
     uint32_t nn[3]; // cube: cells per axis (cell list: 0, its length, 1)
     int32_t lo[3];  // cube: first cell per axis
     uint32_t self;  // sorted position excluded (EXCLUDE_SELF, all agents) or ~0
+    uint32_t kbr;   // F_KBOUND: a radius holding K objects
     uint32_t c[3];  // home cell
     uint32_t f[3];  // position inside the home cell
     uint32_t up[3]; // e - f: distance to the next cell up
@@ -435,6 +439,7 @@ __device__ __forceinline__ Query load_query(const LatArgs& L, const QArgs& A, ui
         s.lo[1] = (int32_t)d[13];
         s.lo[2] = (int32_t)d[14];
     }
+    s.kbr = (s.flags & F_KBOUND) ? d[12] : 0u;
     s.self = (A.qx == nullptr && (A.flags & SPHIDX_EXCLUDE_SELF)) ? qi : kMaxId;
     const uint32_t e = 1u << L.F;
     for (int a = 0; a < 3; ++a) {
@@ -1145,6 +1150,7 @@ __device__ __forceinline__ uint64_t first_bound(const LatArgs& L, const Query& s
     if (!(s.flags & F_SPHERE)) return s.r2;
     const float e = (float)(1u << L.F);
     float rho;
+    if (s.flags & F_KBOUND) return min(s.r2, sq(s.kbr));
     if (s.flags & F_KNN) {
         const uint32_t home = pack_cell(L, s.c[0], s.c[1], s.c[2]);
         const float dens = fmaxf((float)L.n / (float)(L.ncells ? L.ncells : 1u), (float)(L.cs[home + 1] - L.cs[home]));
@@ -1388,10 +1394,12 @@ __global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs 
             return;
         }
         uint32_t hits = 0, inner = 0, kept = 0, cand = 0, walked = 0;
+        uint64_t dmax = 0;  // K-NN: the largest dist^2 among the hits so far
         bool self_inner = false;
         auto visit = [&](bool act, uint32_t p, const uint4& P) -> bool {
             const uint64_t d2 = obj_dist2(aw, s, P);
             const bool hit = act && d2 <= s.r2 && p != s.self;
+            if (knn && hit) dmax = max(dmax, d2);
             const uint64_t hm = __ballot(hit);
             if (STASH && hit) {
                 const uint32_t slot = hits + lanes_below(hm);
@@ -1416,6 +1424,18 @@ __global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs 
                                       [&]() { return s.r2; }, on_row);
             uint32_t total = hits + wave_sum(inner);
             if (__ballot(self_inner) != 0) total -= 1;
+            if (knn && (s.flags & F_SPHERE) && total >= s.k) {
+                // the walk found K objects within the largest of their
+                // distances: that radius (rounded up) bounds the K-th
+                // distance, and the write pass's top-K starts from it
+                const uint32_t rb = (uint32_t)min((double)s.r, ceil(sqrt((double)dmax)) + 1.0);
+                const uint32_t rbm = lane_val(scan_max(rb), 63);
+                if (lane == 0) {
+                    uint32_t* dw = (uint32_t*)(A.desc + 4 * (size_t)qi);
+                    dw[12] = rbm;
+                    dw[6] = s.flags | F_KBOUND;
+                }
+            }
             if (knn && total > s.k) total = s.k;
             hits = total;
         }

@@ -181,7 +181,7 @@ def run_admission_model(batches, executor, slots, pool_bytes, keep=False, clock=
 class GpuExecutor:
     """Runs batches on the device: one stream, workspace and input buffers per slot."""
 
-    def __init__(self, lat, tab, slots, max_batch, pool_bytes, launch=None, stash_pairs=1 << 24):
+    def __init__(self, lat, tab, slots, max_batch, pool_bytes, launch=None, stash_pairs=1 << 25):
         import torch
 
         from . import sphidx
