@@ -1521,6 +1521,7 @@ __host__ __device__ constexpr uint32_t group_chunk(uint32_t cap) {
 }
 // 64-row layers of the largest chunk (sort_cap 256)
 constexpr uint32_t kLayers = (group_chunk(256) + 63) / 64;
+static_assert(kLayers * 64 + 1 <= 255, "candidate-step owner marks hold a chunk row + 1 in one byte");
 __host__ __device__ constexpr size_t group_lds_per_wave(bool stash, uint32_t cap) {
     return 640 + 128 + 256 + (stash ? (size_t)group_hitcap(cap) * 20 : (size_t)group_chunk(cap) * 16);
 }
@@ -1735,17 +1736,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                 // ---- owner row of each of the 64 slots from cb: a row marks
                 // where its range starts in the step (a row begun earlier
                 // marks slot 0), and a max-scan hands every slot to its row
+                // The marks cover a window of four steps (256 slots, one
+                // byte each in the owner map's words): rows are marked once
+                // per window, and each step max-scans its 64 bytes on top of
+                // the owner the window's earlier steps ended with.  Steps are
+                // located in order, each once.
+                uint8_t* own8 = (uint8_t*)own;
+                uint32_t wcarry = 0;
                 auto locate = [&](uint32_t cb, uint32_t& pos, uint32_t& sl) -> bool {
-                    wave_sync();
-                    own[lane] = 0;
-                    wave_sync();
+                    const uint32_t wb = cb & ~255u, wo = cb - wb;
+                    if (wo == 0) {
+                        wave_sync();
+                        own[lane] = 0;
+                        wave_sync();
 #pragma unroll
-                    for (uint32_t k = 0; k < kLayers; ++k)
-                        if (cin[k] > cex[k] && cex[k] < cb + 64 && cin[k] > cb)
-                            own[cex[k] > cb ? cex[k] - cb : 0] = k * 64u + lane + 1u;
-                    wave_sync();
+                        for (uint32_t k = 0; k < kLayers; ++k)
+                            if (cin[k] > cex[k] && cex[k] < wb + 256u && cin[k] > wb)
+                                own8[cex[k] > wb ? cex[k] - wb : 0] = (uint8_t)(k * 64u + lane + 1u);
+                        wave_sync();
+                        wcarry = 0;
+                    }
+                    const uint32_t m = max(scan_max((uint32_t)own8[wo + lane]), wcarry);
+                    wcarry = lane_val(m, 63);
                     // (a step past the end marks nothing: row 0 stands in)
-                    const uint32_t o = max(scan_max(own[lane]), 1u) - 1u;
+                    const uint32_t o = max(m, 1u) - 1u;
                     const uint4 ri = rinfo[o];
                     const uint32_t g = cb + lane;
                     pos = (g < ri.y ? ri.x : ri.z) + g;
