@@ -776,8 +776,9 @@ def leg_knn(args, out):
     lat.build(*dev)
     q = sphidx.make_queries(n, None, cap, K, sphidx.MODE_KNN, 0)
     # rows are at most K long: with stash room the count pass searches each
-    # row once and keeps it, and the write pass only copies.  Rows searched
-    # in groups as radius rows keep their whole radius row (about 1.7K pairs)
+    # row once and keeps it, and the write pass only copies (rows searched in
+    # groups as radius rows keep their first K; the rest of the room absorbs
+    # the regions' unused chunk tails)
     buf = sphidx.QueryBuffers(n, n * K, want_dist2=False, stash_pairs=3 * n * K)
 
     def step_with(launch, count_launch=None):
