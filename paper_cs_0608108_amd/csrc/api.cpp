@@ -175,10 +175,10 @@ sphidx_status resolve_launch(const sphidx_launch* in, const sphidx_tables* tab, 
 }
 
 // Query workspace: counters | descriptors[Q] | longq[Q] | fbq[Q] | walkq[Q] |
-// soff[Q] | xq[Q] | scan partials, then the stash: every byte beyond the
-// minimum.
+// soff[Q] | xq[Q] | lq[Q] | scan partials, then the stash: every byte beyond
+// the minimum.
 struct QLayout {
-    size_t counters, desc, longq, fbq, walkq, soff, xq, scan, total;
+    size_t counters, desc, longq, fbq, walkq, soff, xq, lq, scan, total;
 };
 
 QLayout query_layout(uint32_t Q) {
@@ -196,6 +196,7 @@ QLayout query_layout(uint32_t Q) {
     l.walkq = take((size_t)Q * 4);
     l.soff = take((size_t)Q * 4);
     l.xq = take((size_t)Q * 4);
+    l.lq = take((size_t)Q * 4);
     l.scan = take(scan_i64_tmp_bytes(Q));
     l.total = off;
     return l;
@@ -242,12 +243,14 @@ QArgs q_args(const sphidx_queries* q, sphidx_csr* csr, const Launch& ln) {
     A.walk_count = lists + 2 * SPHIDX_QSTRIDE;
     A.stash_hdr = lists + 3 * SPHIDX_QSTRIDE;
     A.xq_count = lists + 4 * SPHIDX_QSTRIDE;
+    A.lq_count = lists + 5 * SPHIDX_QSTRIDE;
     A.stash_ctr = lists + SPHIDX_NLISTS * SPHIDX_QSTRIDE;
     A.longq = (uint32_t*)(ws + ql.longq);
     A.fbq = (uint32_t*)(ws + ql.fbq);
     A.walkq = (uint32_t*)(ws + ql.walkq);
     A.soff = (uint32_t*)(ws + ql.soff);
     A.xq = (uint32_t*)(ws + ql.xq);
+    A.lq = (uint32_t*)(ws + ql.lq);
     A.desc = (uint4*)(ws + ql.desc);
     A.stash_base = ws + ql.total;
     A.stats = ln.stats;

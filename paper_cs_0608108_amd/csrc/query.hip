@@ -172,8 +172,11 @@ __device__ __forceinline__ uint64_t sq(uint32_t g) { return (uint64_t)g * (uint6
 // F_LIST: the bounding cube).
 // F_KBOUND: a K-NN row whose count pass found K objects within the radius
 // stored in descriptor word 12 (an upper bound of its K-th distance; sphere
-// walks only, which leave that word unused)
-enum : uint32_t { F_VALID = 1u, F_KNN = 2u, F_SPHERE = 4u, F_OUTSIDE = 8u, F_LIST = 16u, F_KBOUND = 32u };
+// walks only, which leave that word unused).  F_LONG: a radius row expected
+// to be longer than a wavefront's buffer, counted and kept one block per row.
+enum : uint32_t {
+    F_VALID = 1u, F_KNN = 2u, F_SPHERE = 4u, F_OUTSIDE = 8u, F_LIST = 16u, F_KBOUND = 32u, F_LONG = 64u
+};
 
 struct Query {
     uint32_t q[3];  // normalised centre
@@ -218,7 +221,7 @@ __host__ __device__ inline float knn_target(float k) {
 template <int METHOD>
 __global__ __launch_bounds__(256) void setup_kernel(LatArgs L, TabArgs T, QArgs A) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    bool range_bad = false, fallback = false, to_list = false;
+    bool range_bad = false, fallback = false, to_list = false, longrow = false;
     if (i < A.Q) {
         uint32_t q[3], row, r, k;
         bool valid = true;
@@ -335,6 +338,16 @@ __global__ __launch_bounds__(256) void setup_kernel(LatArgs L, TabArgs T, QArgs 
         fallback = valid && tables && !usable;
         // (chosen per query: the main kernels take every walk themselves)
         to_list = valid && tables && !sphere && A.select != 1u;
+        // a radius row of the main kernels expected (at the lattice's mean
+        // density) to pass 5/4 of a wavefront's row buffer: with the stash
+        // and the block kernel, one block counts, orders and keeps it in a
+        // single walk instead of a count walk and a write walk
+        // (not with per-query statistics, which that kernel does not keep)
+        if (valid && !knn && !to_list && A.stash && A.long_waves > 1 && !A.stats) {
+            const float rc = (float)r / (float)e;
+            const float expect = 4.18879f * rc * rc * rc * ((float)L.n / (float)L.ncells);
+            longrow = expect > 1.25f * (float)A.sort_cap;
+        }
         uint32_t tb = 0, tend = 0, kb = 0, kend = 0;
         if (METHOD == kPaper && sphere && valid) {
             // the paper's tables (Section III.A): with d = r / e, the unshaved
@@ -392,7 +405,7 @@ __global__ __launch_bounds__(256) void setup_kernel(LatArgs L, TabArgs T, QArgs 
             A.method_out[row] = !valid ? 0xFFFFFFFFu
                                        : sphere ? SPHIDX_METHOD_SPHERE : list ? SPHIDX_METHOD_LIST : SPHIDX_METHOD_CUBE;
         const uint32_t flags = (valid ? F_VALID : 0u) | (knn ? F_KNN : 0u) | (sphere ? F_SPHERE : 0u) |
-                               (outside ? F_OUTSIDE : 0u) | (list ? F_LIST : 0u);
+                               (outside ? F_OUTSIDE : 0u) | (list ? F_LIST : 0u) | (longrow ? F_LONG : 0u);
         uint4* d = A.desc + 4 * (size_t)i;
         d[0] = make_uint4(q[0], q[1], q[2], row);
         d[1] = make_uint4(r, k, flags, tb);
@@ -409,6 +422,13 @@ __global__ __launch_bounds__(256) void setup_kernel(LatArgs L, TabArgs T, QArgs 
         if (lane_id() == 0) base = atomicAdd(A.fb_count, (uint32_t)__popcll(lm));
         base = uni(base);
         if (to_list) A.fbq[base + lanes_below(lm)] = i;
+    }
+    const uint64_t gm = __ballot(longrow);
+    if (gm) {
+        uint32_t base = 0;
+        if (lane_id() == 0) base = atomicAdd(A.lq_count, (uint32_t)__popcll(gm));
+        base = uni(base);
+        if (longrow) A.lq[base + lanes_below(gm)] = i;
     }
     if (__ballot(range_bad) && lane_id() == 0) atomicOr(L.status, SPHIDX_FLAG_RANGE);
     if (__ballot(fallback) && lane_id() == 0) atomicOr(L.status, SPHIDX_FLAG_FALLBACK);
@@ -1362,6 +1382,7 @@ __global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs 
         const Query s = load_query(L, A, qi);
         if ((METHOD == kSphere || METHOD == kPaper) && (s.flags & F_VALID) && !(s.flags & F_SPHERE))
             return;  // fallback list
+        if (!FROM_LIST && (s.flags & F_LONG)) return;  // counted one block per row
         const bool knn = s.flags & F_KNN;
         if (KSTASH && knn && (s.flags & F_VALID) && s.k <= 64u) {
             // the row itself: lane i ends with the i-th nearest
@@ -1610,6 +1631,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                         knn = true;
                         rows = d2.z + ((flags & F_OUTSIDE) ? 1u : 0u);
                     }
+                } else if (flags & F_LONG) {
+                    // counted one block per row
                 } else if ((flags & (F_KNN | F_LIST)) || r2bits > d2bits) {
                     extra = true;
                 } else {
@@ -2298,20 +2321,26 @@ __device__ void block_sort_store(const uint64_t* td, const uint32_t* ti, uint32_
     }
 }
 
-template <int METHOD>
+// COUNT: the count pass's form.  The rows come from the list of rows the
+// setup expected to be long; the block counts the row, writes its size and,
+// when it holds at most kLongCap pairs and the stash has room, orders it into
+// the stash (one allocation per row) for the write pass to copy; otherwise
+// the row goes on the walk list like any row the count pass did not keep.
+template <int METHOD, bool COUNT>
 __global__ __launch_bounds__(512) void long_kernel(LatArgs L, TabArgs T, QArgs A) {
     extern __shared__ __align__(16) char smem[];
     uint64_t* td = (uint64_t*)smem;  // hits in arrival order
     uint32_t* ti = (uint32_t*)(td + kLongCap);
     uint32_t* sx = ti + kLongCap;    // their indices by bucket
     uint32_t* hist = sx + kLongCap;
-    uint32_t* ctl = hist + kLongCap;  // [0] hits so far, [1] list entry taken, [4, 12) wave sums
+    uint32_t* ctl = hist + kLongCap;  // [0] hits so far, [1] list entry taken, [2] stash offset, [4, 12) wave sums
     const uint32_t wave = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = lane_id();
     uint32_t* own = ctl + 16 + wave * 64;
-    if (A.row_ptr[A.Q] > A.capacity) return;  // (the write kernel sets the flag)
+    if (!COUNT && A.row_ptr[A.Q] > A.capacity) return;  // (the write kernel sets the flag)
     const AxisWrap aw = axis_wrap(L);
     const uint32_t nq = uni(*A.list_count);
-    uint32_t* qc = queue_set(A, kQExtra);
+    uint32_t* qc = queue_set(A, (int)A.list_set);
+    const uint32_t region = blockIdx.x % SPHIDX_NREGION;
     for (;;) {
         if (threadIdx.x == 0) {
             ctl[1] = atomicAdd(qc, 1u);
@@ -2322,8 +2351,12 @@ __global__ __launch_bounds__(512) void long_kernel(LatArgs L, TabArgs T, QArgs A
         if (t >= nq) break;
         const uint32_t qi = uni(A.list[t]);
         const Query s = load_query(L, A, qi);
-        const int64_t rb = A.row_ptr[s.row];
-        const uint32_t rowlen = (uint32_t)(A.row_ptr[s.row + 1] - rb);
+        int64_t rb = 0;
+        uint32_t rowlen = kLongCap;
+        if (!COUNT) {
+            rb = A.row_ptr[s.row];
+            rowlen = (uint32_t)(A.row_ptr[s.row + 1] - rb);
+        }
         // the same for every wave of the block
         const bool mine = (s.flags & F_VALID) && !(s.flags & F_KNN) && rowlen > 0 && rowlen <= kLongCap;
         if (mine) {
@@ -2350,9 +2383,31 @@ __global__ __launch_bounds__(512) void long_kernel(LatArgs L, TabArgs T, QArgs A
             }, 64u * wave, 64u * nw);
         }
         __syncthreads();
-        if (mine)
+        if (COUNT) {
+            const uint32_t n = (s.flags & F_VALID) ? ctl[0] : 0u;
+            if (threadIdx.x == 0) {
+                A.row_ptr[s.row] = (int64_t)n;
+                uint32_t off = 0u;  // empty rows: nothing to copy
+                if (n > 0) {
+                    off = kMaxId;
+                    if (n <= kLongCap && A.stash) {
+                        const uint32_t c = atomicAdd(A.stash_ctr + region * SPHIDX_QSTRIDE, n);
+                        if ((uint64_t)c + n <= A.stash_region) off = region * A.stash_region + c;
+                    }
+                    if (off == kMaxId) A.walkq[atomicAdd(A.walk_count, 1u)] = qi;
+                }
+                A.soff[qi] = off;
+                ctl[2] = off;
+            }
+            __syncthreads();
+            const uint32_t off = ctl[2];
+            if (n > 0 && off != kMaxId)
+                block_sort_store(td, ti, sx, hist, ctl + 4, n, s.r2, A.stash_ids + off,
+                                 A.stash_d2 ? A.stash_d2 + off : nullptr);
+        } else if (mine) {
             block_sort_store(td, ti, sx, hist, ctl + 4, min(ctl[0], rowlen), s.r2, A.out_ids + rb,
                              A.out_d2 ? A.out_d2 + rb : nullptr);
+        }
         __syncthreads();
     }
 }
@@ -2522,6 +2577,35 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
     const uint32_t lists = SPHIDX_NQSETS * SPHIDX_NQUEUE * SPHIDX_QSTRIDE;
     const uint32_t set_words = SPHIDX_NQUEUE * SPHIDX_QSTRIDE;
     hipError_t e;
+    // one block per long radius row (count pass: the rows the setup listed;
+    // write pass: rows longer than a wavefront's buffer)
+    auto launch_long = [&](bool count, const QArgs& qa) -> hipError_t {
+        const void* lf =
+            count ? (variant == 0   ? (const void*)long_kernel<kCube, true>
+                     : variant == 3 ? (const void*)long_kernel<kPaper, true>
+                                    : (const void*)long_kernel<kEither, true>)
+                  : (variant == 0   ? (const void*)long_kernel<kCube, false>
+                     : variant == 3 ? (const void*)long_kernel<kPaper, false>
+                                    : (const void*)long_kernel<kEither, false>);
+        const size_t lds = long_lds_bytes(qa.long_waves);
+        const uint32_t per_cu = (uint32_t)std::max<size_t>(1, (160u * 1024u) / lds);
+        LatArgs l = L;
+        TabArgs t = T;
+        QArgs a = qa;
+        void* args[] = {&l, &t, &a};
+        return hipLaunchKernel(lf, dim3((uint32_t)device_cu_count() * per_cu), dim3(64u * qa.long_waves), args, lds,
+                               st);
+    };
+    // whether the setup can have listed rows for it: a radius at the tables'
+    // cap (per-query radii) or the batch's radius, at the lattice's mean
+    // density, expected above 5/4 of the row buffer (the setup's test, with a
+    // margin for its single precision)
+    auto long_rows_possible = [&]() -> bool {
+        if (!q.stash || q.long_waves <= 1 || q.mode == SPHIDX_MODE_KNN || q.stats || L.ncells == 0) return false;
+        if (q.rad && (!T.has || q.select == 1u)) return true;
+        const double rc = (double)(q.rad ? T.rmax : q.rad_u) / (double)(1u << L.F);
+        return 4.18879 * rc * rc * rc * ((double)L.n / (double)L.ncells) > 0.98 * 1.25 * (double)q.sort_cap;
+    };
     if (pass == 0) {
         // everything, then the stash header for the write pass
         const uint4 hv = make_uint4(q.stash, q.stash ? q.stash_region * SPHIDX_NREGION : 0u, q.stash_d2 ? 1u : 0u,
@@ -2553,6 +2637,15 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
     const bool either = variant != 0 && q.select == 1u;
     QArgs ql = q;  // list-driven launches: persistent, grabs sized from the list
     ql.persistent = 1;
+    // the count pass's long rows: the setup's list, with the walk-list queue
+    // set (the write pass's, cleared when it starts)
+    auto long_list = [&]() {
+        QArgs a = ql;
+        a.list = q.lq;
+        a.list_count = q.lq_count;
+        a.list_set = kQWalk;
+        return a;
+    };
     if (pass == 0) {
         const int lp = q.stash ? 3 : 0;
         // K-NN rows searched and kept by the count pass
@@ -2578,6 +2671,7 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
                                q.Q, q, w, b, gl, st, L, T);
             if (e == hipSuccess) e = mark(ev_end);
             if (e != hipSuccess) return e;
+            if (long_rows_possible() && (e = launch_long(true, long_list())) != hipSuccess) return e;
             if (variant != 0 && !either) {
                 QArgs qg = ql;
                 qg.list = q.fbq;
@@ -2631,7 +2725,9 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
                         : SPHIDX_PICKP(count_kernel, variant, kSphere, , false, false, false);
         e = launch_ptr(fn, q.Q, q, w, b, query_lds_bytes(lp, q.sort_cap, w, tb), st, L, T);
         if (e == hipSuccess) e = mark(ev_end);
-        if (e != hipSuccess || variant == 0 || either) return e;
+        if (e != hipSuccess) return e;
+        if (long_rows_possible() && (e = launch_long(true, long_list())) != hipSuccess) return e;
+        if (variant == 0 || either) return hipSuccess;
         ql.list = q.fbq;
         ql.list_count = q.fb_count;
         ql.list_set = kQFbCount;
@@ -2666,17 +2762,8 @@ hipError_t launch_query_pass(int pass, const LatArgs& L, const TabArgs& T, const
         ql.list = q.longq;
         ql.list_count = q.long_count;
         if (q.long_waves > 1) {
-            const void* lf = variant == 0   ? (const void*)long_kernel<kCube>
-                             : variant == 3 ? (const void*)long_kernel<kPaper>
-                                            : (const void*)long_kernel<kEither>;
-            const size_t lds = long_lds_bytes(q.long_waves);
-            const uint32_t per_cu = (uint32_t)std::max<size_t>(1, (160u * 1024u) / lds);
-            LatArgs l = L;
-            TabArgs t = T;
-            QArgs a = ql;
-            void* args[] = {&l, &t, &a};
-            e = hipLaunchKernel(lf, dim3((uint32_t)device_cu_count() * per_cu), dim3(64u * q.long_waves), args, lds, st);
-            if (e != hipSuccess) return e;
+            ql.list_set = kQExtra;
+            if ((e = launch_long(false, ql)) != hipSuccess) return e;
         }
         ql.list_set = kQTopm;
         return launch_ptr(SPHIDX_PICKP(topm_kernel, variant, kEither, , true), 0, ql, w, b, sh2, st, L, T);

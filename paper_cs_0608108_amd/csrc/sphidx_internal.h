@@ -134,6 +134,8 @@ struct QArgs {
     uint32_t* walkq;    // stash mode: queries the count pass did not stash
     uint32_t* xq_count;
     uint32_t* xq;       // grouped count: queries left to the one-query-per-wave kernel
+    uint32_t* lq_count;
+    uint32_t* lq;       // stash mode: radius rows expected to be long, counted one block per row
     uint32_t* soff;     // stash mode: per query, first stash element of its sorted row
     uint32_t* stash_hdr;  // stash header written by the count pass (see StashHdr)
     uint32_t* stash_ctr;  // NQUEUE per-region allocation counters
@@ -172,7 +174,7 @@ enum : uint32_t { kHdrMode = 0, kHdrElems = 1, kHdrHasD2 = 2, kHdrD2Off = 3 };
 #define SPHIDX_NREGION SPHIDX_NXCD  // stash regions, one per XCD
 #define SPHIDX_QSTRIDE 32       // counters 128 bytes apart: one L2 line each
 #define SPHIDX_NQSETS 7         // count, write, top-M, fallback count, fallback write, walk list, extra list
-#define SPHIDX_NLISTS 5         // long_count, fb_count, walk_count, stash header, xq_count
+#define SPHIDX_NLISTS 6         // long_count, fb_count, walk_count, stash header, xq_count, lq_count
 #define SPHIDX_COUNTER_WORDS \
     ((SPHIDX_NQSETS * SPHIDX_NQUEUE + SPHIDX_NLISTS + SPHIDX_NREGION) * SPHIDX_QSTRIDE)
 #define SPHIDX_MAX_LOG2_SUM 30
