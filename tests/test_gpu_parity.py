@@ -187,7 +187,7 @@ def test_radius_random_worlds(sx, orc, mask, world):
 def test_radius_uniform_cyclic_32_full_vs_brute_force(sx, orc):
     from paper_cs_0608108_amd import synth
     w = synth.radius_uniform_cyclic()
-    say("C1", w.name)
+    say("uniform cyclic 32^3, 4,096 points", w.name)
     L = orc.Lattice(w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask)
     ref = orc.radius_brute(L, w.pts, w.r_fx)
     lat = lattice(sx, w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask, w.pts)
@@ -196,29 +196,29 @@ def test_radius_uniform_cyclic_32_full_vs_brute_force(sx, orc):
         for name, ln in _launches(sx).items():
             if ln.table_in_lds and tab.info().total_entries * 16 > 60000:
                 continue
-            assert_same(run(sx, lat, tab, w.r_fx, launch=ln), ref, f"C1 {name} s={s}")
+            assert_same(run(sx, lat, tab, w.r_fx, launch=ln), ref, f"uniform 4,096 points {name} s={s}")
         # uniform radius passed as a scalar
-        assert_same(run(sx, lat, tab, int(w.r_fx[0])), ref, "C1 scalar radius")
+        assert_same(run(sx, lat, tab, int(w.r_fx[0])), ref, "uniform 4,096 points, scalar radius")
 
 
 def test_radius_uneven_clipped_full_size(sx, orc):
     from paper_cs_0608108_amd import synth
     w = synth.radius_uneven_clipped()
-    say("C2", w.name)
+    say("uneven radius, 1,048,576 points", w.name)
     L = orc.Lattice(w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask)
     ref = orc.Grid(L, w.pts).radius(w.r_fx)
-    say("C2 oracle pairs", int(ref.row_ptr[-1]))
+    say("uneven radius oracle pairs", int(ref.row_ptr[-1]))
     lat = lattice(sx, w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask, w.pts)
     tab = sx.Tables(lat, 2, 4 * 65536)
     for name in ("sphere-persistent", "sphere-plain", "cube"):
-        assert_same(run(sx, lat, tab, w.r_fx, launch=_launches(sx)[name]), ref, f"C2 {name}")
+        assert_same(run(sx, lat, tab, w.r_fx, launch=_launches(sx)[name]), ref, f"uneven radius {name}")
     # the launches the benchmark times: groups of queries whose rows are
     # sorted and kept in the count pass, grabs of 256 and of 64 queries
     for tile, bpc in ((256, 8), (64, 6)):
         ln = sx.LaunchConfig(method=sx.METHOD_SPHERE, schedule=sx.SCHED_PERSISTENT, grouped=1, interior=1,
                              sort_cap=256, waves_per_block=4, tile=tile, blocks_per_cu=bpc)
-        say("C2 grouped with the stash", tile, bpc)
-        assert_same(run(sx, lat, tab, w.r_fx, launch=ln, stash=True), ref, f"C2 grouped stash tile {tile}")
+        say("uneven radius grouped with the stash", tile, bpc)
+        assert_same(run(sx, lat, tab, w.r_fx, launch=ln, stash=True), ref, f"uneven radius grouped stash tile {tile}")
 
 
 # ---------------------------------------------------------------------------
@@ -256,7 +256,7 @@ def test_knn_clustered_full_size_every_row(sx, orc):
     lat = lattice(sx, w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask, w.pts)
     tab = sx.Tables(lat, 2, cap)
     q = sx.make_queries(n, None, cap, K, sx.MODE_KNN, 0)
-    say("C3 oracle: K nearest of all 4,194,304 points")
+    say("clustered K-NN oracle: K nearest of all 4,194,304 points")
     g = orc.Grid(orc.Lattice(w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask), w.pts)
     ref = g.knn(K, cap)
     g.close()
@@ -266,11 +266,11 @@ def test_knn_clustered_full_size_every_row(sx, orc):
         lat.build(*lat._pts_dev)
         ln = sx.LaunchConfig(method=sx.METHOD_SPHERE, schedule=sx.SCHED_PERSISTENT, grouped=1, interior=1,
                              sort_cap=256, waves_per_block=4, tile=tile, blocks_per_cu=bpc)
-        say("C3 grouped with the stash", order, tile, bpc)
+        say("clustered K-NN grouped with the stash", order, tile, bpc)
         buf = sx.QueryBuffers(n, n * K, want_dist2=True, stash_pairs=3 * n * K)
         sx.query(lat, tab, q, buf, ln)
         torch.cuda.synchronize()
-        assert_same(buf.host(), ref, f"C3 every row, order {order}, tile {tile}")
+        assert_same(buf.host(), ref, f"clustered K-NN every row, order {order}, tile {tile}")
         del buf
     code, flags = lat.status()
     assert code == sx.OK and flags == 0

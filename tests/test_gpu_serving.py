@@ -70,7 +70,7 @@ def test_full_size_serving_lattice_mixed_batches(sx, orc):
     from paper_cs_0608108_amd import serving, synth
     w = synth.serving_lattice()
     spec, seed = w.lat, w.extra["seed"]
-    say(f"C5 full size: n={w.n}")
+    say(f"serving lattice, full size: n={w.n}")
     lat = sx.Lattice(spec.log2_cells, spec.frac_bits, spec.cyclic_mask, w.n)
     dev = [sx.to_dev_u32(a) for a in w.pts]
     lat.build(*dev)
@@ -93,7 +93,7 @@ def test_full_size_serving_lattice_mixed_batches(sx, orc):
     torch.cuda.synchronize()
     code, flags = lat.status()
     assert code == sx.OK and not (flags & sx.FLAG_CAPACITY), (code, flags)
-    say("C5 oracle grid")
+    say("serving lattice oracle grid")
     g = orc.Grid(orc.Lattice(spec.log2_cells, spec.frac_bits, spec.cyclic_mask), w.pts)
     for b in batches:
         assert not b.rejected, b.index

@@ -287,7 +287,7 @@ def test_full_size_timestep_in_the_benchmark_launch(sx, orc, resident):
                          sort_cap=256, waves_per_block=4, tile=64, blocks_per_cu=8)
     sim = timestep.AgentSim(w.lat.log2_cells, w.lat.frac_bits, w.lat.cyclic_mask, w.pts, r, seed, launch=ln,
                             resident=resident is True, incremental=resident == "incremental")
-    say(f"C4 full size resident={resident}")
+    say(f"8,388,608-agent timestep, full size, resident={resident}")
     sim.step()
     torch.cuda.synchronize()
     sim.capture()
