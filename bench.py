@@ -994,18 +994,22 @@ def leg_serving(args, out):
     batch_ms = mean_ms(pev)
     del st, tbuf, bbuf
 
-    fast = serving.GpuExecutor(lat, tab, slots, int(sizes.max()), pool, launch=fast_ln)
-    plain = serving.GpuExecutor(lat, tab, 1, int(sizes.max()), pool,
-                                launch=sphidx.LaunchConfig(schedule=sphidx.SCHED_PLAIN))
+    # both paths are the library's serving loop (sphidx_server_*): the
+    # continuous one with `slots` streams and the tuned persistent launch,
+    # the baseline with one slot and the plain schedule (count, size, write,
+    # then the next batch)
+    torch.cuda.synchronize()
+    fast = sphidx.Server(lat, tab, slots, int(sizes.max()), pool, stash_pairs=1 << 25, launch=fast_ln)
+    plain = sphidx.Server(lat, tab, 1, int(sizes.max()), pool, stash_pairs=1 << 25,
+                          launch=sphidx.LaunchConfig(schedule=sphidx.SCHED_PLAIN))
     paths = (("continuous", fast, slots), ("plain_per_batch", plain, 1))
     for _, ex, sl in paths:
-        serving.run_admission_model(make(np.zeros(warm), wq), ex, sl, pool)
-    torch.cuda.synchronize()
+        serving.run_on_server(ex, make(np.zeros(warm), wq))
     # capacity: every batch queued at t = 0
     res = {}
     for name, ex, sl in paths:
         bs = make(np.zeros(nb))
-        serving.run_admission_model(bs, ex, sl, pool)
+        serving.run_on_server(ex, bs)
         res[name + "_saturated"] = serving.latency_stats(bs)
         log(f"serving {name} saturated: {res[name + '_saturated']['queries_per_s']:.0f} q/s")
     mean_batch = float(sizes.mean())
@@ -1014,9 +1018,9 @@ def leg_serving(args, out):
     def offered(name, ex, sl, rate, tag):
         arr = np.cumsum(synth.serving_interarrivals(seed + tag, nb, rate))
         bs = make(arr)
-        adm = serving.run_admission_model(bs, ex, sl, pool)
+        peak = serving.run_on_server(ex, bs)
         s = serving.latency_stats(bs)
-        s.update({"batches_per_s": round(rate, 2), "pool_peak_bytes": adm.pool.peak,
+        s.update({"batches_per_s": round(rate, 2), "pool_peak_bytes": peak,
                   "rejected": sum(b.rejected for b in bs)})
         return s
 
@@ -1048,7 +1052,7 @@ def leg_serving(args, out):
         pick = sorted(set(order[-2:].tolist()) | {int(order[int(f * (nb - 1))]) for f in np.linspace(0, 0.97, 10)})
         chk = make(np.zeros(nb))
         chk = [chk[i] for i in pick]
-        serving.run_admission_model(chk, fast, slots, pool, keep=True)
+        serving.run_on_server(fast, chk, keep=True)
         L = oracle.Lattice(spec.log2_cells, spec.frac_bits, spec.cyclic_mask)
         g = oracle.Grid(L, w.pts)
         exact = True
@@ -1067,6 +1071,7 @@ def leg_serving(args, out):
         log(f"serving oracle: {cpu['value']:.0f} q/s; {len(chk)} batches bit-exact {exact}")
     out["serving"] = {
         "workload": w.name, "batches": nb, "warmup_batches": warm, "slots": slots,
+        "loop": "the library's serving loop (sphidx_server_run) for both paths",
         "launch": dict(cfg, schedule="persistent"), "subcell_bits": sbits,
         "mean_batch": mean_batch, "median_batch": float(np.median(sizes)), **res,
         "load_own_rate": own,
@@ -1083,6 +1088,8 @@ def leg_serving(args, out):
                              {"bytes_per_query": round(b_alg / 65536, 1), "pairs": bt}),
         "cpu_baseline": cpu,
     }
+    fast.close()
+    plain.close()
     del fast, plain, lat, tab, dev
     torch.cuda.empty_cache()
 

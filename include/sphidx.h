@@ -495,6 +495,76 @@ sphidx_status sphidx_lattice_positions(const sphidx_lattice* lat, uint32_t* x_de
  * (mod 2^64), from row_ptr (Q + 1 entries).  out_dev is uint64[2]. */
 sphidx_status sphidx_count_checksum(const int64_t* row_ptr_dev, uint32_t Q, uint64_t* out_dev, void* stream);
 
+/* ---------------------------------------------------------------------- *
+ * Serving: batches of queries against a device-resident lattice, with
+ * continuous batching (many independent query sets against one maintained
+ * index, the use Section I describes).
+ *
+ * A server holds `slots` batches in flight, each on its own stream (default
+ * priority) with its own inputs, row_ptr and workspace (stash included), so
+ * their kernels overlap on the device.  A batch is started when a slot is
+ * free: its host inputs are staged through pinned memory and its count pass
+ * runs.  When the count is done its exact output size is known, and it is
+ * admitted to the write pass only when that many bytes fit in the server's
+ * output pool (first fit; admission by memory, in arrival order); otherwise
+ * it waits.  Its ids then stay in the pool until the batch is seen complete.
+ * With slots = 1 and a SPHIDX_SCHED_PLAIN launch this is one plain launch
+ * per batch: count, size, write, then the next batch.
+ *
+ * sphidx_server_run replays a schedule: batch i arrives arrival_s seconds
+ * after the call starts (batches sorted by arrival), and the call returns when
+ * every batch is complete.  The lattice must be complete before the call
+ * (its build's stream synchronised) and stay unchanged during it.  Times
+ * are host steady-clock seconds from the start of the call.  The server
+ * allocates its device and pinned memory once, in sphidx_server_create;
+ * runs allocate nothing. */
+typedef struct sphidx_server sphidx_server;
+
+typedef struct {
+    uint32_t count;             /* queries, at most the server's max_batch */
+    const uint32_t* x;          /* host arrays of `count` entries, read when the batch starts */
+    const uint32_t* y;
+    const uint32_t* z;
+    const uint32_t* radius_fx;  /* per query: the radius, or the K-NN cap */
+    const uint32_t* k;          /* per query: K (0 = a radius query); NULL = every query a radius query */
+    double arrival_s;           /* seconds after the run starts */
+    int64_t* row_ptr_out;       /* optional host int64[count + 1]: the batch's row_ptr */
+    uint32_t* ids_out;          /* optional host uint32[ids_capacity]: its ids (rows ordered by
+                                   (dist^2, id)), copied when it completes if they fit */
+    uint64_t ids_capacity;
+} sphidx_batch;
+
+typedef struct {
+    double start_s;             /* its count pass was launched */
+    double admit_s;             /* its write pass was launched (its pool range reserved) */
+    double done_s;              /* its write pass was seen complete (or it was rejected) */
+    int64_t pairs;              /* its output pairs */
+    uint64_t pool_in_use;       /* pool bytes reserved just after its admission */
+    uint32_t rejected;          /* 1: its output alone is larger than the whole pool (nothing written) */
+    uint32_t status;            /* SPHIDX_OK, or the error of one of its launches */
+} sphidx_batch_result;
+
+/* lat, tab: the lattice and tables every batch queries (kept by the caller
+ * for the server's life; tab NULL for a cube-only launch).  slots >= 1,
+ * max_batch >= 1, pool_bytes: the output pool (ids only), stash_pairs: the
+ * stash per slot (0: none).  launch: the launch of every pass (NULL:
+ * defaults; its statistics, method and event outputs are ignored).  Errors:
+ * INVALID_ARG (null lattice or out, zero sizes, a pool under 256 bytes, a
+ * launch that sphidx_count would refuse, e.g. null tables with a method
+ * other than CUBE), SPHIDX_ERR_OUT_OF_MEMORY (device or pinned allocation
+ * failed), DEVICE. */
+sphidx_status sphidx_server_create(const sphidx_lattice* lat, const sphidx_tables* tab, uint32_t slots,
+                                   uint32_t max_batch, size_t pool_bytes, uint64_t stash_pairs,
+                                   const sphidx_launch* launch, sphidx_server** out);
+void sphidx_server_destroy(sphidx_server* s);
+/* Replay nbatch batches (sorted by arrival_s; INVALID_ARG otherwise, or for a
+ * batch above max_batch or with a null input array) and fill results[i] for
+ * batch i.  Returns the first launch error (later batches are not started)
+ * or SPHIDX_OK; the lattice's status word collects device-side flags as for
+ * any query. */
+sphidx_status sphidx_server_run(sphidx_server* s, uint32_t nbatch, const sphidx_batch* batches,
+                                sphidx_batch_result* results);
+
 /* ---------------------------------------------------------------------- */
 
 const char* sphidx_status_string(sphidx_status s);

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsphidx.so")
-SOURCES = ["api.cpp", "tables.cpp", "census.cpp", "lattice.hip", "query.hip", "timestep.hip", "noalloc.hip"]
+SOURCES = ["api.cpp", "tables.cpp", "census.cpp", "lattice.hip", "query.hip", "timestep.hip", "noalloc.hip", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

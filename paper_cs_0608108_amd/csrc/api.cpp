@@ -388,6 +388,20 @@ sphidx_status run_pass(int pass, const sphidx_lattice* lat, const sphidx_tables*
 
 }  // namespace
 
+sphidx_status check_launch(const sphidx_launch* launch, const sphidx_tables* tab) {
+    Launch ln{};
+    return resolve_launch(launch, tab, ln);
+}
+
+void forget_stream(void* stream) {
+    std::lock_guard<std::mutex> lk(g_touch_mu);
+    g_touched.erase(std::remove_if(g_touched.begin(), g_touched.end(),
+                                   [stream](const std::pair<void*, const sphidx_lattice*>& t) {
+                                       return t.first == stream;
+                                   }),
+                    g_touched.end());
+}
+
 extern "C" {
 
 size_t sphidx_lattice_workspace_bytes(const sphidx_lattice_desc* desc, uint32_t max_points) {

@@ -221,3 +221,9 @@ hipError_t launch_count_checksum(const int64_t* row_ptr, uint32_t Q, uint64_t* o
 int device_cu_count();
 size_t query_lds_bytes(int pass, uint32_t cap, uint32_t waves, size_t table_bytes);
 size_t long_lds_bytes(uint32_t waves);
+// Drop a stream from the record of streams that touched a lattice (called
+// before the stream is destroyed).
+void forget_stream(void* stream);
+// The checks every query call makes of a launch descriptor (with these
+// tables), without launching anything.
+sphidx_status check_launch(const sphidx_launch* launch, const sphidx_tables* tab);

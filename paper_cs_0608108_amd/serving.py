@@ -13,10 +13,14 @@ priority), so their kernels overlap on the device:
     done    record the latency (completion - arrival), release the slot and
             the pool range (after handing the result to the caller)
 
-`MemoryPool` and `Admission` are plain host logic (no GPU), so their
-invariants are tested without a device.  `one_launch_per_batch` is the
-baseline: one stream, each batch counted, sized and written before the next
-one starts.
+The loop runs in the library (sphidx_server_*, driven here by
+`run_on_server`); with one slot and the plain schedule the same loop is one
+launch per batch: count, size, write, then the next batch.
+`run_admission_model` is the same policy in Python over an abstract
+executor, so the policy's invariants (slots, first-fit pool, arrival-order
+admission, rejection) are tested without a device.  `one_launch_per_batch`
+runs each batch alone through the plain query calls (a check of the
+server's rows).
 """
 from __future__ import annotations
 
@@ -178,92 +182,20 @@ def run_admission_model(batches, executor, slots, pool_bytes, keep=False, clock=
     return adm
 
 
-class GpuExecutor:
-    """Runs batches on the device: one stream, workspace and input buffers per slot."""
-
-    def __init__(self, lat, tab, slots, max_batch, pool_bytes, launch=None, stash_pairs=1 << 25):
-        import torch
-
-        from . import sphidx
-        self.sx, self.torch = sphidx, torch
-        self.lat, self.tab = lat, tab
-        self.launch = launch or sphidx.LaunchConfig()
-        self.pool = torch.empty(int(pool_bytes) + ALIGN, dtype=torch.uint8, device="cuda")
-        self.pool_base = self.pool.data_ptr() + ((-self.pool.data_ptr()) % ALIGN)
-        self.free_slots = list(range(slots))
-        self.slot = []
-        for _ in range(slots):
-            s = dict(stream=torch.cuda.Stream(),
-                     buf=sphidx.QueryBuffers(max_batch, 0, want_dist2=False, stash_pairs=stash_pairs),
-                     inp=torch.empty((5, max_batch), dtype=torch.int32, device="cuda"),
-                     host=torch.empty((5, max_batch), dtype=torch.int32, pin_memory=True),
-                     total=torch.empty(1, dtype=torch.int64, pin_memory=True))
-            self.slot.append(s)
-
-    def output_bytes(self, pairs):
-        return 4 * max(pairs, 1)
-
-    def start(self, b):
-        sx, torch = self.sx, self.torch
-        si = self.free_slots.pop()
-        s = self.slot[si]
-        n = b.size
-        h = s["host"].numpy().view(np.uint32)
-        for a in range(3):
-            h[a, :n] = b.centres[a]
-        h[3, :n] = b.radius
-        h[4, :n] = b.k
-        with torch.cuda.stream(s["stream"]):
-            s["inp"][:, :n].copy_(s["host"][:, :n], non_blocking=True)
-            inp = s["inp"]
-            q = sx.make_queries(n, (inp[0], inp[1], inp[2]), inp[3], inp[4], sx.MODE_MIXED)
-            buf = s["buf"]
-            cs = buf.c()
-            cs.capacity = 0
-            sx.check(sx.load().sphidx_count(self.lat.handle, self.tab.handle, sx.ctypes.byref(q),
-                                            sx.ctypes.byref(cs), sx.ctypes.byref(self.launch.c()),
-                                            sx._stream(s["stream"])), "count")
-            s["total"].copy_(buf.row_ptr[n:n + 1], non_blocking=True)
-            ev = torch.cuda.Event()
-            ev.record(s["stream"])
-        return dict(si=si, q=q, n=n, ev=ev, done=None)
-
-    def counted(self, tok):
-        if not tok["ev"].query():
-            return None
-        return int(self.slot[tok["si"]]["total"][0])
-
-    def write(self, tok, res):
-        sx, torch = self.sx, self.torch
-        s = self.slot[tok["si"]]
-        off, nb = res
-        cs = s["buf"].c()
-        cs.ids_dev = self.pool_base + off
-        cs.dist2_dev = None
-        cs.capacity = nb // 4
-        with torch.cuda.stream(s["stream"]):
-            sx.check(sx.load().sphidx_write(self.lat.handle, self.tab.handle, sx.ctypes.byref(tok["q"]),
-                                            sx.ctypes.byref(cs), sx.ctypes.byref(self.launch.c()),
-                                            sx._stream(s["stream"])), "write")
-            ev = torch.cuda.Event()
-            ev.record(s["stream"])
-        tok["done"] = ev
-        tok["res"] = res
-
-    def done(self, tok):
-        return tok["done"].query()
-
-    def collect(self, tok):
-        s = self.slot[tok["si"]]
-        n = tok["n"]
-        rp = s["buf"].row_ptr[: n + 1].cpu().numpy()
-        off, nb = tok["res"]
-        tot = int(rp[-1])
-        ids = self.pool[off + ((-self.pool.data_ptr()) % ALIGN):][: 4 * tot].view(self.torch.int32)
-        return rp, ids.cpu().numpy().view(np.uint32)
-
-    def release(self, tok):
-        self.free_slots.append(tok["si"])
+def run_on_server(server, batches, keep=False):
+    """Replay `batches` (Batch objects) on a library server (sphidx.Server):
+    the loop above, in native code, on the GPU.  Fills each batch's start
+    and completion times, pairs and rejection (and result with keep).
+    Returns the peak pool bytes reserved at once."""
+    order = sorted(batches, key=lambda b: b.arrival)
+    res, rows = server.run([b.arrival for b in order], [b.centres for b in order], [b.radius for b in order],
+                           [b.k for b in order], keep=keep)
+    for i, b in enumerate(order):
+        b.t_start, b.t_done = float(res["start_s"][i]), float(res["done_s"][i])
+        b.pairs, b.rejected = int(res["pairs"][i]), bool(res["rejected"][i])
+        if keep:
+            b.result = rows[i]
+    return int(res["pool_in_use"].max()) if len(order) else 0
 
 
 def one_launch_per_batch(batches, lat, tab, launch=None, keep=False):

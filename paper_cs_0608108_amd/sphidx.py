@@ -60,6 +60,16 @@ class LaunchDesc(ctypes.Structure):
                 ("select_model", U32), ("method_dev", P), ("long_row_waves", U32)]
 
 
+
+class BatchDesc(ctypes.Structure):
+    _fields_ = [("count", U32), ("x", P), ("y", P), ("z", P), ("radius_fx", P), ("k", P),
+                ("arrival_s", ctypes.c_double), ("row_ptr_out", P), ("ids_out", P), ("ids_capacity", U64)]
+
+
+class BatchResult(ctypes.Structure):
+    _fields_ = [("start_s", ctypes.c_double), ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double),
+                ("pairs", I64), ("pool_in_use", U64), ("rejected", U32), ("status", U32)]
+
 # Every symbol include/sphidx.h declares, with its ctypes signature.
 SIGNATURES = {
     "sphidx_lattice_workspace_bytes": (SZ, [ctypes.POINTER(LatticeDesc), U32]),
@@ -103,6 +113,10 @@ SIGNATURES = {
     "sphidx_move_incremental": (ctypes.c_int, [P, U64, U32, P, P, ctypes.c_size_t, P]),
     "sphidx_lattice_positions": (ctypes.c_int, [P, P, P, P, P]),
     "sphidx_count_checksum": (ctypes.c_int, [P, U32, P, P]),
+    "sphidx_server_create": (ctypes.c_int, [P, P, U32, U32, SZ, U64, ctypes.POINTER(LaunchDesc),
+                                             ctypes.POINTER(P)]),
+    "sphidx_server_destroy": (None, [P]),
+    "sphidx_server_run": (ctypes.c_int, [P, U32, ctypes.POINTER(BatchDesc), ctypes.POINTER(BatchResult)]),
     "sphidx_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sphidx_version": (ctypes.c_char_p, []),
 }
@@ -538,3 +552,76 @@ def count_checksum(row_ptr, Q, out, stream=None):
 
 def version() -> str:
     return load().sphidx_version().decode()
+
+
+class Server:
+    """A serving loop in the library (sphidx_server_*): `slots` batches in
+    flight on their own streams, an output pool of `pool_bytes` admitted by
+    memory in arrival order.  The lattice must be built and its stream
+    synchronised before `run`."""
+
+    def __init__(self, lat, tab, slots, max_batch, pool_bytes, stash_pairs=0, launch: LaunchConfig | None = None):
+        self.lat, self.tab = lat, tab  # kept alive for the server's life
+        self.max_batch = int(max_batch)
+        self.handle = None
+        h = P()
+        ln = launch.c() if launch is not None else None
+        check(load().sphidx_server_create(lat.handle, tab.handle if tab else None, int(slots), self.max_batch,
+                                          int(pool_bytes), int(stash_pairs),
+                                          ctypes.byref(ln) if ln is not None else None, ctypes.byref(h)),
+              "server_create")
+        self.handle = h.value
+
+    def close(self):
+        if self.handle:
+            load().sphidx_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, arrivals, centres, radius, k, keep=False):
+        """Replay batches: arrivals[i] (seconds, non-decreasing), centres[i]
+        = (x, y, z) host uint32 arrays, radius[i], k[i] host uint32 arrays
+        (k[i] None: radius queries only).  Returns the per-batch results
+        (structured numpy array) and, with keep, each batch's (row_ptr, ids)
+        on the host (None for a rejected batch)."""
+        n = len(arrivals)
+        descs = (BatchDesc * max(n, 1))()
+        res = (BatchResult * max(n, 1))()
+        hold, outs = [], []
+        for i in range(n):
+            x, y, z = (np.ascontiguousarray(a, dtype=np.uint32) for a in centres[i])
+            r = np.ascontiguousarray(radius[i], dtype=np.uint32)
+            kk = None if k[i] is None else np.ascontiguousarray(k[i], dtype=np.uint32)
+            hold.append((x, y, z, r, kk))
+            d = descs[i]
+            d.count = len(r)
+            d.x, d.y, d.z, d.radius_fx = x.ctypes.data, y.ctypes.data, z.ctypes.data, r.ctypes.data
+            d.k = None if kk is None else kk.ctypes.data
+            d.arrival_s = float(arrivals[i])
+            if keep:
+                rp = np.empty(len(r) + 1, dtype=np.int64)
+                outs.append([rp, None])
+                d.row_ptr_out = rp.ctypes.data
+        if keep:
+            # sizes first: the ids copies need each batch's total
+            code = load().sphidx_server_run(self.handle, n, descs, res)
+            check(code, "server_run")
+            for i in range(n):
+                tot = int(res[i].pairs)
+                ids = np.empty(max(tot, 1), dtype=np.uint32)
+                outs[i][1] = ids
+                descs[i].ids_out = ids.ctypes.data
+                descs[i].ids_capacity = tot
+        code = load().sphidx_server_run(self.handle, n, descs, res)
+        check(code, "server_run")
+        out = np.ctypeslib.as_array(res)[:n].copy()
+        if not keep:
+            return out, None
+        rows = [None if out["rejected"][i] else (outs[i][0], outs[i][1][: int(out["pairs"][i])]) for i in range(n)]
+        return out, rows
+

@@ -20,6 +20,8 @@ STRUCTS = {
     "sphidx_queries": sphidx.Queries,
     "sphidx_csr": sphidx.CSRDesc,
     "sphidx_launch": sphidx.LaunchDesc,
+    "sphidx_batch": sphidx.BatchDesc,
+    "sphidx_batch_result": sphidx.BatchResult,
 }
 
 

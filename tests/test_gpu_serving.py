@@ -1,6 +1,6 @@
-"""Serving loop on the GPU: batches that overlap on several streams, admitted
-by slots and output memory, give the same rows as each batch run alone and
-as the oracle (mixed radius / K-NN rows, bit for bit)."""
+"""The library's serving loop on the GPU: batches that overlap on several
+streams, admitted by slots and output memory, give the same rows as each
+batch run alone and as the oracle (mixed radius / K-NN rows, bit for bit)."""
 import numpy as np
 import pytest
 
@@ -25,8 +25,13 @@ def _rows_equal(a, b, what):
     assert np.array_equal(np.asarray(ids_a)[: int(rp_a[-1])], np.asarray(ids_b)[: int(rp_b[-1])]), what + ": ids"
 
 
-@pytest.mark.parametrize("slots,pool_mb", [(3, 64), (4, 1)])
-def test_batches_in_the_mix_equal_alone_and_oracle(sx, orc, slots, pool_mb):
+@pytest.mark.parametrize("slots,pool_mb,plain,spacing_ms", [(3, 64, False, 0.0), (4, 1, False, 0.0),
+                                                          (1, 64, True, 0.0), (2, 64, False, 0.3)])
+def test_batches_in_the_mix_equal_alone_and_oracle(sx, orc, slots, pool_mb, plain, spacing_ms):
+    """The library's serving loop: batches on `slots` streams (or one slot
+    with the plain schedule: one launch per batch), admitted by a pool of
+    `pool_mb` MB, arriving together or `spacing_ms` apart; an empty batch
+    among them."""
     from paper_cs_0608108_amd import serving, synth
     spec = synth.LatticeSpec((6, 6, 6), 16, 7)
     n = 150000
@@ -35,27 +40,72 @@ def test_batches_in_the_mix_equal_alone_and_oracle(sx, orc, slots, pool_mb):
     dev = [sx.to_dev_u32(a) for a in pts]
     lat.build(*dev)
     tab = sx.Tables(lat, 2, 4 * spec.edge)
-    sizes = synth.serving_batch_sizes(21, 14, 2048)
+    sizes = [int(s) for s in synth.serving_batch_sizes(21, 14, 2048)]
+    sizes.insert(5, 0)
     batches = []
     for i, s in enumerate(sizes):
-        q, r, k = synth.serving_batch(spec, 21, i, int(s), rmin_k=64, rmax_k=256, knn_cap_cells=4)
-        batches.append(serving.Batch(i, 0.0, q, r, k))
-    say(f"serving slots={slots} pool={pool_mb} MB sizes={list(map(int, sizes))}")
-    ex = serving.GpuExecutor(lat, tab, slots, int(max(sizes)), pool_mb << 20)
-    serving.run_admission_model(batches, ex, slots, pool_mb << 20, keep=True)
+        q, r, k = synth.serving_batch(spec, 21, i, s, rmin_k=64, rmax_k=256, knn_cap_cells=4)
+        batches.append(serving.Batch(i, i * spacing_ms * 1e-3, q, r, k))
+    say(f"serving slots={slots} pool={pool_mb} MB plain={plain} spacing={spacing_ms} ms sizes={sizes}")
+    import torch
+    torch.cuda.synchronize()
+    ln = sx.LaunchConfig(schedule=sx.SCHED_PLAIN) if plain else sx.LaunchConfig()
+    server = sx.Server(lat, tab, slots, max(sizes), pool_mb << 20, stash_pairs=1 << 20, launch=ln)
+    peak = serving.run_on_server(server, batches, keep=True)
+    assert 0 < peak <= pool_mb << 20
     L = orc.Lattice(spec.log2_cells, spec.frac_bits, spec.cyclic_mask)
     g = orc.Grid(L, pts)
-    alone = [serving.Batch(b.index, 0.0, b.centres, b.radius, b.k) for b in batches]
+    alone = [serving.Batch(b.index, 0.0, b.centres, b.radius, b.k) for b in batches if b.size]
     serving.one_launch_per_batch(alone, lat, tab, keep=True)
-    for b, a in zip(batches, alone):
+    alone = {a.index: a for a in alone}
+    for b in batches:
+        assert b.t_start >= b.arrival and b.t_done >= b.t_start, b.index
+        if b.size == 0:
+            assert not b.rejected and b.pairs == 0
+            assert np.array_equal(b.result[0], [0]) and len(b.result[1]) == 0
+            continue
         ref = g.mixed(b.k, b.radius, queries=b.centres)
+        assert b.pairs == int(ref.row_ptr[-1]), b.index
         if b.rejected:
             assert 4 * int(ref.row_ptr[-1]) > (pool_mb << 20), b.index
+            assert b.result is None
             continue
         _rows_equal(b.result, (ref.row_ptr, ref.ids), f"batch {b.index} in the mix vs oracle")
-        _rows_equal(a.result[:2], (ref.row_ptr, ref.ids), f"batch {b.index} alone vs oracle")
+        _rows_equal(alone[b.index].result[:2], (ref.row_ptr, ref.ids), f"batch {b.index} alone vs oracle")
     g.close()
     assert sum(not b.rejected for b in batches) >= len(batches) - 2
+    code, flags = lat.status()
+    assert code == sx.OK and not (flags & sx.FLAG_CAPACITY), (code, flags)
+    server.close()
+
+
+def test_server_refuses_what_it_cannot_serve(sx):
+    """A batch above max_batch or out of arrival order is refused before
+    anything starts; a run after the refusal serves normally."""
+    import torch
+
+    from paper_cs_0608108_amd import serving, synth
+    spec = synth.LatticeSpec((5, 5, 5), 16, 7)
+    pts = synth.uniform_points(spec, 20000, 3)
+    lat = sx.Lattice(spec.log2_cells, spec.frac_bits, spec.cyclic_mask, 20000)
+    dev = [sx.to_dev_u32(a) for a in pts]
+    lat.build(*dev)
+    tab = sx.Tables(lat, 2, 4 * spec.edge)
+    torch.cuda.synchronize()
+    server = sx.Server(lat, tab, 2, 100, 1 << 20)
+    q, r, k = synth.serving_batch(spec, 3, 0, 101, rmin_k=64, rmax_k=128, knn_cap_cells=2)
+    with pytest.raises(sx.SphidxError):
+        serving.run_on_server(server, [serving.Batch(0, 0.0, q, r, k)])
+    q2, r2, k2 = synth.serving_batch(spec, 3, 1, 50, rmin_k=64, rmax_k=128, knn_cap_cells=2)
+    with pytest.raises(sx.SphidxError):
+        server.run([0.2, 0.1], [q2, q2], [r2, r2], [k2, k2])
+    bs = [serving.Batch(0, 0.0, q2, r2, k2)]
+    serving.run_on_server(server, bs, keep=True)
+    dq = tuple(sx.to_dev_u32(c) for c in q2)  # held: the query descriptor keeps raw pointers
+    dr, dk = sx.to_dev_u32(r2), sx.to_dev_u32(k2)
+    ref = sx.run(lat, tab, sx.make_queries(50, dq, dr, dk, sx.MODE_MIXED), want_dist2=False)
+    _rows_equal(bs[0].result, ref[:2], "after a refused run")
+    server.close()
 
 
 def test_full_size_serving_lattice_mixed_batches(sx, orc):
@@ -63,7 +113,7 @@ def test_full_size_serving_lattice_mixed_batches(sx, orc):
     cyclic 512^3 lattice, tables to 16 cells, batches of the serving mix
     (radius 1-16 cells, K from {1, 8, 32, 128} with the 16-cell cap), among
     them radius-16-cell queries and K = 128 queries, run through the
-    continuous-batching executor with 3 slots; every row against the
+    library's serving loop with 3 slots; every row against the
     oracle."""
     import torch
 
@@ -88,9 +138,9 @@ def test_full_size_serving_lattice_mixed_batches(sx, orc):
     nr16 = sum(int(((b.radius == 16 * spec.edge) & (b.k == 0)).sum()) for b in batches)
     nk128 = sum(int((b.k == 128).sum()) for b in batches)
     assert nr16 >= 40 and nk128 >= 40
-    ex = serving.GpuExecutor(lat, tab, 3, max(sizes), 256 << 20)
-    serving.run_admission_model(batches, ex, 3, 256 << 20, keep=True)
     torch.cuda.synchronize()
+    server = sx.Server(lat, tab, 3, max(sizes), 256 << 20, stash_pairs=1 << 22)
+    serving.run_on_server(server, batches, keep=True)
     code, flags = lat.status()
     assert code == sx.OK and not (flags & sx.FLAG_CAPACITY), (code, flags)
     say("serving lattice oracle grid")
@@ -100,5 +150,6 @@ def test_full_size_serving_lattice_mixed_batches(sx, orc):
         ref = g.mixed(b.k, b.radius, queries=b.centres)
         _rows_equal(b.result, (ref.row_ptr, ref.ids), f"full-size batch {b.index} ({b.size} queries)")
     g.close()
-    del ex, lat, tab, dev
+    server.close()
+    del server, lat, tab, dev
     torch.cuda.empty_cache()

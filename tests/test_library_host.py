@@ -242,6 +242,39 @@ def test_build_validation(sx):
     lib.sphidx_lattice_destroy(lat)
 
 
+def test_server_validation(sx):
+    """The serving loop's argument checks return before any allocation or launch."""
+    lib = sx.load()
+    lat = _fake_lattice(sx)
+    out = ctypes.c_void_p(1)
+    ln = sx.LaunchDesc()
+    ln.method = sx.METHOD_CUBE
+    ok = dict(slots=2, max_batch=16, pool=1 << 20, stash=0)
+
+    def create(lat_=lat, tab=None, launch=ln, **kw):
+        a = dict(ok, **kw)
+        return lib.sphidx_server_create(lat_, tab, a["slots"], a["max_batch"], a["pool"], a["stash"],
+                                        ctypes.byref(launch) if launch is not None else None, ctypes.byref(out))
+
+    assert create(lat_=None) == sx.ERR_INVALID_ARG
+    assert out.value is None  # cleared on every error
+    assert create(slots=0) == sx.ERR_INVALID_ARG
+    assert create(max_batch=0) == sx.ERR_INVALID_ARG
+    assert create(pool=255) == sx.ERR_INVALID_ARG
+    assert create(launch=None) == sx.ERR_INVALID_ARG  # the default walk needs tables
+    for field, val in [("schedule", 5), ("waves_per_block", 3), ("sort_cap", 100), ("method", 9)]:
+        old = getattr(ln, field)
+        setattr(ln, field, val)
+        assert create() == sx.ERR_INVALID_ARG, field
+        setattr(ln, field, old)
+    assert lib.sphidx_server_create(lat, None, 1, 1, 1 << 20, 0, ctypes.byref(ln), None) == sx.ERR_INVALID_ARG
+    res = (sx.BatchResult * 1)()
+    bd = (sx.BatchDesc * 1)()
+    assert lib.sphidx_server_run(None, 1, bd, res) == sx.ERR_INVALID_ARG
+    lib.sphidx_server_destroy(None)
+    lib.sphidx_lattice_destroy(lat)
+
+
 def test_status_strings(sx):
     lib = sx.load()
     names = {lib.sphidx_status_string(c).decode() for c in range(8)}
