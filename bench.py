@@ -6,8 +6,10 @@ moving agents uniform at the start in a cyclic 256^3 lattice (cell edge
 2^16 fixed-point units), radius 3 cells.  One step is the whole hot path on
 that input, captured once as a HIP graph and replayed:
 
-    move every agent (counter-hash displacement in [-1/4, 1/4] cell per axis)
-    lattice rebuild (cell histogram, exclusive scan, scatter)
+    move every agent (counter-hash displacement in [-1/4, 1/4] cell per axis,
+        applied to the lattice's own records, keyed by agent id)
+    lattice rebuild from those records (cell histogram, exclusive scan,
+        scatter)
     count pass (sphere-table walk, rows sorted and kept) + scan -> row_ptr
     write pass (kept rows copied into place) + neighbour-count checksum
 
@@ -16,7 +18,8 @@ with inputs resident in HBM and the sphere tables built once beforehand
 timed between device synchronisations after `--warmup W`; the run then
 continues to the workload's 100 steps and checks positions, the
 neighbour-count checksum over all rows and sampled rows against the CPU
-oracle's replay.  The bin-lattice cube scan, the plain launch and the
+oracle's replay.  The bin-lattice cube scan, the plain launch, the step
+that moves by-id coordinate arrays and rebuilds from them, and the
 incremental lattice update run the same steps beside it.
 
 Further workloads, each under its own key of the same JSON line with its
@@ -99,17 +102,13 @@ def query_bytes(n, ncells, Q, pairs, dist2=False):
     return 16 * n + 4 * (ncells + 2) + 8 * (Q + 1) + (12 if dist2 else 4) * pairs
 
 
-def rebuild_bytes(n, ncells):
-    """Counting sort: coordinates read by the histogram and the scatter
-    (12 + 12 B), the record written (16 B); counts zeroed, incremented,
-    scanned (read + write) and read as cursors (4 + 4 + 8 + 4 B per cell)."""
-    return n * (12 + 12 + 16) + ncells * (4 + 4 + 8 + 4)
-
-
-def move_bytes(n):
-    """Coordinates read and written once (12 + 12 B) plus the step counter's
-    share, rounded to the survey's 28 B per agent (16 B read + 12 B write)."""
-    return 28 * n
+def resident_update_bytes(n, ncells):
+    """The lattice kept from its own records: the move reads and writes every
+    record (16 + 16 B); the rebuild reads them in the histogram and the
+    scatter (16 + 16 B) and writes them (16 B); the counts are zeroed,
+    incremented, scanned (read + write) and read as cursors (4 + 4 + 8 + 4 B
+    per cell)."""
+    return {"move": 32 * n, "rebuild": n * (16 + 16 + 16) + ncells * (4 + 4 + 8 + 4)}
 
 
 def overhead_bytes(Q, pairs):
@@ -222,7 +221,10 @@ def leg_timestep(args, out):
     ncells = 1 << sum(spec.log2_cells)
     K = args.steps
     log(f"workload {w.name}: n={n} r={r}")
-    sim = timestep.AgentSim(spec.log2_cells, spec.frac_bits, spec.cyclic_mask, w.pts, r, seed)
+    # the lattice is kept from its own records (moved in place, rebuilt from
+    # them); the step that moves by-id coordinate arrays and rebuilds from
+    # them is timed beside it
+    sim = timestep.AgentSim(spec.log2_cells, spec.frac_bits, spec.cyclic_mask, w.pts, r, seed, resident=True)
     shape = dict(workload=w.name, n=n)
 
     def query_step(ln):
@@ -288,10 +290,10 @@ def leg_timestep(args, out):
     log(f"timestep: {ms:.3f} ms/step (wall {wall:.3f}), count kernel {kern_ms:.3f} ms, pairs {pairs}, "
         f"status {code}/{flags}")
 
-    # the same steps with the bin-lattice cube scan, the plain launch and the
-    # incremental lattice update; each runs to the same final step and is
-    # compared with the path above
-    def other(tag, launch, resident=False, incremental=False):
+    # the same steps with the bin-lattice cube scan, the plain launch, the
+    # by-id rebuild and the incremental lattice update; each runs to the same
+    # final step and is compared with the path above
+    def other(tag, launch, resident=True, incremental=False):
         o = timestep.AgentSim(spec.log2_cells, spec.frac_bits, spec.cyclic_mask, w.pts, r, seed, launch=launch,
                               resident=resident, incremental=incremental, subcell_bits=sbits)
         o.step()
@@ -360,10 +362,10 @@ def leg_timestep(args, out):
         base["paper64"] = other("paper64", sphidx.LaunchConfig(method=sphidx.METHOD_PAPER64))
         base["paper64"]["step"] = ("the same step with the paper's 64 specialised cell tables and the Eq. 1 "
                                    "run-time test (one query per wavefront)")
-        base["resident"] = other("resident", sim.launch, resident=True)
-        base["resident"]["step"] = ("move the lattice's records + rebuild the lattice from them + count + scan + "
-                                    "write + checksum, one graph replay")
-        base["incremental"] = other("incremental", sim.launch, incremental=True)
+        base["rebuild_by_id"] = other("rebuild by id", sim.launch, resident=False)
+        base["rebuild_by_id"]["step"] = ("move the by-id coordinate arrays + counting-sort rebuild from them + "
+                                         "count + scan + write + checksum, one graph replay")
+        base["incremental"] = other("incremental", sim.launch, resident=False, incremental=True)
         base["incremental"]["step"] = ("move the lattice's records + place again only the agents that changed "
                                        "cell (stayers keep their order) + count + scan + write + checksum")
         base["maintenance_ms"] = maintenance_times()
@@ -417,13 +419,14 @@ def leg_timestep(args, out):
         log(f"cpu oracle: {cpu['value']:.0f} agent-queries/s on {cpu['cores']} threads")
 
     alg = query_bytes(n, ncells, n, pairs)
-    step_alg = move_bytes(n) + rebuild_bytes(n, ncells) + alg
+    upd = resident_update_bytes(n, ncells)
+    step_alg = upd["move"] + upd["rebuild"] + alg
     rl = roofline(w.name, ("group_count_kernel" if cfg.get("grouped") else "count_kernel")
                   + " (walk, test, sort, keep rows)", alg, kern_ms, out.get("hbm_copy_GBps"),
                   {"step": {"algorithmic_bytes": int(step_alg), "ms": round(ms, 4),
                             "achieved": round(step_alg / (ms * 1e-3) / 1e9, 2),
                             "frac": round(step_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
-                            "bytes": {"move": move_bytes(n), "rebuild": rebuild_bytes(n, ncells), "query": alg}},
+                            "bytes": {**upd, "query": alg}},
                    "library_overhead_bytes": overhead_bytes(n, pairs)})
     out.update({
         "metric": METRIC,
@@ -432,7 +435,8 @@ def leg_timestep(args, out):
         "ms_per_step": round(ms, 4),
         "config": {"workload": w.name, "agents": n, "lattice": "256^3 cyclic, cell edge 2^16 units",
                    "radius": "3 cells", "steps": 100,
-                   "step": "move + rebuild + count + scan + write + checksum, one graph replay",
+                   "step": "move the lattice's records + rebuild it from them + count + scan + write + "
+                           "checksum, one graph replay",
                    "subcell_bits": sbits, "launch": dict(cfg, schedule="persistent")},
         "pairs_per_step": pairs,
         "pairs_per_s": round(pairs / (ms * 1e-3), 1),
