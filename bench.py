@@ -688,6 +688,22 @@ def leg_c2(args, out):
                           "same_result": bool(np.array_equal(rp_p, rp) and np.array_equal(ids_p, ids))}
         log(f"paper64: {ms_p64:.3f} ms/step (count kernel {k_p64[0]:.3f}); row tables one query per wave "
             f"{ms_one:.3f} (count kernel {k_one[0]:.3f}); same {res['paper64']['same_result']}")
+        # the row table staged in LDS, whole and in per-class chunks, against
+        # the tuned launch that reads it from device memory
+        lds = {"table_bytes": int(tab.info().total_entries) * 16, "device_memory_ms_per_step": round(ms, 4),
+               "device_memory_count_kernel_ms": round(float(kern[0]), 4)}
+        for mode, tag in ((1, "whole"), (2, "chunked")):
+            try:
+                ms_l, _, k_l = timed(dataclasses.replace(tuned, table_in_lds=mode), k2, 1)
+            except sphidx.SphidxError as e:
+                lds[tag] = {"refused": str(e)}
+                continue
+            rp_l = buf.row_ptr.cpu().numpy()
+            ids_l = buf.ids[: int(rp_l[-1])].cpu().numpy().view(np.uint32)
+            lds[tag] = {"ms_per_step": round(ms_l, 4), "count_kernel_ms": round(float(k_l[0]), 4),
+                        "same_result": bool(np.array_equal(rp_l, rp) and np.array_equal(ids_l, ids))}
+        res["table_in_lds"] = lds
+        log(f"row table in LDS: {lds}")
         # the per-query choice (Section III.B/C) with the tuned launch, by
         # cells (the paper's volumes) and by estimated lane work; the
         # non-empty cell list is kept (and rebuilt) only here

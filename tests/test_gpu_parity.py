@@ -201,6 +201,30 @@ def test_radius_uniform_cyclic_32_full_vs_brute_force(sx, orc):
         assert_same(run(sx, lat, tab, int(w.r_fx[0])), ref, "uniform 4,096 points, scalar radius")
 
 
+def test_tables_loaded_from_file_answer_queries(sx, orc, tmp_path):
+    """Tables written to a file and read back (their row tables rebuilt at
+    load) give the same rows as the oracle, with the table in device memory
+    and staged in LDS, on a clipped and a cyclic world with uneven radii."""
+    from paper_cs_0608108_amd import synth
+    rng = np.random.default_rng(2029)
+    for mask in (0, 7):
+        lat_s = synth.LatticeSpec((4, 4, 4), 10, mask)
+        pts = synth.uniform_points(lat_s, 3000, 71 + mask)
+        r = rng.integers(lat_s.edge // 2, 3 * lat_s.edge, size=3000, dtype=np.uint32)
+        say("loaded tables, mask", mask)
+        L = orc.Lattice(lat_s.log2_cells, lat_s.frac_bits, mask)
+        ref = orc.radius_brute(L, pts, r)
+        lat = lattice(sx, lat_s.log2_cells, lat_s.frac_bits, mask, pts)
+        path = tmp_path / f"tables_{mask}.bin"
+        sx.Tables(lat, 1, int(2.5 * lat_s.edge)).save(path)  # radii above the cap fall back to the cube
+        tab = sx.Tables.load_file(path)
+        assert tab.info().total_entries * 16 <= 60000, "the LDS launch needs the whole table in LDS"
+        for name in ("sphere-persistent", "sphere-grouped", "sphere-lds-table"):
+            assert_same(run(sx, lat, tab, r, launch=_launches(sx)[name]), ref, f"loaded tables {name} mask {mask}")
+        assert_same(run(sx, lat, tab, r, launch=_launches(sx)["sphere-grouped"], stash=True), ref,
+                    f"loaded tables grouped stash mask {mask}")
+
+
 def test_radius_uneven_clipped_full_size(sx, orc):
     from paper_cs_0608108_amd import synth
     w = synth.radius_uneven_clipped()
