@@ -1411,7 +1411,7 @@ __global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs 
                     if (lane == 0) A.walkq[atomicAdd(A.walk_count, 1u)] = qi;
                 }
             }
-            if (lane == 0) A.soff[qi] = off;
+            if (lane == 0) A.soff[s.row] = off;
             return;
         }
         uint32_t hits = 0, inner = 0, kept = 0, cand = 0, walked = 0;
@@ -1477,7 +1477,7 @@ __global__ __launch_bounds__(256) void count_kernel(LatArgs L, TabArgs T, QArgs 
                     if (lane == 0) A.walkq[atomicAdd(A.walk_count, 1u)] = qi;
                 }
             }
-            if (lane == 0) A.soff[qi] = off;
+            if (lane == 0) A.soff[s.row] = off;
         }
         if (A.stats) {
             const uint32_t kept_all = wave_sum(kept);
@@ -1888,7 +1888,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
             }
             if (invalid) {
                 A.row_ptr[row] = 0;
-                if (STASH) A.soff[qi] = 0u;
+                if (STASH) A.soff[row] = 0u;
             }
             {
                 // the queries left to the one-query-per-wave kernel
@@ -2006,12 +2006,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
                         }
                     }
                     wave_sync();
-                    if (mine) A.soff[qi] = cur + (KNN ? qo0 : qs0);
+                    if (mine) A.soff[row] = cur + (KNN ? qo0 : qs0);
                     cur += tout;
                 } else {
                     // not kept: the write pass walks these rows again
                     const bool walk_again = mine && nq > 0;
-                    if (mine) A.soff[qi] = walk_again ? kMaxId : 0u;
+                    if (mine) A.soff[row] = walk_again ? kMaxId : 0u;
                     const uint64_t wm = __ballot(walk_again);
                     uint32_t wb0 = 0;
                     if (wm != 0 && lane == 0) wb0 = atomicAdd(A.walk_count, (uint32_t)__popcll(wm));
@@ -2055,8 +2055,8 @@ __global__ __launch_bounds__(256) void write_kernel(LatArgs L, TabArgs T, QArgs 
     for_each_query(nq, A, queue_set(A, FROM_LIST ? (int)A.list_set : (from_walk ? kQWalk : kQWrite)),
                    [&](uint32_t ti_) {
         const uint32_t qi = FROM_LIST ? uni(A.list[ti_]) : (from_walk ? uni(A.walkq[ti_]) : ti_);
-        if (FROM_LIST && stashed && uni(A.soff[qi]) != kMaxId) return;  // copied by the gather kernel
         const Query s = load_query(L, A, qi);
+        if (FROM_LIST && stashed && uni(A.soff[s.row]) != kMaxId) return;  // copied by the gather kernel
         if ((METHOD == kSphere || METHOD == kPaper) && (s.flags & F_VALID) && !(s.flags & F_SPHERE))
             return;  // fallback list
         const int64_t rb = A.row_ptr[s.row];
@@ -2396,7 +2396,7 @@ __global__ __launch_bounds__(512) void long_kernel(LatArgs L, TabArgs T, QArgs A
                     }
                     if (off == kMaxId) A.walkq[atomicAdd(A.walk_count, 1u)] = qi;
                 }
-                A.soff[qi] = off;
+                A.soff[s.row] = off;
                 ctl[2] = off;
             }
             __syncthreads();
@@ -2429,14 +2429,19 @@ __global__ void clear_counters_kernel(uint32_t* c, uint32_t begin, uint32_t end,
 }
 
 // Pass 1 with the stash: copy each kept row into place.  A wavefront takes 64
-// queries; one lane reads each query's stash offset, output row and length.
-// Their objects are numbered in query order (a prefix sum), and each lane
-// copies every 64th of them: its query is the last whose first number is at
-// most the object's, found by a binary search over the starts kept in LDS
-// (read-only, so steps need no barrier and four are in flight).  Consecutive
-// queries' stash rows are mostly adjacent, so the loads are one stream.  Rows
-// the count pass could not keep are left to the write kernel (offset ~0), as
-// are rows whose dist^2 the stash lacks.
+// consecutive output rows and reads each one's stash offset (kept per output
+// row) and its place from row_ptr.  Their objects are numbered in row order (a
+// prefix sum), and each lane copies every 64th of them: its row is the last
+// whose first number is at most the object's, found by a binary search over
+// the starts kept in LDS (read-only, so steps need no barrier and four are in
+// flight).  The writes are then one sequential stream per wavefront and each
+// stash row is one contiguous read; rows come out of the count pass in lattice
+// order, which is not the output's order for all-agents queries, and writing
+// rows scattered over the output costs more than reading them scattered.
+// Rows the count pass could not keep are left to the write kernel (offset ~0).
+// When the write wants dist^2 and the stash lacks it, every kept row is walked
+// again instead, and the walk list takes query slots: then the wavefront takes
+// 64 consecutive query slots and finds each one's output row.
 __global__ __launch_bounds__(256) void gather_kernel(QArgs A, const uint4* pts, uint32_t* status) {
     __shared__ uint32_t starts_all[4 * 64];
     const uint32_t* hdr = A.stash_hdr;
@@ -2452,24 +2457,26 @@ __global__ __launch_bounds__(256) void gather_kernel(QArgs A, const uint4* pts, 
     const uint32_t* s_ids = (const uint32_t*)A.stash_base;
     const bool has_d2 = hdr[kHdrHasD2] != 0u;
     const int64_t* s_d2 = (const int64_t*)(A.stash_base + hdr[kHdrD2Off] * (size_t)256);
+    // walk again (dist^2 wanted, not stashed): by query slot; else by output row
+    const bool again = A.out_d2 && !has_d2;
     const uint64_t qi = q0 + lane;
     uint32_t len = 0, src = 0;
     int64_t dst = 0;
     if (qi < A.Q) {
-        src = A.soff[qi];
+        // the output row: the object's id for all-agents queries (their
+        // processing order is the sorted order), else the query index
+        const uint32_t row = (again && A.qx == nullptr) ? pts[qi].w : (uint32_t)qi;
+        src = A.soff[row];
         if (src != kMaxId) {
-            // the output row: the object's id for all-agents queries (their
-            // processing order is the sorted order), else the query index
-            const uint32_t row = A.qx == nullptr ? pts[qi].w : (uint32_t)qi;
             dst = A.row_ptr[row];
             len = (uint32_t)(A.row_ptr[row + 1] - dst);
-            if (len > 0 && A.out_d2 && !has_d2) {
+            if (len > 0 && again) {
                 // the stash holds no dist^2 for this row: it is walked again,
                 // by the main write kernel (from the walk list) or, for a row
                 // off the sphere tables, by the list kernels, which walk rows
                 // whose offset says "not kept"; marked so once, a later write
                 // does not list it again
-                A.soff[qi] = kMaxId;
+                A.soff[row] = kMaxId;
                 A.walkq[atomicAdd(A.walk_count, 1u)] = (uint32_t)qi;
                 len = 0;
             }

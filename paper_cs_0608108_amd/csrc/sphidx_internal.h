@@ -136,7 +136,7 @@ struct QArgs {
     uint32_t* xq;       // grouped count: queries left to the one-query-per-wave kernel
     uint32_t* lq_count;
     uint32_t* lq;       // stash mode: radius rows expected to be long, counted one block per row
-    uint32_t* soff;     // stash mode: per query, first stash element of its sorted row
+    uint32_t* soff;     // stash mode: per output row, first stash element of its sorted row
     uint32_t* stash_hdr;  // stash header written by the count pass (see StashHdr)
     uint32_t* stash_ctr;  // NQUEUE per-region allocation counters
     char* stash_base;     // start of the stash area of the workspace
