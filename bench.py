@@ -1296,7 +1296,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs (profiling runs)")
     ap.add_argument("--no-baselines", action="store_true", help="skip the plain-launch and cube-scan legs")
     ap.add_argument("--serving-batches", type=int, default=2000)
-    ap.add_argument("--serving-slots", type=int, default=4)
+    # slots of the continuous serving path: capacity on the serving mix grew
+    # with slots up to about 8 (1: 14.9, 2: 24.6, 4: 31.5, 8: 36.9, 12: 37.3,
+    # 16: 37.1 M queries/s over 1,000 batches), most batches being too small
+    # to fill the GPU alone
+    ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--copy-bytes", type=int, default=0, help="only time a plain device copy of this size")
     args = ap.parse_args()
     if args.gpus != 1:
