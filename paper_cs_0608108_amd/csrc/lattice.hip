@@ -310,13 +310,46 @@ __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(const T* in, T*
     if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = partial[nb];
 }
 
+// Short arrays in one launch: one block takes the chunks of kScanBlock
+// elements in order, carrying the running total (each chunk is read whole
+// before any of it is written, so the scan can be in place).  A query batch
+// of a few thousand rows then costs one launch instead of three.
+constexpr uint32_t kScanSingleChunks = 4;
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void scan_single_kernel(const T* in, T* out, size_t n) {
+    __shared__ T sh[kScanThreads / 64 + 1];
+    T carry = 0;
+    for (size_t c0 = 0; c0 < n; c0 += kScanBlock) {
+        const size_t base = c0 + (size_t)threadIdx.x * kScanItems;
+        T v[kScanItems];
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) v[k] = (base + k < n) ? in[base + k] : (T)0;
+        T s = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) s += v[k];
+        T tot;
+        T off = block_exclusive_scan<T>(s, sh, tot) + carry;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            if (base + k < n) out[base + k] = off;
+            off += v[k];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
 // Exclusive scan of in[0..n) into out[0..n) (in place when in == out);
 // out[n] receives the total.  `partial` needs ceil(n / kScanBlock) + 1
 // elements.
 template <typename T>
 hipError_t scan_exclusive_to(const T* in, T* out, size_t n, T* partial, hipStream_t st) {
     uint32_t nb = (uint32_t)((n + kScanBlock - 1) / kScanBlock);
-    if (nb == 0) nb = 1;
+    if (nb <= kScanSingleChunks) {
+        scan_single_kernel<T><<<1, kScanThreads, 0, st>>>(in, out, n);
+        return hipGetLastError();
+    }
     scan_reduce_kernel<T><<<nb, kScanThreads, 0, st>>>(in, n, partial);
     scan_partials_kernel<T><<<1, kScanThreads, 0, st>>>(partial, nb);
     if ((((uintptr_t)in | (uintptr_t)out) & 15u) == 0)
