@@ -132,7 +132,11 @@ sphidx_status sphidx_lattice_attach_cell_list(sphidx_lattice* lat, void* list_de
  * whole rows.  Applies to sphidx_build_lattice; sphidx_move_resident and
  * sphidx_move_incremental leave cells unordered.  INVALID_ARG for another
  * value.  Host only; the order is made by the next build, and queries narrow
- * rows only while the order set is X and the last build ordered every cell. */
+ * rows only while the order set is X and the last build ordered every cell.
+ * The first call with X allocates a second record array of 16 bytes per
+ * point (max_points), which the build's counting sort fills before the x
+ * ranking writes each record into the lattice; the library owns it and
+ * sphidx_lattice_destroy frees it (OUT_OF_MEMORY when it cannot be had). */
 #define SPHIDX_ORDER_ANY 0u
 #define SPHIDX_ORDER_X 1u
 sphidx_status sphidx_lattice_set_cell_order(sphidx_lattice* lat, uint32_t order);

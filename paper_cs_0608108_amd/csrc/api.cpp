@@ -431,6 +431,7 @@ sphidx_status sphidx_lattice_create(const sphidx_lattice_desc* desc, uint32_t ma
     lat->status = (uint32_t*)(b + ly.status);
     lat->bytes = ly.total;
     lat->cell_order = SPHIDX_ORDER_ANY;
+    lat->xbuf = nullptr;
     (void)hipGetDevice(&lat->device);
     // an empty lattice until the first build: every cell empty, status clear
     // (skipped on a host without a device, where only validation can run)
@@ -448,6 +449,7 @@ sphidx_status sphidx_lattice_create(const sphidx_lattice_desc* desc, uint32_t ma
 void sphidx_lattice_destroy(sphidx_lattice* lat) {
     if (!lat) return;
     forget_lattice(lat);
+    if (lat->xbuf) (void)hipFree(lat->xbuf);
     delete lat;
 }
 
@@ -492,6 +494,12 @@ sphidx_status sphidx_lattice_get_view(const sphidx_lattice* lat, sphidx_lattice_
 
 sphidx_status sphidx_lattice_set_cell_order(sphidx_lattice* lat, uint32_t order) {
     if (!lat || order > SPHIDX_ORDER_X) return SPHIDX_ERR_INVALID_ARG;
+    if (order == SPHIDX_ORDER_X && !lat->xbuf && lat->max_points > 0) {
+        // the counting sort's records, before the x ranking places them
+        void* p = nullptr;
+        if (hipMalloc(&p, (size_t)lat->max_points * sizeof(uint4)) != hipSuccess) return SPHIDX_ERR_OUT_OF_MEMORY;
+        lat->xbuf = (uint4*)p;
+    }
     lat->cell_order = order;
     return SPHIDX_OK;
 }

@@ -37,6 +37,7 @@ struct BuildArgs {
     uint32_t* rank;
     uint4* pts;
     uint32_t* status;
+    uint4* out;  // x order: where the ranking places the records (pts holds the counting sort's)
 };
 
 // Normalise one object and return its cell: region cells are packed ZYX
@@ -111,10 +112,10 @@ __global__ __launch_bounds__(256) void scatter_records_kernel(BuildArgs a) {
 }
 
 // Objects inside a cell in x order (then id), for cells of at most
-// kXSortCap objects: after the scatter, every object counts the objects of
-// its cell that come before it and keeps that rank by id; a second scatter
-// from the inputs then places it.  In a larger cell an object keeps its
-// place and the lattice's x-order word is cleared.  A block's 256 positions
+// kXSortCap objects: after the scatter (into a second record array), every
+// object counts the objects of its cell that come before it and is written
+// to the lattice's records at its cell's start plus that rank.  In a larger
+// cell an object keeps its place and the lattice's x-order word is cleared.  A block's 256 positions
 // cover a run of whole or partial cells; when the cells' objects number at
 // most kXStage they are staged in LDS as (x, id) keys and counted there,
 // else every thread reads its cell from device memory.
@@ -128,7 +129,7 @@ __global__ __launch_bounds__(256) void xrank_kernel(BuildArgs a) {
     const uint32_t last = min(a.n, p0 + blockDim.x) - 1u;
     const bool act = p < a.n;
     uint4 P = make_uint4(0, 0, 0, 0);
-    uint32_t lo = 0, hi = 0;
+    uint32_t lo = 0, hi = 0;  // the cell's positions (the last two cells: no x)
     if (act) {
         P = a.pts[p];
         uint32_t vx = P.x, vy = P.y, vz = P.z;
@@ -166,7 +167,7 @@ __global__ __launch_bounds__(256) void xrank_kernel(BuildArgs a) {
             r += (Q.x < P.x || (Q.x == P.x && Q.w < P.w)) ? 1u : 0u;
         }
     }
-    a.rank[P.w] = r;
+    a.out[lo + r] = P;
 }
 
 // Packed region cell of a sorted record (normalised, inside the region).
@@ -391,6 +392,7 @@ BuildArgs build_args(const sphidx_lattice* lat, const uint32_t* x, const uint32_
     a.rank = lat->rank;
     a.pts = lat->pts;
     a.status = lat->status;
+    a.out = nullptr;
     return a;
 }
 
@@ -423,9 +425,16 @@ hipError_t launch_build(const sphidx_lattice* lat, const uint32_t* x, const uint
     if (n > 0) hist_kernel<<<blocks, 256, 0, st>>>(a);
     e = scan_exclusive<uint32_t>(lat->cell_start, ncount, lat->scan_tmp, st);
     if (e != hipSuccess) return e;
-    if (n > 0) scatter_kernel<<<blocks, 256, 0, st>>>(a);
-    if (n > 0 && xo) {
-        xrank_kernel<<<blocks, 256, 0, st>>>(a);
+    if (xo && lat->xbuf) {
+        // the counting sort into the second array, then ranked into place
+        BuildArgs ax = a;
+        ax.pts = lat->xbuf;
+        ax.out = lat->pts;
+        if (n > 0) {
+            scatter_kernel<<<blocks, 256, 0, st>>>(ax);
+            xrank_kernel<<<blocks, 256, 0, st>>>(ax);
+        }
+    } else if (n > 0) {
         scatter_kernel<<<blocks, 256, 0, st>>>(a);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -22,6 +22,8 @@ struct sphidx_lattice {
     uint32_t* scan_tmp; // scan partial sums
     uint32_t* status;   // device status word; status[1]: 1 while every cell's objects are in x order
     uint32_t cell_order; // SPHIDX_ORDER_*: the order builds give the objects inside a cell
+    uint4* xbuf;         // ORDER_X: library-owned records (max_points x 16 B) the counting sort
+                         // fills before the x ranking places them; NULL until that order is set
     size_t bytes;
     int device;
     // attached non-empty cell list (caller-owned): count word, then entries
